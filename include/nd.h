@@ -1,0 +1,123 @@
+/*
+ * nd.h -- C ABI of the MI355X (gfx950) (r,s) nucleus decomposition library.
+ *
+ * The operation (Shi, Dhulipala, Shun, "Theoretically and Practically
+ * Efficient Parallel Nucleus Decomposition", Section 2, "(r,s) nucleus
+ * decomposition problem"): given a simple undirected graph G and 1 <= r < s,
+ * compute for every r-clique R of G its (r,s)-clique core number kappa(R),
+ * the largest c such that R belongs to a set X of r-cliques in which every
+ * member lies in at least c s-cliques whose r-subsets are all in X.  The
+ * library follows Algorithm 2 ("arb-nucleus-decomp"): orient G, count the
+ * s-cliques containing each r-clique (Count-Func), then peel the minimum
+ * bucket round by round, re-listing the s-cliques of every peeled r-clique
+ * and decrementing the other r-cliques in them (Update / Update-Func).
+ *
+ * Conventions of every entry point:
+ *   - All pointers named *_dev are DEVICE pointers on the current HIP device;
+ *     the caller owns them.  Host pointers are named *_host or are structs.
+ *   - Work is enqueued on the stream given at plan creation and runs in
+ *     stream order; entry points that return sizes or statistics synchronise
+ *     that stream before returning.
+ *   - Every entry point returns nd_status; nothing throws across the ABI.
+ *     On error the outputs are unspecified, nd_last_error() holds a detail
+ *     string for the calling thread, and a plan stays destroyable.
+ *   - A plan is not thread-safe; separate plans are independent.
+ */
+#ifndef ND_H
+#define ND_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ND_OK = 0,
+  ND_EINVAL = 1,     /* bad argument: r < 1, s <= r, s > ND_MAX_S, null pointer, ... */
+  ND_EGRAPH = 2,     /* CSR is not simple/symmetric/sorted, or ids out of range */
+  ND_EKEYWIDTH = 3,  /* (r-1) * ceil(log2 n) > 63: an r-clique key does not fit 64 bits */
+  ND_EOVERFLOW = 4,  /* an s-clique count exceeds UINT32_MAX, or a size exceeds 2^32 slots */
+  ND_ENOMEM = 5,     /* device memory budget exceeded or allocation failed */
+  ND_EHIP = 6,       /* a HIP runtime call failed */
+  ND_ESTATE = 7      /* entry point called in the wrong order */
+} nd_status;
+
+#define ND_MAX_S 7
+
+/* Simple undirected graph in CSR form, DEVICE pointers, caller-owned.
+ * row_ptr[n+1] (int64, row_ptr[0] = 0, row_ptr[n] = nnz), col[nnz] (int32);
+ * each undirected edge appears in both rows; rows strictly ascending, no
+ * self-loops (paper Section 2, "Graph Storage": CSR). */
+typedef struct {
+  int32_t n;
+  int64_t nnz;
+  const int64_t *row_ptr;
+  const int32_t *col;
+} nd_csr;
+
+/* Options; zero-initialised = defaults. */
+typedef struct {
+  int32_t orient;        /* 0 = degree order (ties by id), 1 = exact core (degeneracy) order */
+  int32_t reserved0;
+  float load_factor;     /* r-clique table load factor in (0, 0.9]; 0 = 0.5 */
+  uint32_t reserved1;
+} nd_options;
+
+typedef struct {
+  uint64_t n_r;          /* r-cliques */
+  uint64_t n_s;          /* s-cliques */
+  uint64_t rounds;       /* peeling rounds rho (Section 3.2, peeling complexity) */
+  uint64_t k_advances;   /* times the level k moved to a new minimum bucket */
+  uint64_t decrements;   /* count decrements applied while peeling */
+  uint64_t discoveries;  /* (peeled r-clique, s-clique) pairs listed while peeling */
+  uint64_t table_slots;  /* capacity of the r-clique table */
+  uint32_t max_kappa;
+  uint32_t max_out_degree; /* of the orientation */
+  float ms[8];           /* phase times: 0 validate, 1 orient+relabel, 2 table,
+                            3 count, 4 bucket init, 5 peel loop, 6 emit, 7 total */
+} nd_stats;
+
+typedef struct nd_plan_s *nd_plan; /* opaque, library-owned */
+
+/* Validate the graph (a1), orient and relabel it (a2: Section 2
+ * "O(alpha)-Orientation", Section 4.4 "Graph Relabeling") and build the
+ * two-level r-clique table (a3: Sections 4.1-4.3, contiguous last-level
+ * tables, slot position = r-clique index).  hbm_budget_bytes = 0 means no
+ * budget.  On success *out owns device memory until nd_plan_destroy. */
+nd_status nd_plan_create(const nd_csr *g, int r, int s, const nd_options *opt,
+                         uint64_t hbm_budget_bytes, void *hip_stream, nd_plan *out);
+
+/* Number of r-cliques (rows of the output) and device bytes held by the plan. */
+nd_status nd_plan_sizes(nd_plan p, uint64_t *n_r, uint64_t *device_bytes);
+
+/* Count (Algorithm 2 Count-Func), bucket and peel (Algorithm 2 main loop,
+ * Update, Update-Func), then emit.  Outputs (DEVICE, caller-owned):
+ *   rcliques_dev[n_r * r]  int32: row i = the vertices (original ids,
+ *                          ascending) of r-clique i; rows in library order;
+ *   kappa_dev[n_r]         uint32: nucleus number of row i;
+ *   counts_dev[n_r]        uint32, may be NULL: initial s-clique count of row i.
+ * stats (host) may be NULL.  Every r-clique of G is a row, including those in
+ * no s-clique (kappa 0).  Can be called once per plan. */
+nd_status nd_run(nd_plan p, int32_t *rcliques_dev, uint32_t *kappa_dev, uint32_t *counts_dev,
+                 nd_stats *stats);
+
+/* Round sizes |A_t| and levels k_t of the last nd_run (host arrays of
+ * capacity cap); *rounds receives rho.  Either array may be NULL. */
+nd_status nd_round_trace(nd_plan p, uint64_t *sizes_host, uint32_t *levels_host, uint64_t cap,
+                         uint64_t *rounds);
+
+nd_status nd_plan_destroy(nd_plan p);
+
+/* Free the library's cached device blocks (its allocator keeps freed blocks
+ * for reuse by later plans). */
+nd_status nd_release_cached(void);
+
+const char *nd_status_str(nd_status st);
+const char *nd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ND_H */

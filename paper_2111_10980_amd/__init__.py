@@ -1,0 +1,218 @@
+"""MI355X (gfx950) (r,s) nucleus decomposition -- Python binding.
+
+A thin ctypes layer over the C ABI in ``include/nd.h``: the functions below
+carry the ABI's names and only marshal arguments (torch tensors give device
+pointers and the HIP stream).  Every step of the decomposition runs in the
+library's HIP kernels; there is no CPU fallback: the first call raises
+ImportError if the built library ``libnd.so`` is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnd.so")
+
+ND_MAX_S = 7
+STATUS = {0: "ND_OK", 1: "ND_EINVAL", 2: "ND_EGRAPH", 3: "ND_EKEYWIDTH", 4: "ND_EOVERFLOW",
+          5: "ND_ENOMEM", 6: "ND_EHIP", 7: "ND_ESTATE"}
+PHASES = ("validate", "orient", "table", "count", "bucket", "peel", "emit", "total")
+
+
+class NdError(RuntimeError):
+    def __init__(self, code: int, detail: str):
+        super().__init__(f"{STATUS.get(code, code)}: {detail}")
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+
+
+class nd_csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p)]
+
+
+class nd_options(ctypes.Structure):
+    _fields_ = [("orient", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("load_factor", ctypes.c_float), ("reserved1", ctypes.c_uint32)]
+
+
+class nd_stats(ctypes.Structure):
+    _fields_ = [("n_r", ctypes.c_uint64), ("n_s", ctypes.c_uint64), ("rounds", ctypes.c_uint64),
+                ("k_advances", ctypes.c_uint64), ("decrements", ctypes.c_uint64),
+                ("discoveries", ctypes.c_uint64), ("table_slots", ctypes.c_uint64),
+                ("max_kappa", ctypes.c_uint32), ("max_out_degree", ctypes.c_uint32),
+                ("ms", ctypes.c_float * 8)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is not built; run paper_2111_10980_amd.build.build() (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    lib.nd_plan_create.argtypes = [ctypes.POINTER(nd_csr), ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(nd_options), ctypes.c_uint64, P,
+                                   ctypes.POINTER(P)]
+    lib.nd_plan_sizes.argtypes = [P, ctypes.POINTER(ctypes.c_uint64),
+                                  ctypes.POINTER(ctypes.c_uint64)]
+    lib.nd_run.argtypes = [P, P, P, P, ctypes.POINTER(nd_stats)]
+    lib.nd_round_trace.argtypes = [P, P, P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
+    lib.nd_plan_destroy.argtypes = [P]
+    lib.nd_release_cached.argtypes = []
+    lib.nd_status_str.argtypes = [ctypes.c_int]
+    lib.nd_status_str.restype = ctypes.c_char_p
+    lib.nd_last_error.argtypes = []
+    lib.nd_last_error.restype = ctypes.c_char_p
+    for name in ("nd_plan_create", "nd_plan_sizes", "nd_run", "nd_round_trace",
+                 "nd_plan_destroy", "nd_release_cached"):
+        getattr(lib, name).restype = ctypes.c_int
+    return lib
+
+
+class _Lazy:
+    """Loads libnd.so on first use; raises ImportError if it is not built."""
+
+    _h = None
+
+    def __getattr__(self, name):
+        if _Lazy._h is None:
+            _Lazy._h = _load()
+        return getattr(_Lazy._h, name)
+
+
+_lib = _Lazy()
+
+
+def library():
+    """The loaded ctypes library (raises ImportError when it is not built)."""
+    if _Lazy._h is None:
+        _Lazy._h = _load()
+    return _Lazy._h
+
+EXPORTED = ("nd_plan_create", "nd_plan_sizes", "nd_run", "nd_round_trace", "nd_plan_destroy",
+            "nd_release_cached", "nd_status_str", "nd_last_error")
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise NdError(rc, _lib.nd_last_error().decode(errors="replace"))
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ------------------------------------------------------------------ raw ABI
+
+def nd_plan_create(row_ptr, col, r: int, s: int, orient: int = 0, load_factor: float = 0.0,
+                   hbm_budget_bytes: int = 0, stream=None):
+    """row_ptr (int64, n+1) and col (int32) are CUDA tensors; returns a plan handle."""
+    import torch
+    if row_ptr.dtype != torch.int64 or col.dtype != torch.int32:
+        raise TypeError("row_ptr must be int64 and col int32")
+    if not (row_ptr.is_cuda and (col.is_cuda or col.numel() == 0)):
+        raise TypeError("row_ptr and col must be device tensors")
+    row_ptr = row_ptr.contiguous()
+    col = col.contiguous()
+    g = nd_csr(int(row_ptr.numel() - 1), int(col.numel()), row_ptr.data_ptr(),
+               col.data_ptr() if col.numel() else None)
+    opt = nd_options(int(orient), 0, float(load_factor), 0)
+    h = ctypes.c_void_p()
+    _check(_lib.nd_plan_create(ctypes.byref(g), int(r), int(s), ctypes.byref(opt),
+                               int(hbm_budget_bytes), _stream_handle(stream), ctypes.byref(h)))
+    return h
+
+
+def nd_plan_sizes(plan):
+    n_r = ctypes.c_uint64()
+    nbytes = ctypes.c_uint64()
+    _check(_lib.nd_plan_sizes(plan, ctypes.byref(n_r), ctypes.byref(nbytes)))
+    return int(n_r.value), int(nbytes.value)
+
+
+def nd_run(plan, rcliques, kappa, counts=None) -> dict:
+    st = nd_stats()
+    _check(_lib.nd_run(plan, rcliques.data_ptr() if rcliques.numel() else None,
+                       kappa.data_ptr() if kappa.numel() else None,
+                       counts.data_ptr() if counts is not None and counts.numel() else None,
+                       ctypes.byref(st)))
+    return stats_dict(st)
+
+
+def nd_round_trace(plan):
+    import numpy as np
+    rounds = ctypes.c_uint64()
+    _check(_lib.nd_round_trace(plan, None, None, 0, ctypes.byref(rounds)))
+    n = int(rounds.value)
+    sizes = np.zeros(max(n, 1), dtype=np.uint64)
+    levels = np.zeros(max(n, 1), dtype=np.uint32)
+    _check(_lib.nd_round_trace(plan, sizes.ctypes.data_as(ctypes.c_void_p),
+                               levels.ctypes.data_as(ctypes.c_void_p), n, ctypes.byref(rounds)))
+    return sizes[:n], levels[:n]
+
+
+def nd_plan_destroy(plan):
+    _check(_lib.nd_plan_destroy(plan))
+
+
+def nd_release_cached():
+    _check(_lib.nd_release_cached())
+
+
+def nd_status_str(code: int) -> str:
+    return _lib.nd_status_str(int(code)).decode()
+
+
+def nd_last_error() -> str:
+    return _lib.nd_last_error().decode(errors="replace")
+
+
+def stats_dict(st: nd_stats) -> dict:
+    d = {name: int(getattr(st, name)) for name, _ in nd_stats._fields_ if name != "ms"}
+    d["ms"] = {ph: float(st.ms[i]) for i, ph in enumerate(PHASES)}
+    return d
+
+
+# --------------------------------------------------------------- convenience
+
+@dataclass
+class Decomposition:
+    r: int
+    s: int
+    rcliques: object          # torch.int32 [n_r, r] (device), original ids ascending per row
+    kappa: object             # torch.int32 view of uint32 [n_r] (device)
+    counts: object | None     # initial s-clique counts [n_r] (device) or None
+    stats: dict = field(default_factory=dict)
+    round_sizes: object = None
+    round_levels: object = None
+
+
+def decompose(row_ptr, col, r: int, s: int, with_counts: bool = False, orient: int = 0,
+              load_factor: float = 0.0, hbm_budget_bytes: int = 0, stream=None) -> Decomposition:
+    """Whole hot path on the current device: plan, run, round trace, destroy."""
+    import torch
+    plan = nd_plan_create(row_ptr, col, r, s, orient, load_factor, hbm_budget_bytes, stream)
+    try:
+        n_r, _ = nd_plan_sizes(plan)
+        dev = row_ptr.device
+        rcl = torch.empty((n_r, r), dtype=torch.int32, device=dev)
+        kap = torch.empty((n_r,), dtype=torch.int32, device=dev)
+        cnt = torch.empty((n_r,), dtype=torch.int32, device=dev) if with_counts else None
+        stats = nd_run(plan, rcl, kap, cnt)
+        sizes, levels = nd_round_trace(plan)
+    finally:
+        nd_plan_destroy(plan)
+    return Decomposition(r, s, rcl, kap, cnt, stats, sizes, levels)
+
+
+def to_device(g, device="cuda"):
+    """Host CSR (inputs.CSR) -> (row_ptr, col) device tensors."""
+    import torch
+    rp = torch.from_numpy(g.row_ptr).to(device=device, dtype=torch.int64)
+    col = torch.from_numpy(g.col).to(device=device, dtype=torch.int32)
+    return rp, col

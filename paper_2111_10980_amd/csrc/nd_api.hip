@@ -1,0 +1,482 @@
+// Host runtime and C ABI (include/nd.h).
+//
+// Memory: every device buffer comes from the device's stream-ordered memory
+// pool (hipMallocAsync / hipFreeAsync on the plan's stream) with the release
+// threshold raised, so buffers freed by one plan are reused by the next one
+// without returning to the driver.  nd_release_cached() trims the pool.
+//
+// The peel loop (Algorithm 2, "while finished < |T|") runs on the host and
+// enqueues, per round: stamp(A_t), peel(A_t) -> A_{t+1}, then reads back the
+// 4-byte size of A_{t+1}.  When A_{t+1} is empty the level advances to the
+// minimum live count (reduction + partition of the live list).
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/nd.h"
+#include "nd_host.h"
+
+namespace nd {
+
+namespace {
+
+thread_local hipStream_t g_stream = nullptr;
+thread_local std::string g_last_error;
+
+struct Failure {
+  nd_status st;
+};
+
+[[noreturn]] void fail(nd_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  throw Failure{st};
+}
+
+void hip_check(hipError_t e, const char *what) {
+  if (e != hipSuccess) {
+    if (e == hipErrorOutOfMemory) fail(ND_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+    fail(ND_EHIP, "%s: %s", what, hipGetErrorString(e));
+  }
+}
+
+std::once_flag g_pool_once;
+
+void configure_pool() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t thr = UINT64_MAX;
+    hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+}
+
+struct StreamScope {
+  hipStream_t prev;
+  explicit StreamScope(hipStream_t s) : prev(g_stream) {
+    std::call_once(g_pool_once, configure_pool);
+    g_stream = s;
+  }
+  ~StreamScope() { g_stream = prev; }
+};
+
+int64_t grid_for(int64_t n, int threads, int64_t cap = 65536) {
+  int64_t b = (n + threads - 1) / threads;
+  if (b < 1) b = 1;
+  return b < cap ? b : cap;
+}
+
+__global__ void k_caps(int32_t n, int r, float lf, const uint32_t *__restrict__ cnt,
+                       uint64_t *cap) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t c = cnt[v];
+    uint64_t k;
+    if (r == 1) k = 1;
+    else if (c == 0) k = 0;
+    else {
+      k = (uint64_t)((double)c / (double)lf + 0.999999);
+      if (k < c + 1) k = c + 1;  // at least one empty slot ends every probe chain
+    }
+    cap[v] = k;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sum_slot_counts(const Slot *__restrict__ s, uint64_t n,
+                                                         unsigned long long *out) {
+  uint64_t acc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    acc += s[i].cnt;
+  acc = wave_sum_u64(acc);
+  if (lane_id() == 0 && acc) atomicAdd(out, (unsigned long long)acc);
+}
+
+uint64_t binom_u64(int n, int k) {
+  uint64_t r = 1;
+  for (int i = 1; i <= k; i++) r = r * (uint64_t)(n - k + i) / (uint64_t)i;
+  return r;
+}
+
+int bits_for(uint64_t maxval) {
+  int b = 0;
+  while (b < 64 && (maxval >> b) != 0) b++;
+  return b;
+}
+
+struct Timer {
+  hipEvent_t ev[9];
+  bool ok = false;
+  Timer() {
+    ok = true;
+    for (auto &e : ev)
+      if (hipEventCreate(&e) != hipSuccess) ok = false;
+  }
+  ~Timer() {
+    for (auto &e : ev) hipEventDestroy(e);
+  }
+  void mark(int i, hipStream_t st) {
+    if (ok) hipEventRecord(ev[i], st);
+  }
+  float between(int a, int b) {
+    float ms = 0;
+    if (ok && hipEventElapsedTime(&ms, ev[a], ev[b]) == hipSuccess) return ms;
+    return 0;
+  }
+};
+
+template <class T>
+T read_dev(const T *p, hipStream_t st) {
+  T h;
+  hip_check(hipMemcpyAsync(&h, p, sizeof(T), hipMemcpyDeviceToHost, st), "read back");
+  hip_check(hipStreamSynchronize(st), "synchronize");
+  return h;
+}
+
+}  // namespace
+
+void *dev_alloc(size_t bytes) {
+  void *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMallocAsync(&p, bytes, g_stream);
+  if (e != hipSuccess || !p) {
+    hipGetLastError();
+    fail(ND_ENOMEM, "device allocation of %zu bytes failed", bytes);
+  }
+  return p;
+}
+
+void dev_free(void *p) {
+  if (p) hipFreeAsync(p, g_stream);
+}
+
+}  // namespace nd
+
+using namespace nd;
+
+struct nd_plan_s {
+  hipStream_t st = nullptr;
+  int r = 0, s = 0;
+  nd_options opt{};
+  uint64_t budget = 0;
+  OrientedGraph g;
+  DevBuf<uint64_t> seg;
+  DevBuf<Slot> slots;
+  DevBuf<int32_t> v1;
+  DevBuf<uint32_t> occ;
+  DevBuf<Counters> ctr;
+  uint64_t n_r = 0, n_slots = 0, held = 0;
+  int bits = 1;
+  bool ran = false;
+  std::vector<uint64_t> round_sizes;
+  std::vector<uint32_t> round_k;
+  uint64_t k_advances = 0;
+  float ms_create[3] = {0, 0, 0};
+  TableView table() const { return TableView{bits, seg.get(), slots.get(), v1.get()}; }
+};
+
+template <class F>
+static nd_status guarded(hipStream_t st, F &&f) {
+  StreamScope scope(st);
+  try {
+    f();
+    return ND_OK;
+  } catch (const Failure &e) {
+    return e.st;
+  } catch (const std::bad_alloc &) {
+    g_last_error = "host allocation failed";
+    return ND_ENOMEM;
+  } catch (...) {
+    g_last_error = "unexpected internal error";
+    return ND_EHIP;
+  }
+}
+
+extern "C" {
+
+const char *nd_status_str(nd_status st) {
+  switch (st) {
+    case ND_OK: return "ok";
+    case ND_EINVAL: return "invalid argument";
+    case ND_EGRAPH: return "malformed graph";
+    case ND_EKEYWIDTH: return "r-clique key does not fit 64 bits";
+    case ND_EOVERFLOW: return "count or size overflow";
+    case ND_ENOMEM: return "out of device memory or budget";
+    case ND_EHIP: return "HIP runtime error";
+    case ND_ESTATE: return "wrong call order";
+  }
+  return "unknown status";
+}
+
+const char *nd_last_error(void) { return g_last_error.c_str(); }
+
+nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
+                         uint64_t hbm_budget_bytes, void *hip_stream, nd_plan *out) {
+  if (!out) {
+    g_last_error = "out is null";
+    return ND_EINVAL;
+  }
+  *out = nullptr;
+  if (!gin) {
+    g_last_error = "graph is null";
+    return ND_EINVAL;
+  }
+  if (r < 1 || s <= r || s > ND_MAX_S) {
+    g_last_error = "need 1 <= r < s <= ND_MAX_S";
+    return ND_EINVAL;
+  }
+  if (gin->n < 0 || gin->nnz < 0 || (gin->n > 0 && !gin->row_ptr) ||
+      (gin->nnz > 0 && !gin->col)) {
+    g_last_error = "bad CSR header";
+    return ND_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  nd_plan p = new (std::nothrow) nd_plan_s();
+  if (!p) return ND_ENOMEM;
+  nd_status rc = guarded(st, [&] {
+    p->st = st;
+    p->r = r;
+    p->s = s;
+    if (opt) p->opt = *opt;
+    if (p->opt.load_factor <= 0.f) p->opt.load_factor = 0.5f;
+    if (p->opt.load_factor > 0.9f) fail(ND_EINVAL, "load_factor must be <= 0.9");
+    if (p->opt.orient != 0 && p->opt.orient != 1) fail(ND_EINVAL, "orient must be 0 or 1");
+    p->budget = hbm_budget_bytes;
+    const int32_t n = gin->n;
+    Timer tm;
+    tm.mark(0, st);
+    p->ctr.reset(1);
+    fill_u32((uint32_t *)p->ctr.get(), 0, sizeof(Counters) / 4, st);
+    if (validate_csr(n, gin->nnz, gin->row_ptr, gin->col, p->ctr.get(), st))
+      fail(ND_EGRAPH, "CSR is not a simple symmetric graph with sorted rows");
+    tm.mark(1, st);
+    int vb = bits_for(n > 1 ? (uint64_t)(n - 1) : 1);
+    p->bits = vb < 1 ? 1 : vb;
+    if ((r - 1) * p->bits > 63)
+      fail(ND_EKEYWIDTH, "(r-1)*ceil(log2 n) = %d exceeds 63", (r - 1) * p->bits);
+    uint64_t graph_bytes = (uint64_t)(n + 1) * 8 * 2 + (uint64_t)gin->nnz * 4 + (uint64_t)n * 4;
+    if (p->budget && graph_bytes > p->budget) fail(ND_ENOMEM, "graph exceeds the HBM budget");
+    orient_relabel(n, gin->nnz, gin->row_ptr, gin->col, p->opt.orient, &p->g, st);
+    tm.mark(2, st);
+    // r-clique table: count per first vertex, capacities, prefix sum
+    DevBuf<uint32_t> cnt(n > 0 ? (size_t)n : 1);
+    count_rcliques(p->g, r, cnt.get(), st);
+    p->seg.reset((size_t)n + 1);
+    fill_u64(p->seg.get() + n, 0, 1, st);
+    if (n > 0)
+      hipLaunchKernelGGL(k_caps, dim3((unsigned)grid_for(n, 256)), dim3(256), 0, st, n, r,
+                         p->opt.load_factor, cnt.get(), p->seg.get());
+    scan_exclusive_u64(p->seg.get(), p->seg.get(), (int64_t)n + 1, st);
+    fill_u64((uint64_t *)&p->ctr.get()->n_s, 0, 1, st);
+    sum_u32(cnt.get(), n, (uint64_t *)&p->ctr.get()->n_s, st);
+    p->n_slots = read_dev(p->seg.get() + n, st);
+    p->n_r = read_dev((uint64_t *)&p->ctr.get()->n_s, st);
+    if (p->n_slots >= (1ull << 32) - 1)
+      fail(ND_EOVERFLOW, "table needs %llu slots (limit 2^32-1)", (unsigned long long)p->n_slots);
+    uint64_t table_bytes = p->n_slots * (sizeof(Slot) + 4) + p->n_r * 4 * 5;
+    p->held = graph_bytes + table_bytes + (uint64_t)(n + 1) * 8;
+    if (p->budget && p->held > p->budget)
+      fail(ND_ENOMEM, "plan needs %llu bytes, budget %llu", (unsigned long long)p->held,
+           (unsigned long long)p->budget);
+    p->slots.reset(p->n_slots ? p->n_slots : 1);
+    p->v1.reset(p->n_slots ? p->n_slots : 1);
+    fill_slots(p->slots.get(), (int64_t)p->n_slots, st);
+    fill_u32(&p->ctr.get()->err, 0, 1, st);
+    insert_rcliques(p->g, r, p->table(), p->ctr.get(), st);
+    p->occ.reset(p->n_r ? p->n_r : 1);
+    occupied_list(p->slots.get(), p->n_slots, p->occ.get(), st);
+    uint32_t err = read_dev(&p->ctr.get()->err, st);
+    if (err) fail(ND_EHIP, "r-clique table build failed (flags %u)", err);
+    tm.mark(3, st);
+    hip_check(hipStreamSynchronize(st), "synchronize");
+    hip_check(hipGetLastError(), "kernel launch");
+    p->ms_create[0] = tm.between(0, 1);
+    p->ms_create[1] = tm.between(1, 2);
+    p->ms_create[2] = tm.between(2, 3);
+  });
+  if (rc != ND_OK) {
+    {
+      StreamScope scope(st);
+      delete p;
+    }
+    return rc;
+  }
+  *out = p;
+  return ND_OK;
+}
+
+nd_status nd_plan_sizes(nd_plan p, uint64_t *n_r, uint64_t *device_bytes) {
+  if (!p) {
+    g_last_error = "plan is null";
+    return ND_EINVAL;
+  }
+  if (n_r) *n_r = p->n_r;
+  if (device_bytes) *device_bytes = p->held;
+  return ND_OK;
+}
+
+nd_status nd_run(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *counts_dev,
+                 nd_stats *stats) {
+  if (!p) {
+    g_last_error = "plan is null";
+    return ND_EINVAL;
+  }
+  if (p->ran) {
+    g_last_error = "nd_run was already called on this plan";
+    return ND_ESTATE;
+  }
+  if (p->n_r && (!rcl_dev || !kappa_dev)) {
+    g_last_error = "output pointer is null";
+    return ND_EINVAL;
+  }
+  hipStream_t st = p->st;
+  return guarded(st, [&] {
+    p->ran = true;
+    const int r = p->r, s = p->s;
+    Counters *dc = p->ctr.get();
+    Timer tm;
+    tm.mark(0, st);
+    // ---- count (Count-Func)
+    fill_u32((uint32_t *)dc, 0, sizeof(Counters) / 4, st);
+    count_scliques(p->g, r, s, p->table(), dc, st);
+    DevBuf<uint64_t> total(1);
+    fill_u64(total.get(), 0, 1, st);
+    if (p->n_slots)
+      hipLaunchKernelGGL(k_sum_slot_counts, dim3((unsigned)grid_for(p->n_slots, 256 * 16, 4096)),
+                         dim3(256), 0, st, p->slots.get(), p->n_slots,
+                         (unsigned long long *)total.get());
+    Counters hc = read_dev(dc, st);
+    if (hc.err) fail(ND_EHIP, "s-clique count failed (flags %u)", hc.err);
+    const uint64_t n_s = hc.n_s;
+    const uint64_t sum = read_dev(total.get(), st);
+    if (sum != binom_u64(s, r) * n_s)
+      fail(ND_EOVERFLOW, "an s-clique count exceeds 32 bits");
+    if (counts_dev) gather_counts(p->occ.get(), p->n_r, p->slots.get(), counts_dev, st);
+    tm.mark(1, st);
+    // ---- bucket init + peel
+    DevBuf<uint32_t> F(p->n_r ? p->n_r : 1), Fn(p->n_r ? p->n_r : 1), L(p->n_r ? p->n_r : 1),
+        L2(p->n_r ? p->n_r : 1);
+    if (p->n_r)
+      hip_check(hipMemcpyAsync(L.get(), p->occ.get(), 4 * p->n_r, hipMemcpyDeviceToDevice, st),
+                "copy");
+    uint64_t nL = p->n_r, finished = 0;
+    uint32_t k = 0, t = 0, nF = 0;
+    p->round_sizes.clear();
+    p->round_k.clear();
+    p->k_advances = 0;
+    bool first = true;
+    while (finished < p->n_r) {
+      if (nF == 0) {
+        live_min(L.get(), (uint32_t)nL, p->slots.get(), dc, st);
+        uint32_t m = read_dev(&dc->live_min, st);
+        if (m == 0xFFFFFFFFu) fail(ND_EHIP, "no live r-clique left before the peel finished");
+        if (m > k) k = m;
+        live_partition(L.get(), (uint32_t)nL, p->slots.get(), k, F.get(), L2.get(), dc, st);
+        Counters h2 = read_dev(dc, st);
+        nF = h2.next_size;
+        nL = h2.live_size;
+        std::swap(L.p, L2.p);
+        p->k_advances++;
+        if (first) tm.mark(2, st);
+        first = false;
+        if (nF == 0) fail(ND_EHIP, "empty bucket after a level advance");
+      }
+      stamp_frontier(F.get(), nF, p->slots.get(), t, st);
+      fill_u32(&dc->next_size, 0, 1, st);
+      peel_round(p->g, r, s, p->table(), F.get(), nF, t, k, Fn.get(), dc, st);
+      p->round_sizes.push_back(nF);
+      p->round_k.push_back(k);
+      finished += nF;
+      nF = read_dev(&dc->next_size, st);
+      std::swap(F.p, Fn.p);
+      t++;
+    }
+    if (first) tm.mark(2, st);
+    tm.mark(3, st);
+    // ---- emit
+    DevBuf<uint32_t> kround(p->round_k.size() ? p->round_k.size() : 1);
+    if (!p->round_k.empty())
+      hip_check(hipMemcpyAsync(kround.get(), p->round_k.data(), 4 * p->round_k.size(),
+                               hipMemcpyHostToDevice, st),
+                "copy levels");
+    emit(r, p->occ.get(), p->n_r, p->table(), p->g.new2old.get(), kround.get(),
+         (uint32_t)p->round_k.size(), rcl_dev, kappa_dev, st);
+    tm.mark(4, st);
+    hc = read_dev(dc, st);
+    hip_check(hipGetLastError(), "kernel launch");
+    if (hc.err) fail(ND_EHIP, "peel failed (flags %u)", hc.err);
+    if (stats) {
+      memset(stats, 0, sizeof(*stats));
+      stats->n_r = p->n_r;
+      stats->n_s = n_s;
+      stats->rounds = p->round_sizes.size();
+      stats->k_advances = p->k_advances;
+      stats->decrements = hc.decrements;
+      stats->discoveries = hc.discoveries;
+      stats->table_slots = p->n_slots;
+      stats->max_kappa = p->round_k.empty() ? 0 : p->round_k.back();
+      stats->max_out_degree = p->g.max_out;
+      stats->ms[0] = p->ms_create[0];
+      stats->ms[1] = p->ms_create[1];
+      stats->ms[2] = p->ms_create[2];
+      stats->ms[3] = tm.between(0, 1);
+      stats->ms[4] = tm.between(1, 2);
+      stats->ms[5] = tm.between(2, 3);
+      stats->ms[6] = tm.between(3, 4);
+      stats->ms[7] = p->ms_create[0] + p->ms_create[1] + p->ms_create[2] + tm.between(0, 4);
+    }
+  });
+}
+
+nd_status nd_round_trace(nd_plan p, uint64_t *sizes_host, uint32_t *levels_host, uint64_t cap,
+                         uint64_t *rounds) {
+  if (!p) {
+    g_last_error = "plan is null";
+    return ND_EINVAL;
+  }
+  if (!p->ran) {
+    g_last_error = "nd_run has not been called";
+    return ND_ESTATE;
+  }
+  uint64_t n = p->round_sizes.size();
+  if (rounds) *rounds = n;
+  uint64_t m = n < cap ? n : cap;
+  for (uint64_t i = 0; i < m; i++) {
+    if (sizes_host) sizes_host[i] = p->round_sizes[i];
+    if (levels_host) levels_host[i] = p->round_k[i];
+  }
+  return ND_OK;
+}
+
+nd_status nd_plan_destroy(nd_plan p) {
+  if (!p) return ND_OK;
+  hipStream_t st = p->st;
+  StreamScope scope(st);
+  delete p;
+  hipStreamSynchronize(st);
+  return ND_OK;
+}
+
+nd_status nd_release_cached(void) {
+  return guarded(nullptr, [&] {
+    hip_check(hipDeviceSynchronize(), "synchronize");
+    int dev = 0;
+    hip_check(hipGetDevice(&dev), "get device");
+    hipMemPool_t pool;
+    hip_check(hipDeviceGetDefaultMemPool(&pool, dev), "get pool");
+    hip_check(hipMemPoolTrimTo(pool, 0), "trim pool");
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,103 @@
+// Host-side launch interfaces shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "nd_internal.h"
+
+namespace nd {
+
+// Device memory from the library's caching pool (never hipMalloc directly).
+void *dev_alloc(size_t bytes);
+void dev_free(void *p);
+
+// Scratch buffer that returns to the pool when it goes out of scope.
+template <class T>
+struct DevBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t count) { reset(count); }
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf &operator=(DevBuf &&o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p; n = o.n; o.p = nullptr; o.n = 0;
+    }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void reset(size_t count) {
+    release();
+    n = count;
+    p = count ? (T *)dev_alloc(count * sizeof(T)) : nullptr;
+  }
+  void release() {
+    if (p) dev_free(p);
+    p = nullptr;
+    n = 0;
+  }
+  T *get() const { return p; }
+};
+
+struct OutOfMemory {};
+
+// ---- primitives (nd_prims.hip)
+void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
+void fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st);
+void fill_slots(Slot *p, int64_t n, hipStream_t st);
+void iota_u32(uint32_t *p, int64_t n, hipStream_t st);
+// exclusive prefix sum, in place allowed; n elements
+void scan_exclusive_u64(const uint64_t *in, uint64_t *out, int64_t n, hipStream_t st);
+void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t st);
+// stable LSD radix sort of keys (low `bits` bits significant), optional values
+void radix_sort(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t st);
+// sum of a u32 array into *out (device u64, accumulated)
+void sum_u32(const uint32_t *p, int64_t n, uint64_t *out, hipStream_t st);
+uint32_t max_u32_host(const uint32_t *p, int64_t n, hipStream_t st);
+
+// ---- graph (nd_graph.hip)
+struct OrientedGraph {
+  int32_t n = 0;
+  int64_t nnz = 0;
+  DevBuf<int64_t> rp, up;
+  DevBuf<int32_t> col;
+  DevBuf<int32_t> new2old;  // rank -> original id
+  uint32_t max_out = 0;
+  GraphView view() const { return GraphView{n, rp.get(), col.get(), up.get()}; }
+};
+// returns 0 or kErrGraph
+uint32_t validate_csr(int32_t n, int64_t nnz, const int64_t *rp, const int32_t *col,
+                      Counters *dctr, hipStream_t st);
+void orient_relabel(int32_t n, int64_t nnz, const int64_t *rp, const int32_t *col, int mode,
+                    OrientedGraph *og, hipStream_t st);
+
+// ---- cliques (nd_clique.hip)
+// count the r-cliques rooted at each vertex (lowest rank), into cnt[n]
+void count_rcliques(const OrientedGraph &g, int r, uint32_t *cnt, hipStream_t st);
+void insert_rcliques(const OrientedGraph &g, int r, const TableView &T, Counters *dctr,
+                     hipStream_t st);
+void count_scliques(const OrientedGraph &g, int r, int s, const TableView &T, Counters *dctr,
+                    hipStream_t st);
+
+// ---- peel (nd_peel.hip)
+void stamp_frontier(const uint32_t *F, uint32_t nF, Slot *slots, uint32_t t, hipStream_t st);
+void peel_round(const OrientedGraph &g, int r, int s, const TableView &T, const uint32_t *F,
+                uint32_t nF, uint32_t t, uint32_t k, uint32_t *Fnext, Counters *dctr,
+                hipStream_t st);
+void live_min(const uint32_t *L, uint32_t nL, const Slot *slots, Counters *dctr,
+              hipStream_t st);
+void live_partition(const uint32_t *L, uint32_t nL, const Slot *slots, uint32_t k, uint32_t *F,
+                    uint32_t *Lout, Counters *dctr, hipStream_t st);
+void occupied_list(const Slot *slots, uint64_t n_slots, uint32_t *occ, hipStream_t st);
+void gather_counts(const uint32_t *occ, uint64_t n_r, const Slot *slots, uint32_t *out,
+                   hipStream_t st);
+void emit(int r, const uint32_t *occ, uint64_t n_r, const TableView &T, const int32_t *new2old,
+          const uint32_t *kround, uint32_t nrounds, int32_t *rcl_out, uint32_t *kappa_out,
+          hipStream_t st);
+
+}  // namespace nd

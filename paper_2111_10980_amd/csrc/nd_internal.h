@@ -1,0 +1,233 @@
+// Internal definitions shared by the library's HIP translation units.
+// Device layout (all in HBM, all indices 0-based):
+//   relabeled graph G'   rp[n+1] int64, col[2m] int32 (rows ascending),
+//                        up[n] int64 = first position in row v holding a
+//                        neighbour > v; the out-neighbours of v under the
+//                        orientation are col[up[v] .. rp[v+1]).
+//   r-clique table T     seg[n+1] uint64: the last-level table of first
+//                        vertex v occupies slots [seg[v], seg[v+1]);
+//                        slots[] 16-byte {key, cnt, stamp}; v1[] int32 per
+//                        slot.  The slot position is the r-clique's index.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nd {
+
+constexpr uint32_t kLive = 0xFFFFFFFFu;      // stamp of an unpeeled r-clique
+constexpr uint64_t kOcc = 1ull << 63;        // key bit marking an occupied slot
+constexpr int kWave = 64;
+constexpr int kMaxS = 7;
+constexpr int kMaxBitmapWords = 8;           // 8 x 64 = 512 out-neighbours per root
+
+struct alignas(16) Slot {
+  uint64_t key;    // kOcc | v2 | v3 << b | ... ; 0 = empty
+  uint32_t cnt;    // s-clique count, decremented while peeling
+  uint32_t stamp;  // round in which the r-clique was peeled, or kLive
+};
+static_assert(sizeof(Slot) == 16, "slot must be 16 bytes");
+
+struct GraphView {
+  int32_t n;
+  const int64_t *__restrict__ rp;
+  const int32_t *__restrict__ col;
+  const int64_t *__restrict__ up;
+};
+
+struct TableView {
+  int bits;                            // bits per vertex field of a key
+  const uint64_t *__restrict__ seg;    // n+1
+  Slot *__restrict__ slots;
+  int32_t *__restrict__ v1;            // first vertex of each occupied slot
+};
+
+// Device-side error flags (bit set in a device word, read by the host).
+enum : uint32_t { kErrGraph = 1u, kErrLookup = 2u, kErrOverflow = 4u, kErrTable = 8u };
+
+// ----------------------------------------------------------------- helpers
+
+// splitmix64 output mixer (Steele, Lea, Flood, "Fast splittable pseudorandom
+// number generators", OOPSLA 2014): a bijective 64-bit finaliser.
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+  x ^= x >> 30;
+  x *= 0xbf58476d1ce4e5b9ull;
+  x ^= x >> 27;
+  x *= 0x94d049bb133111ebull;
+  x ^= x >> 31;
+  return x;
+}
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint64_t lanes_below() {
+  return (1ull << lane_id()) - 1ull;
+}
+
+// true if x occurs in the sorted range a[lo, hi)
+__device__ __forceinline__ bool sorted_contains(const int32_t *__restrict__ a, int64_t lo,
+                                                int64_t hi, int32_t x) {
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    int32_t v = a[mid];
+    if (v == x) return true;
+    if (v < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return false;
+}
+
+// Edge test through the orientation: the lower-ranked endpoint's
+// out-neighbour list is short (bounded by the orientation's out-degree).
+__device__ __forceinline__ bool adjacent(const GraphView &g, int32_t x, int32_t y) {
+  int32_t a = x < y ? x : y;
+  int32_t b = x < y ? y : x;
+  if (a == b) return false;
+  return sorted_contains(g.col, g.up[a], g.rp[a + 1], b);
+}
+
+// Key of a sorted r-tuple: fields v[1..R-1], bits each, plus the occupied bit.
+template <int R>
+__device__ __forceinline__ uint64_t make_key(const int32_t *v, int bits) {
+  uint64_t k = kOcc;
+#pragma unroll
+  for (int i = 1; i < R; i++) k |= (uint64_t)(uint32_t)v[i] << (bits * (i - 1));
+  return k;
+}
+
+template <int R>
+__device__ __forceinline__ void decode_key(uint64_t key, int bits, int32_t *v) {
+  uint64_t mask = (bits >= 63) ? ~0ull : ((1ull << bits) - 1ull);
+#pragma unroll
+  for (int i = 1; i < R; i++) v[i] = (int32_t)((key >> (bits * (i - 1))) & mask);
+}
+
+__device__ __forceinline__ uint64_t home_slot(uint64_t key, uint64_t cap) {
+  // fastrange: maps the high 32 hash bits onto [0, cap) without a division
+  return ((mix64(key) >> 32) * cap) >> 32;
+}
+
+// Linear probe of the last-level table of vertex v1.  Returns the slot
+// index, or -1 when absent; *out receives the slot's contents.
+__device__ __forceinline__ int64_t table_find(const TableView &T, int32_t v1, uint64_t key,
+                                              Slot *out) {
+  uint64_t base = T.seg[v1];
+  uint64_t cap = T.seg[v1 + 1] - base;
+  if (cap == 0) return -1;
+  uint64_t i = home_slot(key, cap);
+  for (uint64_t probe = 0; probe < cap; probe++) {
+    Slot s = T.slots[base + i];
+    if (s.key == key) {
+      *out = s;
+      return (int64_t)(base + i);
+    }
+    if (s.key == 0) return -1;
+    if (++i == cap) i = 0;
+  }
+  return -1;
+}
+
+__device__ __forceinline__ int64_t table_insert(const TableView &T, int32_t v1, uint64_t key) {
+  uint64_t base = T.seg[v1];
+  uint64_t cap = T.seg[v1 + 1] - base;
+  if (cap == 0) return -1;
+  uint64_t i = home_slot(key, cap);
+  for (uint64_t probe = 0; probe < cap; probe++) {
+    unsigned long long *kp = (unsigned long long *)&T.slots[base + i].key;
+    unsigned long long prev = atomicCAS(kp, 0ull, (unsigned long long)key);
+    if (prev == 0ull || prev == key) {
+      T.v1[base + i] = v1;
+      return (int64_t)(base + i);
+    }
+    if (++i == cap) i = 0;
+  }
+  return -1;
+}
+
+// Wave-aggregated append: every active lane calls it; lanes with want=true
+// get consecutive positions in buf reserved with one atomic per wave.
+__device__ __forceinline__ void wave_append(bool want, uint32_t val, uint32_t *buf,
+                                            uint32_t *counter) {
+  uint64_t m = __ballot(want);
+  if (m == 0) return;
+  int leader = __ffsll((unsigned long long)m) - 1;
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+  base = __shfl(base, leader);
+  if (want) buf[base + (uint32_t)__popcll(m & lanes_below())] = val;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    uint32_t o = __shfl_xor(v, off);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
+// Inclusive prefix sum across the wave.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  int lane = lane_id();
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    uint32_t o = __shfl_up(v, off);
+    if (lane >= off) v += o;
+  }
+  return v;
+}
+
+// ---------------------------------------------------- r-subsets of s-sets
+
+constexpr int binom(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  int r = 1;
+  for (int i = 1; i <= k; i++) r = r * (n - k + i) / i;
+  return r;
+}
+
+// All R-subsets of {0..S-1}, lexicographic, as bit masks.
+template <int S, int R>
+struct Combos {
+  static constexpr int N = binom(S, R);
+  uint8_t mask[N > 0 ? N : 1];
+  uint8_t idx[N > 0 ? N : 1][R > 0 ? R : 1];
+  constexpr Combos() : mask{}, idx{} {
+    int c[R > 0 ? R : 1] = {};
+    for (int i = 0; i < R; i++) c[i] = i;
+    for (int q = 0; q < N; q++) {
+      uint8_t m = 0;
+      for (int i = 0; i < R; i++) {
+        idx[q][i] = (uint8_t)c[i];
+        m = (uint8_t)(m | (1u << c[i]));
+      }
+      mask[q] = m;
+      int i = R - 1;
+      while (i >= 0 && c[i] == S - R + i) i--;
+      if (i < 0) break;
+      c[i]++;
+      for (int j = i + 1; j < R; j++) c[j] = c[j - 1] + 1;
+    }
+  }
+};
+
+// ------------------------------------------------------- host-side launch
+
+struct Counters {
+  uint64_t n_s;          // s-cliques listed by the count phase
+  uint64_t decrements;
+  uint64_t discoveries;
+  uint32_t err;          // kErr* bits
+  uint32_t next_size;    // size of the next frontier
+  uint32_t live_min;     // minimum live count (k-advance)
+  uint32_t live_size;    // size of the compacted live list
+  uint32_t class_size[8];
+};
+
+}  // namespace nd

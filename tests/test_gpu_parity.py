@@ -1,0 +1,225 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Every comparison is exact (all arithmetic is integer): the r-clique table,
+initial counts, nucleus numbers, the number of rounds, every round's size
+and level, and the total number of decrements.  Rows are compared after a
+lexicographic sort (the library's row order is its table order).
+"""
+import sys
+from math import comb
+
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_2111_10980_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _nd():
+    import paper_2111_10980_amd as nd
+    return nd
+
+
+def _canon(rcl, *vals):
+    rcl = np.asarray(rcl)
+    if rcl.shape[0] == 0:
+        return (rcl,) + tuple(np.asarray(v) for v in vals)
+    order = np.lexsort(rcl.T[::-1])
+    return (rcl[order],) + tuple(np.asarray(v)[order] for v in vals)
+
+
+def run_gpu(g, r, s, **kw):
+    nd = _nd()
+    rp, col = nd.to_device(g)
+    d = nd.decompose(rp, col, r, s, with_counts=True, **kw)
+    rcl = d.rcliques.cpu().numpy()
+    kap = d.kappa.cpu().numpy().view(np.uint32)
+    cnt = d.counts.cpu().numpy().view(np.uint32)
+    return rcl, kap, cnt, d
+
+
+def check_against_oracle(g, r, s, **kw):
+    print(f"[parity] n={g.n} m={g.m} r={r} s={s} {kw}", flush=True)
+    rcl, kap, cnt, d = run_gpu(g, r, s, **kw)
+    ref = oracle.decompose(g.n, g.row_ptr, g.col, r, s)
+    grc, gk, gc = _canon(rcl, kap, cnt)
+    assert grc.shape == ref.rcliques.shape
+    np.testing.assert_array_equal(grc, ref.rcliques)
+    np.testing.assert_array_equal(gc.astype(np.uint64), ref.counts)
+    np.testing.assert_array_equal(gk.astype(np.uint64), ref.kappa)
+    assert d.stats["n_s"] == ref.n_s
+    assert d.stats["n_r"] == ref.n_r
+    assert d.stats["rounds"] == ref.rounds
+    np.testing.assert_array_equal(d.round_sizes, ref.round_sizes)
+    np.testing.assert_array_equal(d.round_levels.astype(np.uint64), ref.round_k)
+    assert d.stats["decrements"] == ref.decrements
+    return d
+
+
+RS_ALL = [(1, 2), (1, 3), (2, 3), (2, 4), (3, 4), (3, 5), (4, 5), (2, 5), (1, 4), (4, 6),
+          (5, 6), (3, 6), (2, 6), (1, 5), (5, 7), (6, 7), (1, 6), (2, 7)]
+
+
+@pytest.mark.parametrize("r,s", [(3, 4), (2, 3), (1, 2), (4, 5), (2, 4), (1, 3)])
+def test_worked_example(r, s):
+    check_against_oracle(inputs.worked_example(), r, s)
+
+
+@pytest.mark.parametrize("r,s", RS_ALL)
+def test_planted_small_all_rs(r, s):
+    g = inputs.planted_er(120, 6.0, 3, 6, 11, 31)
+    check_against_oracle(g, r, s)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+@pytest.mark.parametrize("r,s", [(2, 3), (3, 4), (2, 4), (1, 2)])
+def test_er_medium(seed, r, s):
+    g = inputs.erdos_renyi(1500, 15000 if s - r == 1 else 9000, seed)
+    check_against_oracle(g, r, s)
+
+
+def test_er_2000_23_full_workload():
+    """The (2,3) workload at its full size: G(n=2,000, m=10,000)."""
+    for seed in (1, 2, 3, 4, 5):
+        check_against_oracle(inputs.er_2000(seed), 2, 3)
+
+
+@pytest.mark.parametrize("r,s", [(3, 4), (2, 3), (2, 4), (1, 2), (4, 5), (1, 3)])
+def test_rmat_small(r, s):
+    g = inputs.rmat(10, 8, 123)
+    check_against_oracle(g, r, s)
+
+
+@pytest.mark.parametrize("r,s", [(3, 4), (4, 5), (2, 4)])
+def test_chung_lu_small(r, s):
+    g = inputs.chung_lu_planted(3000, 8.0, 2.1, 4, 8, 16, 77)
+    check_against_oracle(g, r, s)
+
+
+@pytest.mark.parametrize("r,s", [(2, 3), (3, 4)])
+def test_core_order_orientation(r, s):
+    g = inputs.rmat(10, 8, 9)
+    check_against_oracle(g, r, s, orient=1)
+
+
+@pytest.mark.parametrize("lf", [0.25, 0.9])
+def test_load_factors(lf):
+    g = inputs.planted_er(200, 8.0, 2, 8, 14, 5)
+    check_against_oracle(g, 3, 4, load_factor=lf)
+
+
+@pytest.mark.parametrize("n,r,s", [(8, 3, 4), (40, 2, 3), (70, 1, 3), (65, 2, 4), (129, 1, 2),
+                                   (260, 1, 2), (300, 2, 3), (520, 1, 2), (600, 1, 3),
+                                   (530, 2, 3)])
+def test_complete_graph_closed_form(n, r, s):
+    """K_n: every r-clique in C(n-r, s-r) s-cliques, all peeled in one round.
+    n > 513 sends roots through the heavy-root kernel."""
+    print(f"[parity] K_{n} r={r} s={s}", flush=True)
+    rcl, kap, cnt, d = run_gpu(inputs.complete_graph(n), r, s)
+    assert rcl.shape[0] == comb(n, r)
+    assert (cnt == comb(n - r, s - r)).all()
+    assert (kap == comb(n - r, s - r)).all()
+    assert d.stats["n_s"] == comb(n, s)
+    assert d.stats["rounds"] == 1
+
+
+def test_disjoint_cliques():
+    sizes = [3, 5, 9, 17, 33, 65, 70]
+    g = inputs.disjoint_union([inputs.complete_graph(k) for k in sizes])
+    check_against_oracle(g, 2, 3)
+    check_against_oracle(g, 3, 4)
+
+
+def test_empty_and_isolated():
+    nd = _nd()
+    g = inputs.csr_from_edges(10, [], [])
+    rcl, kap, cnt, d = run_gpu(g, 1, 2)
+    assert rcl.shape == (10, 1) and (kap == 0).all() and d.stats["rounds"] == 1
+    rcl, kap, cnt, d = run_gpu(g, 2, 3)
+    assert rcl.shape == (0, 2) and d.stats["rounds"] == 0
+    # a single edge plus isolated vertices
+    g = inputs.csr_from_edges(6, [1], [4])
+    check_against_oracle(g, 1, 2)
+    check_against_oracle(g, 2, 3)
+
+
+def test_determinism():
+    g = inputs.rmat(11, 8, 4)
+    a = run_gpu(g, 3, 4)
+    b = run_gpu(g, 3, 4)
+    ca, cb = _canon(a[0], a[1], a[2]), _canon(b[0], b[1], b[2])
+    for x, y in zip(ca, cb):
+        np.testing.assert_array_equal(x, y)
+
+
+# ------------------------------------------------------------------ errors
+
+def _raw(n, rows):
+    import torch
+    rp = np.zeros(n + 1, dtype=np.int64)
+    rp[1:] = np.cumsum([len(x) for x in rows])
+    col = np.array([c for x in rows for c in x] or [0], dtype=np.int32)[: rp[-1]]
+    return torch.from_numpy(rp).cuda(), torch.from_numpy(col.copy()).cuda()
+
+
+@pytest.mark.parametrize("rows", [[[1, 1], [0]], [[0], []], [[1], []], [[2, 1], [0], [0]],
+                                  [[5], []], [[-1], []]])
+def test_malformed_graph_rejected(rows):
+    nd = _nd()
+    rp, col = _raw(len(rows), rows)
+    with pytest.raises(nd.NdError) as e:
+        nd.decompose(rp, col, 2, 3)
+    assert e.value.name == "ND_EGRAPH"
+
+
+def test_bad_arguments():
+    nd = _nd()
+    rp, col = nd.to_device(inputs.complete_graph(5))
+    for r, s in [(0, 2), (2, 2), (3, 1), (1, 8)]:
+        with pytest.raises(nd.NdError) as e:
+            nd.decompose(rp, col, r, s)
+        assert e.value.name == "ND_EINVAL"
+    with pytest.raises(nd.NdError) as e:
+        nd.decompose(rp, col, 2, 3, load_factor=0.95)
+    assert e.value.name == "ND_EINVAL"
+
+
+def test_key_width_rejected():
+    nd = _nd()
+    g = inputs.csr_from_edges((1 << 21) + 2, [0, 1], [1, 2])
+    rp, col = nd.to_device(g)
+    with pytest.raises(nd.NdError) as e:
+        nd.decompose(rp, col, 4, 5)
+    assert e.value.name == "ND_EKEYWIDTH"
+
+
+def test_budget_rejected():
+    nd = _nd()
+    rp, col = nd.to_device(inputs.rmat(10, 8, 3))
+    with pytest.raises(nd.NdError) as e:
+        nd.decompose(rp, col, 3, 4, hbm_budget_bytes=4096)
+    assert e.value.name == "ND_ENOMEM"
+
+
+def test_plan_lifecycle():
+    nd = _nd()
+    import torch
+    rp, col = nd.to_device(inputs.worked_example())
+    plan = nd.nd_plan_create(rp, col, 3, 4)
+    n_r, nbytes = nd.nd_plan_sizes(plan)
+    assert n_r == 14 and nbytes > 0
+    with pytest.raises(nd.NdError) as e:
+        nd.nd_round_trace(plan)
+    assert e.value.name == "ND_ESTATE"
+    rcl = torch.empty((n_r, 3), dtype=torch.int32, device="cuda")
+    kap = torch.empty((n_r,), dtype=torch.int32, device="cuda")
+    nd.nd_run(plan, rcl, kap)
+    with pytest.raises(nd.NdError) as e:
+        nd.nd_run(plan, rcl, kap)
+    assert e.value.name == "ND_ESTATE"
+    sizes, levels = nd.nd_round_trace(plan)
+    assert sizes.tolist() == [1, 3, 10] and levels.tolist() == [0, 1, 2]
+    nd.nd_plan_destroy(plan)
+    nd.nd_release_cached()
