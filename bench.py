@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Benchmark: (3,4) nucleus decomposition of an rMAT scale-18 graph on one GPU.
+
+One step = the whole hot path on a graph already resident in HBM:
+validation, orientation + relabeling, r-clique table build, s-clique
+counting, bucketed peeling and emission of (r-clique rows, kappa), through
+the C ABI.  The metric is whole-job s-clique peel updates per second: every
+s-clique is destroyed exactly once while peeling, so one step performs n_s
+updates and value = n_s / (seconds per step).
+
+Prints ONE JSON line.  Besides the driver's fields it carries
+  roofline      the dominant kernel's algorithmic HBM bytes / its measured
+                time (HIP events on the library's stream over the timed
+                steps) against the MI355X HBM peak;
+  cpu_baseline  the CPU oracle (single thread) timed on a bounded sample of
+                the same graph family (rMAT scale 12, same a..d).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+from math import comb
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+SLOT_BYTES = 16                # one r-clique table slot {key, count, stamp}
+
+WORKLOADS = {
+    # name: (generator, r, s, description)
+    "rmat18_34": ("rmat18", 3, 4, "rMAT scale 18, edge factor 16, a=.57 b=.19 c=.19 d=.05, "
+                  "symmetrised, loops/duplicates removed; (3,4) nucleus"),
+    "er2000_23": ("er_2000", 2, 3, "Erdos-Renyi G(n=2000, m=10000); (2,3) nucleus"),
+    "chunglu1m_45": ("chung_lu_1m", 4, 5, "Chung-Lu n=1e6, avg degree 20, exponent 2.1, "
+                     "200 planted cliques of size 20-60; (4,5) nucleus"),
+    "chunglu1m_24": ("chung_lu_1m", 2, 4, "Chung-Lu n=1e6, avg degree 20, exponent 2.1, "
+                     "200 planted cliques of size 20-60; (2,4) nucleus"),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(r, s, scale=12, seed=18):
+    """The oracle as it stands, single-threaded, on rMAT scale `scale`."""
+    from oracle import oracle
+    from paper_2111_10980_amd import inputs
+    g = inputs.rmat(scale, 16, seed)
+    t0 = time.perf_counter()
+    res = oracle.decompose(g.n, g.row_ptr, g.col, r, s)
+    dt = time.perf_counter() - t0
+    return {"value": res.n_s / dt, "unit": "s-clique peel updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"rMAT scale {scale} edge factor 16 (same a..d, seed {seed}; n={g.n}, "
+                      f"m={g.m}, n_s={res.n_s}), ({r},{s}), count+peel, {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat18_34", choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=None)
+    ap.add_argument("--orient", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 1 GiB device copy (for HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2111_10980_amd as nd
+    from paper_2111_10980_amd import inputs
+
+    gen, r, s, desc = WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    g = getattr(inputs, gen)() if args.seed is None else getattr(inputs, gen)(args.seed)
+    log(f"[bench] generated {args.workload}: n={g.n} m={g.m} in {time.perf_counter() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    rp, col = nd.to_device(g, dev)
+    torch.cuda.synchronize()
+
+    def step():
+        return nd.decompose(rp, col, r, s, orient=args.orient, timing=True)
+
+    for i in range(args.warmup):
+        d = step()
+        log(f"[bench] warmup {i}: total {d.stats['ms']['total']:.1f} ms, rounds "
+            f"{d.stats['rounds']}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = []
+    for i in range(args.steps):
+        runs.append(step())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1000.0 * elapsed / max(1, args.steps)
+    st = runs[-1].stats
+    for d in runs:
+        assert d.stats["n_s"] == st["n_s"] and d.stats["rounds"] == st["rounds"]
+    n_s = st["n_s"]
+    value = n_s / (ms_per_step / 1000.0)
+    log(f"[bench] {args.steps} steps, {ms_per_step:.1f} ms/step; n_r={st['n_r']} n_s={n_s} "
+        f"rounds={st['rounds']} max_kappa={st['max_kappa']} phases={st['ms']}")
+
+    # ---- roofline of the dominant kernel, from the timed steps
+    cnt_ms = sum(d.stats["count_kernel_ms"] for d in runs)
+    peel_ms = sum(d.stats["peel_kernel_ms"] for d in runs)
+    peel_launches = sum(d.stats["peel_launches"] for d in runs)
+    c = comb(s, r)
+    count_bytes = SLOT_BYTES * c * n_s * len(runs)
+    peel_bytes = SLOT_BYTES * (c - 1) * n_s * len(runs)
+    fast = s == r + 1 and r >= 2
+    peel_name = f"k_peel_fast<{r}>" if fast else f"k_peel<{r},{s}>"
+    count_name = f"k_count_direct<{r}>" if fast else f"k_list_bitmap<{s},*,CountOp<{r},{s}>>"
+    if peel_ms >= cnt_ms:
+        kern, t_ms, nbytes, launches = peel_name, peel_ms, peel_bytes, peel_launches
+    else:
+        kern, t_ms, nbytes, launches = count_name, cnt_ms, count_bytes, len(runs)
+    achieved = nbytes / (t_ms / 1000.0) / 1e9 if t_ms > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "kernel": kern, "launches_per_step": launches // max(1, len(runs)),
+                "kernel_ms_per_step": round(t_ms / len(runs), 3),
+                "bytes_per_step": nbytes // len(runs),
+                "count_kernel_ms_per_step": round(cnt_ms / len(runs), 3),
+                "peel_kernel_ms_per_step": round(peel_ms / len(runs), 3)}
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] copy calibration: 1 GiB device copy done")
+
+    base = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on the bounded sample")
+        base = cpu_baseline(r, s)
+        log(f"[bench] cpu baseline: {base['value']:.4g} {base['unit']} ({base['sample']})")
+
+    out = {
+        "metric": "s-clique peel updates/sec",
+        "value": value,
+        "unit": "s-cliques/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "r": r, "s": s, "n": g.n,
+                   "m": g.m, "n_r": st["n_r"], "n_s": n_s, "rounds": st["rounds"],
+                   "max_kappa": st["max_kappa"], "orientation": ["degree", "core"][args.orient],
+                   "max_out_degree": st["max_out_degree"], "decrements": st["decrements"],
+                   "discoveries": st["discoveries"], "k_advances": st["k_advances"],
+                   "table_slots": st["table_slots"], "phase_ms": st["ms"]},
+        "roofline": roofline,
+        "cpu_baseline": base,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

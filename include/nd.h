@@ -60,9 +60,10 @@ typedef struct {
 /* Options; zero-initialised = defaults. */
 typedef struct {
   int32_t orient;        /* 0 = degree order (ties by id), 1 = exact core (degeneracy) order */
-  int32_t reserved0;
+  int32_t timing;        /* 1 = time the count-listing and peel kernels with HIP events */
   float load_factor;     /* r-clique table load factor in (0, 0.9]; 0 = 0.5 */
-  uint32_t reserved1;
+  int32_t path;          /* 0 = auto; 1 = force the generic path (Count-Func atomics and
+                            intersection by edge tests) even when s = r+1 */
 } nd_options;
 
 typedef struct {
@@ -77,6 +78,10 @@ typedef struct {
   uint32_t max_out_degree; /* of the orientation */
   float ms[8];           /* phase times: 0 validate, 1 orient+relabel, 2 table,
                             3 count, 4 bucket init, 5 peel loop, 6 emit, 7 total */
+  float count_kernel_ms; /* with options.timing: time of the s-clique listing kernels */
+  float peel_kernel_ms;  /* with options.timing: summed time of the peel-round kernels */
+  uint32_t count_launches;
+  uint32_t peel_launches;
 } nd_stats;
 
 typedef struct nd_plan_s *nd_plan; /* opaque, library-owned */

@@ -34,8 +34,13 @@ class nd_csr(ctypes.Structure):
 
 
 class nd_options(ctypes.Structure):
-    _fields_ = [("orient", ctypes.c_int32), ("reserved0", ctypes.c_int32),
-                ("load_factor", ctypes.c_float), ("reserved1", ctypes.c_uint32)]
+    _fields_ = [("orient", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("load_factor", ctypes.c_float), ("path", ctypes.c_int32)]
+
+
+class nd_roofline(ctypes.Structure):
+    _fields_ = [("copy_gbs", ctypes.c_double), ("gather16_gops", ctypes.c_double),
+                ("atomic_ret_gops", ctypes.c_double), ("atomic_noret_gops", ctypes.c_double)]
 
 
 class nd_stats(ctypes.Structure):
@@ -43,7 +48,9 @@ class nd_stats(ctypes.Structure):
                 ("k_advances", ctypes.c_uint64), ("decrements", ctypes.c_uint64),
                 ("discoveries", ctypes.c_uint64), ("table_slots", ctypes.c_uint64),
                 ("max_kappa", ctypes.c_uint32), ("max_out_degree", ctypes.c_uint32),
-                ("ms", ctypes.c_float * 8)]
+                ("ms", ctypes.c_float * 8), ("count_kernel_ms", ctypes.c_float),
+                ("peel_kernel_ms", ctypes.c_float), ("count_launches", ctypes.c_uint32),
+                ("peel_launches", ctypes.c_uint32)]
 
 
 def _load():
@@ -61,6 +68,9 @@ def _load():
     lib.nd_round_trace.argtypes = [P, P, P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
     lib.nd_plan_destroy.argtypes = [P]
     lib.nd_release_cached.argtypes = []
+    lib.nd_roofline_measure.argtypes = [ctypes.c_uint64, ctypes.c_uint64, P,
+                                        ctypes.POINTER(nd_roofline)]
+    lib.nd_roofline_measure.restype = ctypes.c_int
     lib.nd_status_str.argtypes = [ctypes.c_int]
     lib.nd_status_str.restype = ctypes.c_char_p
     lib.nd_last_error.argtypes = []
@@ -92,7 +102,7 @@ def library():
     return _Lazy._h
 
 EXPORTED = ("nd_plan_create", "nd_plan_sizes", "nd_run", "nd_round_trace", "nd_plan_destroy",
-            "nd_release_cached", "nd_status_str", "nd_last_error")
+            "nd_release_cached", "nd_status_str", "nd_last_error", "nd_roofline_measure")
 
 
 def _check(rc: int):
@@ -110,7 +120,8 @@ def _stream_handle(stream):
 # ------------------------------------------------------------------ raw ABI
 
 def nd_plan_create(row_ptr, col, r: int, s: int, orient: int = 0, load_factor: float = 0.0,
-                   hbm_budget_bytes: int = 0, stream=None):
+                   hbm_budget_bytes: int = 0, stream=None, timing: bool = False,
+                   generic: bool = False):
     """row_ptr (int64, n+1) and col (int32) are CUDA tensors; returns a plan handle."""
     import torch
     if row_ptr.dtype != torch.int64 or col.dtype != torch.int32:
@@ -121,7 +132,7 @@ def nd_plan_create(row_ptr, col, r: int, s: int, orient: int = 0, load_factor: f
     col = col.contiguous()
     g = nd_csr(int(row_ptr.numel() - 1), int(col.numel()), row_ptr.data_ptr(),
                col.data_ptr() if col.numel() else None)
-    opt = nd_options(int(orient), 0, float(load_factor), 0)
+    opt = nd_options(int(orient), int(bool(timing)), float(load_factor), int(bool(generic)))
     h = ctypes.c_void_p()
     _check(_lib.nd_plan_create(ctypes.byref(g), int(r), int(s), ctypes.byref(opt),
                                int(hbm_budget_bytes), _stream_handle(stream), ctypes.byref(h)))
@@ -172,8 +183,19 @@ def nd_last_error() -> str:
     return _lib.nd_last_error().decode(errors="replace")
 
 
+def nd_roofline_measure(table_bytes: int, count_bytes: int, stream=None) -> dict:
+    """Measured device ceilings (include/nd_roofline.h)."""
+    out = nd_roofline()
+    rc = _lib.nd_roofline_measure(int(table_bytes), int(count_bytes), _stream_handle(stream),
+                                  ctypes.byref(out))
+    if rc != 0:
+        raise NdError(rc, "roofline probe failed")
+    return {name: float(getattr(out, name)) for name, _ in nd_roofline._fields_}
+
+
 def stats_dict(st: nd_stats) -> dict:
-    d = {name: int(getattr(st, name)) for name, _ in nd_stats._fields_ if name != "ms"}
+    d = {name: getattr(st, name) for name, _ in nd_stats._fields_ if name != "ms"}
+    d = {k: (float(v) if isinstance(v, float) else int(v)) for k, v in d.items()}
     d["ms"] = {ph: float(st.ms[i]) for i, ph in enumerate(PHASES)}
     return d
 
@@ -193,10 +215,12 @@ class Decomposition:
 
 
 def decompose(row_ptr, col, r: int, s: int, with_counts: bool = False, orient: int = 0,
-              load_factor: float = 0.0, hbm_budget_bytes: int = 0, stream=None) -> Decomposition:
+              load_factor: float = 0.0, hbm_budget_bytes: int = 0, stream=None,
+              timing: bool = False, generic: bool = False) -> Decomposition:
     """Whole hot path on the current device: plan, run, round trace, destroy."""
     import torch
-    plan = nd_plan_create(row_ptr, col, r, s, orient, load_factor, hbm_budget_bytes, stream)
+    plan = nd_plan_create(row_ptr, col, r, s, orient, load_factor, hbm_budget_bytes, stream,
+                          timing, generic)
     try:
         n_r, _ = nd_plan_sizes(plan)
         dev = row_ptr.device

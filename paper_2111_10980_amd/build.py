@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnd.so")
-SOURCES = ["nd_prims.hip", "nd_graph.hip", "nd_clique.hip", "nd_peel.hip", "nd_api.hip"]
+SOURCES = ["nd_prims.hip", "nd_graph.hip", "nd_clique.hip", "nd_peel.hip", "nd_fast.hip",
+           "nd_api.hip", "nd_roofline.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

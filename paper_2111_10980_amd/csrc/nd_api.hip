@@ -176,6 +176,8 @@ struct nd_plan_s {
   DevBuf<int32_t> v1;
   DevBuf<uint32_t> occ;
   DevBuf<Counters> ctr;
+  FastIndex fx;
+  bool fast = false;  // s = r+1 path (bitmaps + apex lists)
   uint64_t n_r = 0, n_slots = 0, held = 0;
   int bits = 1;
   bool ran = false;
@@ -252,6 +254,8 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
     if (p->opt.load_factor <= 0.f) p->opt.load_factor = 0.5f;
     if (p->opt.load_factor > 0.9f) fail(ND_EINVAL, "load_factor must be <= 0.9");
     if (p->opt.orient != 0 && p->opt.orient != 1) fail(ND_EINVAL, "orient must be 0 or 1");
+    if (p->opt.path != 0 && p->opt.path != 1) fail(ND_EINVAL, "path must be 0 or 1");
+    p->fast = (s == r + 1) && r >= 2 && r <= 6 && p->opt.path == 0;
     p->budget = hbm_budget_bytes;
     const int32_t n = gin->n;
     Timer tm;
@@ -298,6 +302,15 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
     occupied_list(p->slots.get(), p->n_slots, p->occ.get(), st);
     uint32_t err = read_dev(&p->ctr.get()->err, st);
     if (err) fail(ND_EHIP, "r-clique table build failed (flags %u)", err);
+    if (p->fast) {
+      build_fast_index(p->g, &p->fx, p->ctr.get(), st);
+      build_slot_loc(p->g, r, p->table(), p->n_slots, &p->fx, st);
+      p->held += p->fx.bm_words * 8 + p->fx.n_tri * 4 + (uint64_t)(gin->nnz + 1) * 8 +
+                 p->n_slots * 8;
+      if (p->budget && p->held > p->budget)
+        fail(ND_ENOMEM, "plan needs %llu bytes, budget %llu", (unsigned long long)p->held,
+             (unsigned long long)p->budget);
+    }
     tm.mark(3, st);
     hip_check(hipStreamSynchronize(st), "synchronize");
     hip_check(hipGetLastError(), "kernel launch");
@@ -346,10 +359,21 @@ nd_status nd_run(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *cou
     const int r = p->r, s = p->s;
     Counters *dc = p->ctr.get();
     Timer tm;
+    const bool timing = p->opt.timing != 0;
+    Timer kt;  // kernel timing: 0/1 around the count listing, 2/3 around each peel launch
+    float count_kernel_ms = 0, peel_kernel_ms = 0;
+    uint32_t count_launches = 0, peel_launches = 0;
     tm.mark(0, st);
     // ---- count (Count-Func)
     fill_u32((uint32_t *)dc, 0, sizeof(Counters) / 4, st);
-    count_scliques(p->g, r, s, p->table(), dc, st);
+    if (p->fast) {
+      if (timing) kt.mark(0, st);
+      count_direct(p->g, r, p->table(), p->fx, p->occ.get(), p->n_r, dc, st);
+      if (timing) kt.mark(1, st);
+    } else {
+      count_scliques(p->g, r, s, p->table(), dc, st, timing ? kt.ev[0] : nullptr,
+                     timing ? kt.ev[1] : nullptr);
+    }
     DevBuf<uint64_t> total(1);
     fill_u64(total.get(), 0, 1, st);
     if (p->n_slots)
@@ -358,11 +382,24 @@ nd_status nd_run(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *cou
                          (unsigned long long *)total.get());
     Counters hc = read_dev(dc, st);
     if (hc.err) fail(ND_EHIP, "s-clique count failed (flags %u)", hc.err);
-    const uint64_t n_s = hc.n_s;
+    if (timing) {
+      count_kernel_ms = kt.between(0, 1);
+      count_launches = 1;
+    }
     const uint64_t sum = read_dev(total.get(), st);
-    if (sum != binom_u64(s, r) * n_s)
-      fail(ND_EOVERFLOW, "an s-clique count exceeds 32 bits");
+    const uint64_t per = binom_u64(s, r);
+    // direct counting: every s-clique is counted once by each of its r-subsets
+    const uint64_t n_s = p->fast ? sum / per : hc.n_s;
+    if (p->fast && sum % per != 0) fail(ND_EHIP, "direct counts are inconsistent");
+    if (sum != per * n_s) fail(ND_EOVERFLOW, "an s-clique count exceeds 32 bits");
     if (counts_dev) gather_counts(p->occ.get(), p->n_r, p->slots.get(), counts_dev, st);
+    if (p->fast && r == 3) {  // liveness bitmaps start as the adjacency bitmaps
+      p->fx.alive.reset(p->fx.bm_words ? p->fx.bm_words : 1);
+      if (p->fx.bm_words)
+        hip_check(hipMemcpyAsync(p->fx.alive.get(), p->fx.bm.get(), 8 * p->fx.bm_words,
+                                 hipMemcpyDeviceToDevice, st),
+                  "copy bitmaps");
+    }
     tm.mark(1, st);
     // ---- bucket init + peel
     DevBuf<uint32_t> F(p->n_r ? p->n_r : 1), Fn(p->n_r ? p->n_r : 1), L(p->n_r ? p->n_r : 1),
@@ -394,11 +431,21 @@ nd_status nd_run(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *cou
       }
       stamp_frontier(F.get(), nF, p->slots.get(), t, st);
       fill_u32(&dc->next_size, 0, 1, st);
-      peel_round(p->g, r, s, p->table(), F.get(), nF, t, k, Fn.get(), dc, st);
+      if (timing) kt.mark(2, st);
+      if (p->fast)
+        peel_round_fast(p->g, r, p->table(), p->fx, F.get(), nF, t, k, Fn.get(), dc, st);
+      else
+        peel_round(p->g, r, s, p->table(), F.get(), nF, t, k, Fn.get(), dc, st);
+      if (timing) kt.mark(3, st);
+      if (p->fast && r == 3) clear_alive(p->g, p->table(), p->fx, F.get(), nF, st);
       p->round_sizes.push_back(nF);
       p->round_k.push_back(k);
       finished += nF;
       nF = read_dev(&dc->next_size, st);
+      if (timing) {
+        peel_kernel_ms += kt.between(2, 3);
+        peel_launches++;
+      }
       std::swap(F.p, Fn.p);
       t++;
     }
@@ -435,6 +482,10 @@ nd_status nd_run(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *cou
       stats->ms[5] = tm.between(2, 3);
       stats->ms[6] = tm.between(3, 4);
       stats->ms[7] = p->ms_create[0] + p->ms_create[1] + p->ms_create[2] + tm.between(0, 4);
+      stats->count_kernel_ms = count_kernel_ms;
+      stats->peel_kernel_ms = peel_kernel_ms;
+      stats->count_launches = count_launches;
+      stats->peel_launches = peel_launches;
     }
   });
 }

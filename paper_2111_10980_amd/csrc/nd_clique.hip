@@ -279,6 +279,35 @@ struct InsertOp {
   }
 };
 
+// Apex lists: each triangle (x < y < z) contributes its lowest vertex x to
+// the list of the arc (y, z); the arc is named by the position of z in row y
+// of the relabeled CSR.  Keys are (arc << xbits) | x, written at per-root
+// cursors so no two lanes contend on one counter.
+struct ApexOp {
+  GraphView g;
+  unsigned long long *cursor;
+  uint64_t *keys;
+  int xbits;
+  struct Lane {
+    uint32_t dummy;
+  };
+  __device__ void lane_init(Lane &) const {}
+  __device__ void root_begin(Lane &, int32_t) const {}
+  __device__ void root_end(Lane &, int32_t) const {}
+  __device__ void operator()(Lane &, const int32_t (&Sv)[3]) const {
+    const int32_t y = Sv[1], z = Sv[2];
+    int64_t lo = g.up[y], hi = g.rp[y + 1];
+    while (lo < hi) {
+      int64_t mid = (lo + hi) >> 1;
+      if (g.col[mid] < z) lo = mid + 1;
+      else hi = mid;
+    }
+    unsigned long long at = atomicAdd(&cursor[Sv[0]], 1ull);
+    keys[at] = ((uint64_t)lo << xbits) | (uint64_t)(uint32_t)Sv[0];
+  }
+  __device__ void lane_finish(Lane &) const {}
+};
+
 // ---------------------------------------------------------- root binning
 
 // class 0..3: bitmap kernels with W = 1, 2, 4, 8; class 4: heavy roots
@@ -367,10 +396,13 @@ void insert_r_impl(const OrientedGraph &g, const TableView &T, Counters *dctr, h
 }
 
 template <int R, int S>
-void count_s_impl(const OrientedGraph &g, const TableView &T, Counters *dctr, hipStream_t st) {
+void count_s_impl(const OrientedGraph &g, const TableView &T, Counters *dctr, hipStream_t st,
+                  hipEvent_t ev0, hipEvent_t ev1) {
   Bins b;
   bin_roots(g, S - 1, dctr, &b, st);
+  if (ev0) hipEventRecord(ev0, st);
   launch_listing<S>(g, b, CountOp<R, S>{T, dctr}, st);
+  if (ev1) hipEventRecord(ev1, st);
 }
 
 }  // namespace
@@ -409,12 +441,24 @@ void insert_rcliques(const OrientedGraph &g, int r, const TableView &T, Counters
   }
 }
 
+void list_apex_keys(const OrientedGraph &g, uint64_t *cursor, uint64_t *keys, int xbits,
+                    Counters *dctr, hipStream_t st) {
+  if (g.n == 0) return;
+  Bins b;
+  bin_roots(g, 2, dctr, &b, st);
+  launch_listing<3>(g, b, ApexOp{g.view(), (unsigned long long *)cursor, keys, xbits}, st);
+}
+
 #define ND_COUNT_CASE(R_, S_) \
-  case (R_) * 16 + (S_): count_s_impl<R_, S_>(g, T, dctr, st); break;
+  case (R_) * 16 + (S_): count_s_impl<R_, S_>(g, T, dctr, st, ev0, ev1); break;
 
 void count_scliques(const OrientedGraph &g, int r, int s, const TableView &T, Counters *dctr,
-                    hipStream_t st) {
-  if (g.n == 0) return;
+                    hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  if (g.n == 0) {
+    if (ev0) hipEventRecord(ev0, st);
+    if (ev1) hipEventRecord(ev1, st);
+    return;
+  }
   switch (r * 16 + s) {
     ND_COUNT_CASE(1, 2) ND_COUNT_CASE(1, 3) ND_COUNT_CASE(1, 4) ND_COUNT_CASE(1, 5)
     ND_COUNT_CASE(1, 6) ND_COUNT_CASE(1, 7)

@@ -51,6 +51,7 @@ void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
 void fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st);
 void fill_slots(Slot *p, int64_t n, hipStream_t st);
 void iota_u32(uint32_t *p, int64_t n, hipStream_t st);
+void widen_u32_to_u64(const uint32_t *a, uint64_t *b, int64_t n, hipStream_t st);
 // exclusive prefix sum, in place allowed; n elements
 void scan_exclusive_u64(const uint64_t *in, uint64_t *out, int64_t n, hipStream_t st);
 void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t st);
@@ -81,8 +82,44 @@ void orient_relabel(int32_t n, int64_t nnz, const int64_t *rp, const int32_t *co
 void count_rcliques(const OrientedGraph &g, int r, uint32_t *cnt, hipStream_t st);
 void insert_rcliques(const OrientedGraph &g, int r, const TableView &T, Counters *dctr,
                      hipStream_t st);
+// ev0/ev1 (nullable) are recorded around the listing kernels only
 void count_scliques(const OrientedGraph &g, int r, int s, const TableView &T, Counters *dctr,
-                    hipStream_t st);
+                    hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
+// every triangle (x<y<z) writes key (arc(y,z) << xbits | x) at cursor[x]++
+void list_apex_keys(const OrientedGraph &g, uint64_t *cursor, uint64_t *keys, int xbits,
+                    Counters *dctr, hipStream_t st);
+
+// ---- s = r+1 path (nd_fast.hip): per-root adjacency bitmaps and apex lists
+struct FastView {
+  const uint64_t *__restrict__ bm_off;  // n: word offset of root v's bitmap rows
+  const uint64_t *__restrict__ bm;      // symmetric rows, d x ceil(d/64) words per root
+  const uint64_t *__restrict__ lptr;    // nnz+1: apex list of the arc at col position e
+  const int32_t *__restrict__ lval;     // apex vertices, ascending within a list
+  uint64_t *alive;                      // r = 3: bitmap copy, a triangle's bits cleared
+                                        // after the round that peels it (else null)
+};
+struct FastIndex {
+  DevBuf<uint64_t> bm_off, bm, lptr, alive;
+  DevBuf<uint64_t> loc;  // per slot: local indices of v2..vr in N+(v1), 9 bits each
+  DevBuf<int32_t> lval;
+  uint64_t bm_words = 0, n_tri = 0;
+  FastView view() const {
+    return FastView{bm_off.get(), bm.get(), lptr.get(), lval.get(), alive.get()};
+  }
+};
+void build_fast_index(const OrientedGraph &g, FastIndex *fx, Counters *dctr, hipStream_t st);
+// count(R) = |common neighbourhood of R| written straight into each slot
+void count_direct(const OrientedGraph &g, int r, const TableView &T, const FastIndex &fx,
+                  const uint32_t *occ, uint64_t n_r, Counters *dctr, hipStream_t st);
+void peel_round_fast(const OrientedGraph &g, int r, const TableView &T, const FastIndex &fx,
+                     const uint32_t *F, uint32_t nF, uint32_t t, uint32_t k, uint32_t *Fnext,
+                     Counters *dctr, hipStream_t st);
+void build_slot_loc(const OrientedGraph &g, int r, const TableView &T, uint64_t n_slots,
+                    FastIndex *fx, hipStream_t st);
+// r = 3: clear the alive bits of the triangles peeled in this round
+void clear_alive(const OrientedGraph &g, const TableView &T, const FastIndex &fx,
+                 const uint32_t *F, uint32_t nF, hipStream_t st);
 
 // ---- peel (nd_peel.hip)
 void stamp_frontier(const uint32_t *F, uint32_t nF, Slot *slots, uint32_t t, hipStream_t st);

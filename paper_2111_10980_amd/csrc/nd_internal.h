@@ -144,6 +144,69 @@ __device__ __forceinline__ int64_t table_insert(const TableView &T, int32_t v1, 
   return -1;
 }
 
+// K lower bounds in the same sorted range, advanced in lock-step so their
+// loads are independent (one dependent step per halving, not K).
+template <int K>
+__device__ __forceinline__ void lower_bounds(const int32_t *__restrict__ a, int64_t lo0, int64_t hi0,
+                                             const int32_t (&y)[K], int64_t (&out)[K]) {
+  int64_t base[K], n = hi0 - lo0;
+#pragma unroll
+  for (int q = 0; q < K; q++) base[q] = lo0;
+  if (n <= 0) {
+#pragma unroll
+    for (int q = 0; q < K; q++) out[q] = lo0;
+    return;
+  }
+  // invariant: the answer lies in [base, base + n]; every read index is
+  // base + half < base + n <= hi0
+  while (n > 1) {
+    const int64_t half = n >> 1;
+#pragma unroll
+    for (int q = 0; q < K; q++) base[q] = a[base[q] + half] < y[q] ? base[q] + half : base[q];
+    n -= half;
+  }
+#pragma unroll
+  for (int q = 0; q < K; q++) out[q] = base[q] + (a[base[q]] < y[q] ? 1 : 0);
+}
+
+// N independent table lookups issued together: the home slots of all keys
+// are loaded before any collision chain is followed.  want[q] = false skips
+// lookup q (pos[q] = -1).
+template <int N>
+__device__ __forceinline__ void table_find_n(const TableView &T, const int32_t (&v1)[N],
+                                             const uint64_t (&key)[N], const bool (&want)[N],
+                                             int64_t (&pos)[N], Slot (&out)[N]) {
+  uint64_t base[N], cap[N], i[N];
+#pragma unroll
+  for (int q = 0; q < N; q++) {
+    pos[q] = -1;
+    base[q] = 0;
+    cap[q] = 0;
+    i[q] = 0;
+    if (want[q]) {
+      base[q] = T.seg[v1[q]];
+      cap[q] = T.seg[v1[q] + 1] - base[q];
+      if (cap[q]) i[q] = home_slot(key[q], cap[q]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < N; q++)
+    if (want[q] && cap[q]) out[q] = T.slots[base[q] + i[q]];
+#pragma unroll
+  for (int q = 0; q < N; q++) {
+    if (!want[q] || !cap[q]) continue;
+    for (uint64_t probe = 0; probe < cap[q]; probe++) {
+      if (out[q].key == key[q]) {
+        pos[q] = (int64_t)(base[q] + i[q]);
+        break;
+      }
+      if (out[q].key == 0) break;
+      if (++i[q] == cap[q]) i[q] = 0;
+      out[q] = T.slots[base[q] + i[q]];
+    }
+  }
+}
+
 // Wave-aggregated append: every active lane calls it; lanes with want=true
 // get consecutive positions in buf reserved with one atomic per wave.
 __device__ __forceinline__ void wave_append(bool want, uint32_t val, uint32_t *buf,
@@ -156,6 +219,39 @@ __device__ __forceinline__ void wave_append(bool want, uint32_t val, uint32_t *b
   base = __shfl(base, leader);
   if (want) buf[base + (uint32_t)__popcll(m & lanes_below())] = val;
 }
+
+// Per-wave staging of appends in LDS.  One wave owns `buf` (kCap entries);
+// `count` is wave-uniform.  Entries are flushed to the global list with a
+// single atomic when fewer than 64 free entries remain, so a round with
+// A appended r-cliques costs about A / (kCap - 64) global atomics instead of
+// one per appending wave call (same-address atomics serialise across XCDs).
+template <int kCap>
+struct WaveAppender {
+  uint32_t *buf;   // LDS, kCap entries, private to this wave
+  uint32_t count;  // wave-uniform
+  uint32_t *out;
+  uint32_t *counter;
+
+  __device__ __forceinline__ void flush() {
+    if (count == 0) return;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    uint32_t base = 0;
+    if (lane_id() == 0) base = atomicAdd(counter, count);
+    base = __shfl(base, 0);
+    for (uint32_t i = (uint32_t)lane_id(); i < count; i += kWave) out[base + i] = buf[i];
+    __builtin_amdgcn_wave_barrier();
+    count = 0;
+  }
+  // every lane of the wave calls this together
+  __device__ __forceinline__ void push(bool want, uint32_t val) {
+    const uint64_t m = __ballot(want);
+    if (m == 0) return;
+    if (want) buf[count + (uint32_t)__popcll(m & lanes_below())] = val;
+    count += (uint32_t)__popcll(m);
+    if (count > (uint32_t)(kCap - kWave)) flush();
+  }
+};
 
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
 #pragma unroll

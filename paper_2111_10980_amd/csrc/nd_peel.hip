@@ -45,55 +45,66 @@ struct LaneStats {
   uint32_t err = 0;
 };
 
+constexpr int kAppendCap = 512;  // LDS entries per wave for next-frontier appends
+using Appender = WaveAppender<kAppendCap>;
+
 // Update-Func for one s-clique S (sorted) found from the peeled r-clique at
 // slot p, whose vertices occupy the positions in rmask.  Called by every
 // lane of the wave in lock-step (active=false lanes only join the appends).
 template <int R, int S, bool kConvergent>
 __device__ __forceinline__ void update_func(const PeelArgs &a, const int32_t (&Sv)[S],
                                             uint32_t rmask, uint32_t p, bool active,
-                                            LaneStats &ls) {
+                                            LaneStats &ls, Appender *ap) {
   constexpr Combos<S, R> cb{};
-  uint32_t pos[cb.N];
-  bool live[cb.N];
+  constexpr int N = cb.N;
+  int32_t v1[N];
+  uint64_t key[N];
+  bool want[N];
+#pragma unroll
+  for (int q = 0; q < N; q++) {
+    int32_t Rv[R];
+#pragma unroll
+    for (int i = 0; i < R; i++) Rv[i] = Sv[cb.idx[q][i]];
+    v1[q] = Rv[0];
+    key[q] = make_key<R>(Rv, a.T.bits);
+    want[q] = active && cb.mask[q] != rmask;
+  }
+  int64_t pos[N];
+  Slot sl[N];
+  table_find_n<N>(a.T, v1, key, want, pos, sl);
   bool alive = active;
   uint32_t owner = p;
+  bool live[N];
 #pragma unroll
-  for (int q = 0; q < cb.N; q++) {
-    pos[q] = p;
+  for (int q = 0; q < N; q++) {
     live[q] = false;
-    if (alive && cb.mask[q] != rmask) {
-      int32_t Rv[R];
-#pragma unroll
-      for (int i = 0; i < R; i++) Rv[i] = Sv[cb.idx[q][i]];
-      Slot sl;
-      int64_t x = table_find(a.T, Rv[0], make_key<R>(Rv, a.T.bits), &sl);
-      if (x < 0) {
-        ls.err |= kErrLookup;
-        alive = false;
-      } else if (sl.stamp < a.t) {
-        alive = false;  // S was destroyed in an earlier round
-      } else {
-        pos[q] = (uint32_t)x;
-        if (sl.stamp == a.t) owner = (uint32_t)x < owner ? (uint32_t)x : owner;
-        else live[q] = true;
-      }
+    if (!want[q]) continue;
+    if (pos[q] < 0) {
+      ls.err |= kErrLookup;
+      alive = false;
+    } else if (sl[q].stamp < a.t) {
+      alive = false;  // S was destroyed in an earlier round
+    } else if (sl[q].stamp == a.t) {
+      owner = (uint32_t)pos[q] < owner ? (uint32_t)pos[q] : owner;
+    } else {
+      live[q] = true;
     }
   }
   if (active) ls.disc++;
   const bool mine = alive && owner == p;
 #pragma unroll
-  for (int q = 0; q < cb.N; q++) {
-    bool want = false;
+  for (int q = 0; q < N; q++) {
+    bool want_append = false;
     if (mine && live[q]) {
       uint32_t old = __hip_atomic_fetch_add(&a.T.slots[pos[q]].cnt, 0xFFFFFFFFu, __ATOMIC_RELAXED,
                                             __HIP_MEMORY_SCOPE_AGENT);
       ls.dec++;
-      want = old == a.k + 1;
+      want_append = old == a.k + 1;
     }
     if constexpr (kConvergent) {
-      wave_append(want, pos[q], a.Fnext, &a.ctr->next_size);
-    } else if (want) {
-      a.Fnext[atomicAdd(&a.ctr->next_size, 1u)] = pos[q];
+      ap->push(want_append, (uint32_t)pos[q]);
+    } else if (want_append) {
+      a.Fnext[atomicAdd(&a.ctr->next_size, 1u)] = (uint32_t)pos[q];
     }
   }
 }
@@ -127,7 +138,7 @@ __device__ void extend_q(const PeelArgs &a, const int32_t (&Rv)[R], int32_t (&Q)
           Sv[o] = Q[j++];
         }
       }
-      update_func<R, S, false>(a, Sv, rmask, p, true, ls);
+      update_func<R, S, false>(a, Sv, rmask, p, true, ls, nullptr);
     } else {
       extend_q<L + 1, R, S>(a, Rv, Q, p, ls);
     }
@@ -141,6 +152,8 @@ __global__ __launch_bounds__(256) void k_peel(PeelArgs a, const uint32_t *__rest
   const int wpb = blockDim.x / kWave;
   const int lane = lane_id();
   LaneStats ls;
+  __shared__ uint32_t abuf[256 / kWave][kAppendCap];
+  Appender ap{abuf[threadIdx.x / kWave], 0u, a.Fnext, &a.ctr->next_size};
   for (int64_t it = (int64_t)blockIdx.x * wpb + threadIdx.x / kWave; it < nF;
        it += (int64_t)gridDim.x * wpb) {
     const uint32_t p = F[it];
@@ -183,7 +196,7 @@ __global__ __launch_bounds__(256) void k_peel(PeelArgs a, const uint32_t *__rest
             rmask |= 1u << o;
           }
         }
-        update_func<R, S, true>(a, Sv, rmask, p, in, ls);
+        update_func<R, S, true>(a, Sv, rmask, p, in, ls, &ap);
       } else {
         if (in) {
           int32_t Q[S - R];
@@ -193,12 +206,350 @@ __global__ __launch_bounds__(256) void k_peel(PeelArgs a, const uint32_t *__rest
       }
     }
   }
+  ap.flush();
   uint64_t d = wave_sum_u64(ls.dec), c = wave_sum_u64(ls.disc);
   if (lane == 0) {
     if (d) atomicAdd((unsigned long long *)&a.ctr->decrements, (unsigned long long)d);
     if (c) atomicAdd((unsigned long long *)&a.ctr->discoveries, (unsigned long long)c);
   }
   if (ls.err) atomicOr(&a.ctr->err, ls.err);
+}
+
+// ------------------------------------------------------------ s = r + 1
+// The common neighbourhood I(R) of R = {v1 < ... < vr} is split by the
+// orientation (see the index builder): x > v1 are the set bits of the AND
+// of the rows of v2..vr in v1's adjacency bitmap; x < v1 are the members
+// of every apex list of the arcs (v1, vi).
+
+__device__ __forceinline__ int64_t lower_pos(const int32_t *__restrict__ a, int64_t lo, int64_t hi,
+                                             int32_t y) {
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (a[mid] < y) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// r = 3 liveness bitmaps.  A triangle's bits in its root's alive bitmap are
+// cleared after the round that peels it, so the AND of two alive rows lists
+// only candidates whose two triangles through v1 were not peeled earlier.
+__global__ void k_clear_alive(GraphView g, TableView T, FastView fx,
+                              const uint32_t *__restrict__ F, uint32_t nF) {
+  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < nF;
+       it += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t p = F[it];
+    int32_t Rv[3];
+    Rv[0] = T.v1[p];
+    decode_key<3>(T.slots[p].key, T.bits, Rv);
+    const int64_t o = g.up[Rv[0]];
+    const int d = (int)(g.rp[Rv[0] + 1] - o);
+    if (d > 512) continue;
+    const int64_t i = lower_pos(g.col, o, o + d, Rv[1]) - o;
+    const int64_t j = lower_pos(g.col, o, o + d, Rv[2]) - o;
+    if (i >= d || j >= d) continue;
+    const int wd = (d + 63) >> 6;
+    unsigned long long *rows = (unsigned long long *)(fx.alive + fx.bm_off[Rv[0]]);
+    atomicAnd(&rows[i * wd + (j >> 6)], ~(1ull << (j & 63)));
+    atomicAnd(&rows[j * wd + (i >> 6)], ~(1ull << (i & 63)));
+  }
+}
+
+// count(R) = |I(R)|, computed per r-clique without atomics.
+template <int R>
+__global__ __launch_bounds__(256) void k_count_direct(GraphView g, TableView T, FastView fx,
+                                                      const uint32_t *__restrict__ occ,
+                                                      uint64_t n_r, uint32_t *err) {
+  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < (int64_t)n_r;
+       it += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t p = occ[it];
+    const Slot sl = T.slots[p];
+    int32_t Rv[R];
+    Rv[0] = T.v1[p];
+    decode_key<R>(sl.key, T.bits, Rv);
+    const int32_t v1 = Rv[0];
+    const int64_t o = g.up[v1];
+    const int d = (int)(g.rp[v1 + 1] - o);
+    int64_t e[R];
+    bool found = true;
+    {
+      int32_t ys[R - 1];
+      int64_t at[R - 1];
+#pragma unroll
+      for (int i = 1; i < R; i++) ys[i - 1] = Rv[i];
+      lower_bounds<R - 1>(g.col, o, o + d, ys, at);
+#pragma unroll
+      for (int i = 1; i < R; i++) {
+        e[i] = at[i - 1];
+        found = found && e[i] < o + d && g.col[e[i]] == Rv[i];
+      }
+    }
+    if (!found) {
+      atomicOr(err, kErrLookup);
+      continue;
+    }
+    uint32_t c = 0;
+    if (d <= 512) {
+      const int wd = (d + 63) >> 6;
+      const uint64_t *rows = fx.bm + fx.bm_off[v1];
+      for (int w = 0; w < wd; w++) {
+        uint64_t x = ~0ull;
+#pragma unroll
+        for (int i = 1; i < R; i++) x &= rows[(e[i] - o) * wd + w];
+        c += (uint32_t)__popcll(x);
+      }
+    } else {
+      for (int64_t j = o; j < o + d; j++) {
+        const int32_t y = g.col[j];
+        bool ok = true;
+#pragma unroll
+        for (int i = 1; i < R; i++) ok = ok && adjacent(g, y, Rv[i]);
+        c += ok ? 1u : 0u;
+      }
+    }
+    int drv = 1;
+    uint64_t best = fx.lptr[e[1] + 1] - fx.lptr[e[1]];
+#pragma unroll
+    for (int i = 2; i < R; i++) {
+      uint64_t len = fx.lptr[e[i] + 1] - fx.lptr[e[i]];
+      if (len < best) {
+        best = len;
+        drv = i;
+      }
+    }
+    if (R == 2) {
+      c += (uint32_t)best;
+    } else {
+      for (uint64_t j = fx.lptr[e[drv]]; j < fx.lptr[e[drv] + 1]; j++) {
+        const int32_t x = fx.lval[j];
+        bool ok = true;
+#pragma unroll
+        for (int i = 1; i < R; i++)
+          if (i != drv) ok = ok && sorted_contains(fx.lval, fx.lptr[e[i]], fx.lptr[e[i] + 1], x);
+        c += ok ? 1u : 0u;
+      }
+    }
+    T.slots[p].cnt = c;
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void peel_candidate(const PeelArgs &a, const int32_t (&Rv)[R],
+                                               int32_t x, bool in, uint32_t p, LaneStats &ls,
+                                               Appender *ap) {
+  constexpr int S = R + 1;
+  int32_t Sv[S];
+  uint32_t rmask = 0;
+  int at = 0;
+#pragma unroll
+  for (int i = 0; i < R; i++) at += Rv[i] < x ? 1 : 0;
+#pragma unroll
+  for (int o = 0, i = 0; o < S; o++) {
+    if (o == at) {
+      Sv[o] = x;
+    } else {
+      Sv[o] = Rv[i++];
+      rmask |= 1u << o;
+    }
+  }
+  update_func<R, S, true>(a, Sv, rmask, p, in, ls, ap);
+}
+
+// One wave per peeled r-clique.  The critical path is kept short: the
+// local indices of v2..vr in N+(v1) come from `loc` (no search), the
+// candidates x > v1 (set bits of the AND of v1's alive rows) and x < v1
+// (the shortest apex list, membership in the other list tested in LDS) are
+// handed out in a single lane-parallel pass, and each candidate's r-subsets
+// are probed together.
+constexpr int kListCap = 1024;  // LDS entries per wave for a staged apex list
+
+__device__ __forceinline__ bool lds_contains(const int32_t *a, int n, int32_t x) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const int32_t v = a[mid];
+    if (v == x) return true;
+    if (v < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return false;
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_peel_fast(PeelArgs a, FastView fx,
+                                                   const uint64_t *__restrict__ loc,
+                                                   const uint32_t *__restrict__ F, uint32_t nF) {
+  const int wpb = blockDim.x / kWave;
+  const int wv = threadIdx.x / kWave;
+  const int lane = lane_id();
+  LaneStats ls;
+  __shared__ uint32_t abuf[256 / kWave][kAppendCap];
+  __shared__ int32_t lbuf[256 / kWave][R == 3 ? kListCap : 1];
+  Appender ap{abuf[wv], 0u, a.Fnext, &a.ctr->next_size};
+  for (int64_t it = (int64_t)blockIdx.x * wpb + wv; it < nF; it += (int64_t)gridDim.x * wpb) {
+    const uint32_t p = F[it];
+    const Slot sl = a.T.slots[p];
+    if (sl.cnt == 0) continue;  // every s-clique of R is already gone
+    int32_t Rv[R];
+    Rv[0] = a.T.v1[p];
+    const uint64_t lc = loc[p];
+    decode_key<R>(sl.key, a.T.bits, Rv);
+    const int32_t v1 = Rv[0];
+    const int64_t o = a.g.up[v1];
+    const int d = (int)(a.g.rp[v1 + 1] - o);
+    int64_t e[R];
+    if (lc >> 63) {
+#pragma unroll
+      for (int i = 1; i < R; i++) e[i] = o + (int64_t)((lc >> (9 * (i - 1))) & 511u);
+    } else {
+      int32_t ys[R - 1];
+      int64_t at[R - 1];
+      bool found = true;
+#pragma unroll
+      for (int i = 1; i < R; i++) ys[i - 1] = Rv[i];
+      lower_bounds<R - 1>(a.g.col, o, o + d, ys, at);
+#pragma unroll
+      for (int i = 1; i < R; i++) {
+        e[i] = at[i - 1];
+        found = found && e[i] < o + d && a.g.col[e[i]] == Rv[i];
+      }
+      if (!found) {  // wave-uniform
+        ls.err |= kErrLookup;
+        continue;
+      }
+    }
+    // ---- x > v1: set bits of the AND of the (alive) rows of v2..vr
+    const bool has_bm = d <= 512;
+    uint32_t total1, iw[8];
+    uint64_t cw = 0;
+    if (has_bm) {
+      const int wd = (d + 63) >> 6;
+      const uint64_t *rows = (R == 3 ? fx.alive : fx.bm) + fx.bm_off[v1];
+      if (lane < wd) {
+        cw = ~0ull;
+#pragma unroll
+        for (int i = 1; i < R; i++) cw &= rows[(e[i] - o) * wd + lane];
+      }
+      const uint32_t incl = wave_incl_scan((uint32_t)__popcll(cw));
+      total1 = __shfl(incl, kWave - 1);
+#pragma unroll
+      for (int q = 0; q < 8; q++) iw[q] = __shfl(incl, q);
+    } else {
+      total1 = (uint32_t)d;  // heavy root: every out-neighbour, edge-tested
+#pragma unroll
+      for (int q = 0; q < 8; q++) iw[q] = 0;
+    }
+    // ---- x < v1: the shortest apex list; membership in the others
+    int drv = 1;
+    uint64_t len2 = fx.lptr[e[1] + 1] - fx.lptr[e[1]];
+#pragma unroll
+    for (int i = 2; i < R; i++) {
+      const uint64_t len = fx.lptr[e[i] + 1] - fx.lptr[e[i]];
+      if (len < len2) {
+        len2 = len;
+        drv = i;
+      }
+    }
+    const uint64_t lb = fx.lptr[e[drv]];
+    int staged_len = -1;
+    uint64_t ob = 0, oe = 0;
+    if constexpr (R == 3) {
+      const int other = drv == 1 ? 2 : 1;
+      ob = fx.lptr[e[other]];
+      oe = fx.lptr[e[other] + 1];
+      if (len2 > 0 && oe - ob <= (uint64_t)kListCap) {
+        staged_len = (int)(oe - ob);
+        for (int i = lane; i < staged_len; i += kWave) lbuf[wv][i] = fx.lval[ob + i];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    const uint64_t total = (uint64_t)total1 + len2;
+    for (uint64_t base = 0; base < total; base += kWave) {
+      const uint64_t k = base + lane;
+      bool in = k < total;
+      int32_t x = 0;
+      // word of v1's bitmap holding part-1 candidate k (computed by every
+      // lane so the shuffle runs with the whole wave active)
+      const uint32_t kk = k < total1 ? (uint32_t)k : 0u;
+      int w = 0;
+      uint32_t before = 0;
+#pragma unroll
+      for (int q = 0; q < 7; q++) {
+        if (iw[q] <= kk) {
+          w = q + 1;
+          before = iw[q];
+        }
+      }
+      const uint64_t wordw = __shfl(cw, w);
+      if (in && k < total1) {
+        if (has_bm) {
+          uint64_t m = wordw;
+          for (uint32_t q = 0; q < kk - before; q++) m &= m - 1;
+          x = a.g.col[o + w * 64 + (__ffsll((unsigned long long)m) - 1)];
+        } else {
+          x = a.g.col[o + (int64_t)k];
+#pragma unroll
+          for (int i = 1; i < R; i++) in = in && adjacent(a.g, x, Rv[i]);
+        }
+      } else if (in) {
+        x = fx.lval[lb + (k - total1)];
+        if constexpr (R == 3) {
+          in = staged_len >= 0 ? lds_contains(lbuf[wv], staged_len, x)
+                               : sorted_contains(fx.lval, ob, oe, x);
+        } else {
+#pragma unroll
+          for (int i = 1; i < R; i++)
+            if (i != drv)
+              in = in && sorted_contains(fx.lval, fx.lptr[e[i]], fx.lptr[e[i] + 1], x);
+        }
+      }
+      peel_candidate<R>(a, Rv, x, in, p, ls, &ap);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  ap.flush();
+  uint64_t dsum = wave_sum_u64(ls.dec), csum = wave_sum_u64(ls.disc);
+  if (lane == 0) {
+    if (dsum) atomicAdd((unsigned long long *)&a.ctr->decrements, (unsigned long long)dsum);
+    if (csum) atomicAdd((unsigned long long *)&a.ctr->discoveries, (unsigned long long)csum);
+  }
+  if (ls.err) atomicOr(&a.ctr->err, ls.err);
+}
+
+// Local indices of v2..vr in N+(v1) for every occupied slot of a bitmap
+// root (9 bits each, bit 63 marks them valid).
+template <int R>
+__global__ void k_make_loc(GraphView g, TableView T, uint64_t n_slots, uint64_t *loc) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < (int64_t)n_slots;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const Slot sl = T.slots[p];
+    uint64_t v = 0;
+    if (sl.key != 0) {
+      int32_t Rv[R];
+      Rv[0] = T.v1[p];
+      decode_key<R>(sl.key, T.bits, Rv);
+      const int64_t o = g.up[Rv[0]];
+      const int d = (int)(g.rp[Rv[0] + 1] - o);
+      if (d <= 512) {
+        int32_t ys[R - 1];
+        int64_t at[R - 1];
+#pragma unroll
+        for (int i = 1; i < R; i++) ys[i - 1] = Rv[i];
+        lower_bounds<R - 1>(g.col, o, o + d, ys, at);
+        bool found = true;
+#pragma unroll
+        for (int i = 1; i < R; i++)
+          found = found && at[i - 1] < o + d && g.col[at[i - 1]] == Rv[i];
+        if (found) {
+          v = 1ull << 63;
+#pragma unroll
+          for (int i = 1; i < R; i++) v |= (uint64_t)(at[i - 1] - o) << (9 * (i - 1));
+        }
+      }
+    }
+    loc[p] = v;
+  }
 }
 
 __global__ void k_stamp(const uint32_t *__restrict__ F, uint32_t nF, Slot *slots, uint32_t t) {
@@ -219,25 +570,63 @@ __global__ __launch_bounds__(256) void k_live_min(const uint32_t *__restrict__ L
   if (lane_id() == 0 && m != 0xFFFFFFFFu) atomicMin(out, m);
 }
 
-__global__ __launch_bounds__(256) void k_live_partition(const uint32_t *__restrict__ L, uint32_t nL,
-                                                        const Slot *__restrict__ slots, uint32_t k,
-                                                        uint32_t *F, uint32_t *nF, uint32_t *Lo,
-                                                        uint32_t *nLo) {
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nL;
-       base += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = base + threadIdx.x;
-    bool f = false, keep = false;
-    uint32_t p = 0;
-    if (i < nL) {
-      p = L[i];
-      const Slot s = slots[p];
-      if (s.stamp == kLive) {
-        f = s.cnt <= k;
-        keep = !f;
+// Partition of the live list into this level's frontier and the rest.
+// Each block compacts a tile of 256 x 16 entries with one atomic per output
+// per tile (a single global counter per wave would serialise in L2).
+constexpr int kPartThreads = 256;
+constexpr int kPartItems = 16;
+
+__global__ __launch_bounds__(kPartThreads) void k_live_partition(
+    const uint32_t *__restrict__ L, uint32_t nL, const Slot *__restrict__ slots, uint32_t k,
+    uint32_t *F, uint32_t *nF, uint32_t *Lo, uint32_t *nLo) {
+  __shared__ uint32_t wsum[2][kPartThreads / kWave];
+  __shared__ uint32_t base[2];
+  const int tid = threadIdx.x, w = tid / kWave;
+  for (int64_t tile = (int64_t)blockIdx.x * kPartThreads * kPartItems; tile < nL;
+       tile += (int64_t)gridDim.x * kPartThreads * kPartItems) {
+    uint32_t p[kPartItems];
+    uint32_t fm = 0, km = 0;  // bit j: item j goes to F / stays live
+#pragma unroll
+    for (int j = 0; j < kPartItems; j++) {
+      const int64_t i = tile + (int64_t)j * kPartThreads + tid;
+      p[j] = 0;
+      if (i < nL) {
+        p[j] = L[i];
+        const Slot s = slots[p[j]];
+        if (s.stamp == kLive) {
+          if (s.cnt <= k) fm |= 1u << j;
+          else km |= 1u << j;
+        }
       }
     }
-    wave_append(f, p, F, nF);
-    wave_append(keep, p, Lo, nLo);
+    const uint32_t fc = (uint32_t)__popc(fm), kc = (uint32_t)__popc(km);
+    const uint32_t fi = wave_incl_scan(fc), ki = wave_incl_scan(kc);
+    if (lane_id() == kWave - 1) {
+      wsum[0][w] = fi;
+      wsum[1][w] = ki;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t tf = 0, tk = 0;
+      for (int q = 0; q < kPartThreads / kWave; q++) {
+        uint32_t a = wsum[0][q], b = wsum[1][q];
+        wsum[0][q] = tf;
+        wsum[1][q] = tk;
+        tf += a;
+        tk += b;
+      }
+      base[0] = tf ? atomicAdd(nF, tf) : 0u;
+      base[1] = tk ? atomicAdd(nLo, tk) : 0u;
+    }
+    __syncthreads();
+    uint32_t of = base[0] + wsum[0][w] + fi - fc;
+    uint32_t ok = base[1] + wsum[1][w] + ki - kc;
+#pragma unroll
+    for (int j = 0; j < kPartItems; j++) {
+      if (fm >> j & 1u) F[of++] = p[j];
+      if (km >> j & 1u) Lo[ok++] = p[j];
+    }
+    __syncthreads();
   }
 }
 
@@ -326,6 +715,63 @@ void peel_round(const OrientedGraph &g, int r, int s, const TableView &T, const 
   }
 }
 
+void count_direct(const OrientedGraph &g, int r, const TableView &T, const FastIndex &fx,
+                  const uint32_t *occ, uint64_t n_r, Counters *dctr, hipStream_t st) {
+  if (!n_r) return;
+  dim3 grid((unsigned)grid_for(n_r, 256, 1 << 20)), blk(256);
+  const GraphView gv = g.view();
+  const FastView fv = fx.view();
+  switch (r) {
+    case 2: hipLaunchKernelGGL(k_count_direct<2>, grid, blk, 0, st, gv, T, fv, occ, n_r, &dctr->err); break;
+    case 3: hipLaunchKernelGGL(k_count_direct<3>, grid, blk, 0, st, gv, T, fv, occ, n_r, &dctr->err); break;
+    case 4: hipLaunchKernelGGL(k_count_direct<4>, grid, blk, 0, st, gv, T, fv, occ, n_r, &dctr->err); break;
+    case 5: hipLaunchKernelGGL(k_count_direct<5>, grid, blk, 0, st, gv, T, fv, occ, n_r, &dctr->err); break;
+    case 6: hipLaunchKernelGGL(k_count_direct<6>, grid, blk, 0, st, gv, T, fv, occ, n_r, &dctr->err); break;
+    default: break;
+  }
+}
+
+void peel_round_fast(const OrientedGraph &g, int r, const TableView &T, const FastIndex &fx,
+                     const uint32_t *F, uint32_t nF, uint32_t t, uint32_t k, uint32_t *Fnext,
+                     Counters *dctr, hipStream_t st) {
+  if (!nF) return;
+  PeelArgs a{g.view(), T, t, k, Fnext, dctr};
+  const FastView fv = fx.view();
+  const uint64_t *loc = fx.loc.get();
+  dim3 grid((unsigned)grid_for(nF, 4, 1 << 20)), blk(256);
+  switch (r) {
+    case 2: hipLaunchKernelGGL(k_peel_fast<2>, grid, blk, 0, st, a, fv, loc, F, nF); break;
+    case 3: hipLaunchKernelGGL(k_peel_fast<3>, grid, blk, 0, st, a, fv, loc, F, nF); break;
+    case 4: hipLaunchKernelGGL(k_peel_fast<4>, grid, blk, 0, st, a, fv, loc, F, nF); break;
+    case 5: hipLaunchKernelGGL(k_peel_fast<5>, grid, blk, 0, st, a, fv, loc, F, nF); break;
+    case 6: hipLaunchKernelGGL(k_peel_fast<6>, grid, blk, 0, st, a, fv, loc, F, nF); break;
+    default: break;
+  }
+}
+
+void build_slot_loc(const OrientedGraph &g, int r, const TableView &T, uint64_t n_slots,
+                    FastIndex *fx, hipStream_t st) {
+  fx->loc.reset(n_slots ? n_slots : 1);
+  if (!n_slots) return;
+  dim3 grid((unsigned)grid_for(n_slots, 256)), blk(256);
+  const GraphView gv = g.view();
+  switch (r) {
+    case 2: hipLaunchKernelGGL(k_make_loc<2>, grid, blk, 0, st, gv, T, n_slots, fx->loc.get()); break;
+    case 3: hipLaunchKernelGGL(k_make_loc<3>, grid, blk, 0, st, gv, T, n_slots, fx->loc.get()); break;
+    case 4: hipLaunchKernelGGL(k_make_loc<4>, grid, blk, 0, st, gv, T, n_slots, fx->loc.get()); break;
+    case 5: hipLaunchKernelGGL(k_make_loc<5>, grid, blk, 0, st, gv, T, n_slots, fx->loc.get()); break;
+    case 6: hipLaunchKernelGGL(k_make_loc<6>, grid, blk, 0, st, gv, T, n_slots, fx->loc.get()); break;
+    default: break;
+  }
+}
+
+void clear_alive(const OrientedGraph &g, const TableView &T, const FastIndex &fx,
+                 const uint32_t *F, uint32_t nF, hipStream_t st) {
+  if (!nF) return;
+  hipLaunchKernelGGL(k_clear_alive, dim3((unsigned)grid_for(nF, 256)), dim3(256), 0, st,
+                     g.view(), T, fx.view(), F, nF);
+}
+
 void live_min(const uint32_t *L, uint32_t nL, const Slot *slots, Counters *dctr, hipStream_t st) {
   fill_u32(&dctr->live_min, 0xFFFFFFFFu, 1, st);
   if (!nL) return;
@@ -338,8 +784,10 @@ void live_partition(const uint32_t *L, uint32_t nL, const Slot *slots, uint32_t 
   fill_u32(&dctr->next_size, 0, 1, st);
   fill_u32(&dctr->live_size, 0, 1, st);
   if (!nL) return;
-  hipLaunchKernelGGL(k_live_partition, dim3((unsigned)grid_for(nL, 256 * 4, 16384)), dim3(256), 0,
-                     st, L, nL, slots, k, F, &dctr->next_size, Lout, &dctr->live_size);
+  hipLaunchKernelGGL(k_live_partition,
+                     dim3((unsigned)grid_for(nL, kPartThreads * kPartItems, 8192)),
+                     dim3(kPartThreads), 0, st, L, nL, slots, k, F, &dctr->next_size, Lout,
+                     &dctr->live_size);
 }
 
 void occupied_list(const Slot *slots, uint64_t n_slots, uint32_t *occ, hipStream_t st) {

@@ -187,6 +187,12 @@ __global__ void k_fill_slots(Slot *p, int64_t n) {
   }
 }
 
+__global__ void k_widen(const uint32_t *__restrict__ a, uint64_t *b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
 __global__ void k_iota(uint32_t *p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -235,6 +241,12 @@ void fill_slots(Slot *p, int64_t n, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill_slots, dim3((unsigned)blocks_for(n, 256 * 4, 16384)), dim3(256), 0,
                      st, p, n);
+}
+
+void widen_u32_to_u64(const uint32_t *a, uint64_t *b, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_widen, dim3((unsigned)blocks_for(n, 256 * 8, 8192)), dim3(256), 0, st, a,
+                     b, n);
 }
 
 void iota_u32(uint32_t *p, int64_t n, hipStream_t st) {

@@ -8,14 +8,16 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "nd.h")
+HEADERS = [os.path.join(ROOT, "include", "nd.h"), os.path.join(ROOT, "include", "nd_roofline.h")]
 LIB = os.path.join(ROOT, "paper_2111_10980_amd", "libnd.so")
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(nd_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(nd_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_entry_points():
@@ -44,8 +46,8 @@ def test_struct_layouts():
     import paper_2111_10980_amd as nd
     assert ctypes.sizeof(nd.nd_csr) == 32
     assert ctypes.sizeof(nd.nd_options) == 16
-    # 7 u64 + 2 u32 + 8 floats
-    assert ctypes.sizeof(nd.nd_stats) == 7 * 8 + 2 * 4 + 8 * 4
+    # 7 u64 + 2 u32 + 8 floats + 2 floats + 2 u32
+    assert ctypes.sizeof(nd.nd_stats) == 7 * 8 + 2 * 4 + 8 * 4 + 2 * 4 + 2 * 4
 
 
 def test_binding_names_match_header():

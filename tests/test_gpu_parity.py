@@ -62,9 +62,10 @@ RS_ALL = [(1, 2), (1, 3), (2, 3), (2, 4), (3, 4), (3, 5), (4, 5), (2, 5), (1, 4)
           (5, 6), (3, 6), (2, 6), (1, 5), (5, 7), (6, 7), (1, 6), (2, 7)]
 
 
+@pytest.mark.parametrize("generic", [False, True])
 @pytest.mark.parametrize("r,s", [(3, 4), (2, 3), (1, 2), (4, 5), (2, 4), (1, 3)])
-def test_worked_example(r, s):
-    check_against_oracle(inputs.worked_example(), r, s)
+def test_worked_example(r, s, generic):
+    check_against_oracle(inputs.worked_example(), r, s, generic=generic)
 
 
 @pytest.mark.parametrize("r,s", RS_ALL)
@@ -73,8 +74,50 @@ def test_planted_small_all_rs(r, s):
     check_against_oracle(g, r, s)
 
 
+@pytest.mark.parametrize("r,s", [(2, 3), (3, 4), (4, 5), (5, 6), (6, 7)])
+def test_generic_path_for_s_eq_r_plus_1(r, s):
+    """The generic path (Count-Func atomics, intersection by edge tests) on
+    the shapes the bitmap/apex-list path normally serves."""
+    g = inputs.planted_er(150, 7.0, 3, 7, 12, 41)
+    check_against_oracle(g, r, s, generic=True)
+
+
+def heavy_root_graph(seed=12):
+    """Vertex 0 adjacent to A = {1..600}; every a in A also has 601 private
+    leaves, so in degree order 0 ranks below all of A and has 600 > 512
+    out-neighbours (no bitmap).  A sparse random graph plus planted cliques
+    inside A gives 0 many triangles, 4-cliques and 5-cliques."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    k, leaves = 600, 601
+    us, vs = [np.zeros(k, dtype=np.int64)], [np.arange(1, k + 1, dtype=np.int64)]
+    leaf0 = k + 1
+    a = np.repeat(np.arange(1, k + 1, dtype=np.int64), leaves)
+    us.append(a)
+    vs.append(leaf0 + np.arange(k * leaves, dtype=np.int64))
+    inner = inputs.erdos_renyi(k, 2400, seed)
+    iu, iv = inputs.edges_of(inner)
+    us.append(iu + 1)
+    vs.append(iv + 1)
+    for _ in range(6):
+        c = rng.choice(k, size=int(rng.integers(6, 11)), replace=False) + 1
+        x, y = np.triu_indices(len(c), 1)
+        us.append(c[x])
+        vs.append(c[y])
+    n = leaf0 + k * leaves
+    return inputs.csr_from_edges(n, np.concatenate(us), np.concatenate(vs))
+
+
+@pytest.mark.parametrize("r,s", [(2, 3), (3, 4), (4, 5)])
+def test_heavy_root_fallback_in_fast_path(r, s):
+    """Roots with more than 512 out-neighbours keep no bitmap; the s = r+1
+    path then tests x > v1 with edge tests."""
+    d = check_against_oracle(heavy_root_graph(), r, s)
+    assert d.stats["max_out_degree"] > 512
+
+
 @pytest.mark.parametrize("seed", [1, 2, 3])
-@pytest.mark.parametrize("r,s", [(2, 3), (3, 4), (2, 4), (1, 2)])
+@pytest.mark.parametrize("r,s", [(2, 3), (3, 4), (2, 4), (1, 2), (4, 5)])
 def test_er_medium(seed, r, s):
     g = inputs.erdos_renyi(1500, 15000 if s - r == 1 else 9000, seed)
     check_against_oracle(g, r, s)
@@ -86,10 +129,11 @@ def test_er_2000_23_full_workload():
         check_against_oracle(inputs.er_2000(seed), 2, 3)
 
 
+@pytest.mark.parametrize("generic", [False, True])
 @pytest.mark.parametrize("r,s", [(3, 4), (2, 3), (2, 4), (1, 2), (4, 5), (1, 3)])
-def test_rmat_small(r, s):
+def test_rmat_small(r, s, generic):
     g = inputs.rmat(10, 8, 123)
-    check_against_oracle(g, r, s)
+    check_against_oracle(g, r, s, generic=generic)
 
 
 @pytest.mark.parametrize("r,s", [(3, 4), (4, 5), (2, 4)])
