@@ -67,8 +67,6 @@ def main():
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--orient", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run one plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -125,21 +123,27 @@ def main():
         kern, t_ms, nbytes, launches = peel_name, peel_ms, peel_bytes, peel_launches
     else:
         kern, t_ms, nbytes, launches = count_name, cnt_ms, count_bytes, len(runs)
+    launches = max(1, launches)
     achieved = nbytes / (t_ms / 1000.0) / 1e9 if t_ms > 0 else 0.0
+    n_launch = max(1, launches)
+    # measured device ceilings; k_copy inside also calibrates the HBM counters
+    ceil = nd.nd_roofline_measure(st["table_slots"] * SLOT_BYTES, st["n_r"] * 4)
+    log(f"[bench] ceilings: {ceil}")
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{kern.split('<')[0]}_{args.workload}.json")
+    if os.path.exists(tfile):
+        from paper_2111_10980_amd import traffic as tr
+        rec = json.load(open(tfile))
+        if rec.get("source_hash") == tr.source_hash():
+            traffic = rec["traffic_bytes_per_launch"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                 "kernel": kern, "launches_per_step": launches // max(1, len(runs)),
                 "kernel_ms_per_step": round(t_ms / len(runs), 3),
-                "bytes_per_step": nbytes // len(runs),
+                "algorithmic_bytes_per_launch": nbytes // n_launch,
                 "count_kernel_ms_per_step": round(cnt_ms / len(runs), 3),
-                "peel_kernel_ms_per_step": round(peel_ms / len(runs), 3)}
-
-    if args.copy_calibration:
-        a = torch.empty(1 << 28, dtype=torch.int32, device=dev)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        log("[bench] copy calibration: 1 GiB device copy done")
+                "peel_kernel_ms_per_step": round(peel_ms / len(runs), 3),
+                "measured_ceilings": {k: round(v, 3) for k, v in ceil.items()}}
 
     base = None
     if not args.no_cpu_baseline:

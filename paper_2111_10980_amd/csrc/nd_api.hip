@@ -176,6 +176,7 @@ struct nd_plan_s {
   DevBuf<int32_t> v1;
   DevBuf<uint32_t> occ;
   DevBuf<Counters> ctr;
+  DevBuf<unsigned long long> stats;  // kStatLines x kStatStride statistic lines
   FastIndex fx;
   bool fast = false;  // s = r+1 path (bitmaps + apex lists)
   uint64_t n_r = 0, n_slots = 0, held = 0;
@@ -366,13 +367,17 @@ nd_status nd_run(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *cou
     tm.mark(0, st);
     // ---- count (Count-Func)
     fill_u32((uint32_t *)dc, 0, sizeof(Counters) / 4, st);
+    p->stats.reset((size_t)kStatLines * kStatStride);
+    fill_u64((uint64_t *)p->stats.get(), 0, (int64_t)kStatLines * kStatStride, st);
     if (p->fast) {
       if (timing) kt.mark(0, st);
       count_direct(p->g, r, p->table(), p->fx, p->occ.get(), p->n_r, dc, st);
       if (timing) kt.mark(1, st);
     } else {
-      count_scliques(p->g, r, s, p->table(), dc, st, timing ? kt.ev[0] : nullptr,
-                     timing ? kt.ev[1] : nullptr);
+      count_scliques(p->g, r, s, p->table(), dc, p->stats.get(), st,
+                     timing ? kt.ev[0] : nullptr, timing ? kt.ev[1] : nullptr);
+      stats_collect(p->stats.get(), dc, st);
+      fill_u64((uint64_t *)p->stats.get(), 0, (int64_t)kStatLines * kStatStride, st);
     }
     DevBuf<uint64_t> total(1);
     fill_u64(total.get(), 0, 1, st);
@@ -407,6 +412,7 @@ nd_status nd_run(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *cou
     if (p->n_r)
       hip_check(hipMemcpyAsync(L.get(), p->occ.get(), 4 * p->n_r, hipMemcpyDeviceToDevice, st),
                 "copy");
+    SplitBufs sb;
     uint64_t nL = p->n_r, finished = 0;
     uint32_t k = 0, t = 0, nF = 0;
     p->round_sizes.clear();
@@ -431,12 +437,15 @@ nd_status nd_run(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *cou
       }
       stamp_frontier(F.get(), nF, p->slots.get(), t, st);
       fill_u32(&dc->next_size, 0, 1, st);
-      if (timing) kt.mark(2, st);
-      if (p->fast)
-        peel_round_fast(p->g, r, p->table(), p->fx, F.get(), nF, t, k, Fn.get(), dc, st);
-      else
-        peel_round(p->g, r, s, p->table(), F.get(), nF, t, k, Fn.get(), dc, st);
-      if (timing) kt.mark(3, st);
+      if (p->fast) {
+        peel_round_split(p->g, r, p->table(), p->fx, F.get(), nF, t, k, Fn.get(), dc,
+                         p->stats.get(), &sb, st, timing ? kt.ev[2] : nullptr,
+                         timing ? kt.ev[3] : nullptr);
+      } else {
+        if (timing) kt.mark(2, st);
+        peel_round(p->g, r, s, p->table(), F.get(), nF, t, k, Fn.get(), dc, p->stats.get(), st);
+        if (timing) kt.mark(3, st);
+      }
       if (p->fast && r == 3) clear_alive(p->g, p->table(), p->fx, F.get(), nF, st);
       p->round_sizes.push_back(nF);
       p->round_k.push_back(k);
@@ -457,6 +466,7 @@ nd_status nd_run(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *cou
       hip_check(hipMemcpyAsync(kround.get(), p->round_k.data(), 4 * p->round_k.size(),
                                hipMemcpyHostToDevice, st),
                 "copy levels");
+    stats_collect(p->stats.get(), dc, st);
     emit(r, p->occ.get(), p->n_r, p->table(), p->g.new2old.get(), kround.get(),
          (uint32_t)p->round_k.size(), rcl_dev, kappa_dev, st);
     tm.mark(4, st);

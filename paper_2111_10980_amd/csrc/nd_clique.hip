@@ -213,6 +213,7 @@ template <int R, int S>
 struct CountOp {
   TableView T;
   Counters *ctr;
+  unsigned long long *stats;
   struct Lane {
     uint64_t ns;
     uint32_t err;
@@ -238,8 +239,7 @@ struct CountOp {
     }
   }
   __device__ void lane_finish(Lane &l) const {
-    uint64_t ns = wave_sum_u64(l.ns);
-    if (lane_id() == 0 && ns) atomicAdd((unsigned long long *)&ctr->n_s, (unsigned long long)ns);
+    stat_add(stats, kStatNs, l.ns);
     if (l.err) atomicOr(&ctr->err, l.err);
   }
 };
@@ -396,12 +396,12 @@ void insert_r_impl(const OrientedGraph &g, const TableView &T, Counters *dctr, h
 }
 
 template <int R, int S>
-void count_s_impl(const OrientedGraph &g, const TableView &T, Counters *dctr, hipStream_t st,
-                  hipEvent_t ev0, hipEvent_t ev1) {
+void count_s_impl(const OrientedGraph &g, const TableView &T, Counters *dctr,
+                  unsigned long long *stats, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   Bins b;
   bin_roots(g, S - 1, dctr, &b, st);
   if (ev0) hipEventRecord(ev0, st);
-  launch_listing<S>(g, b, CountOp<R, S>{T, dctr}, st);
+  launch_listing<S>(g, b, CountOp<R, S>{T, dctr, stats}, st);
   if (ev1) hipEventRecord(ev1, st);
 }
 
@@ -449,11 +449,32 @@ void list_apex_keys(const OrientedGraph &g, uint64_t *cursor, uint64_t *keys, in
   launch_listing<3>(g, b, ApexOp{g.view(), (unsigned long long *)cursor, keys, xbits}, st);
 }
 
+__global__ __launch_bounds__(256) void k_stats_collect(const unsigned long long *__restrict__ stats,
+                                                       Counters *dctr) {
+  // one block: thread i sums column i's lines for the three statistics
+  uint64_t acc[3] = {0, 0, 0};
+  for (int line = threadIdx.x; line < kStatLines; line += blockDim.x)
+    for (int w = 0; w < 3; w++) acc[w] += stats[line * kStatStride + w];
+  for (int w = 0; w < 3; w++) {
+    const uint64_t t = wave_sum_u64(acc[w]);
+    if (lane_id() == 0 && t) {
+      unsigned long long *dst = (unsigned long long *)(w == kStatDec    ? &dctr->decrements
+                                                       : w == kStatDisc ? &dctr->discoveries
+                                                                        : &dctr->n_s);
+      atomicAdd(dst, (unsigned long long)t);
+    }
+  }
+}
+
+void stats_collect(unsigned long long *stats, Counters *dctr, hipStream_t st) {
+  hipLaunchKernelGGL(k_stats_collect, dim3(1), dim3(256), 0, st, stats, dctr);
+}
+
 #define ND_COUNT_CASE(R_, S_) \
-  case (R_) * 16 + (S_): count_s_impl<R_, S_>(g, T, dctr, st, ev0, ev1); break;
+  case (R_) * 16 + (S_): count_s_impl<R_, S_>(g, T, dctr, stats, st, ev0, ev1); break;
 
 void count_scliques(const OrientedGraph &g, int r, int s, const TableView &T, Counters *dctr,
-                    hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+                    unsigned long long *stats, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (g.n == 0) {
     if (ev0) hipEventRecord(ev0, st);
     if (ev1) hipEventRecord(ev1, st);

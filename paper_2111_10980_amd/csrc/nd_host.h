@@ -84,7 +84,10 @@ void insert_rcliques(const OrientedGraph &g, int r, const TableView &T, Counters
                      hipStream_t st);
 // ev0/ev1 (nullable) are recorded around the listing kernels only
 void count_scliques(const OrientedGraph &g, int r, int s, const TableView &T, Counters *dctr,
-                    hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                    unsigned long long *stats, hipStream_t st, hipEvent_t ev0 = nullptr,
+                    hipEvent_t ev1 = nullptr);
+// sum the statistic lines into dctr->decrements, discoveries, n_s (adds)
+void stats_collect(unsigned long long *stats, Counters *dctr, hipStream_t st);
 
 // every triangle (x<y<z) writes key (arc(y,z) << xbits | x) at cursor[x]++
 void list_apex_keys(const OrientedGraph &g, uint64_t *cursor, uint64_t *keys, int xbits,
@@ -114,9 +117,21 @@ void count_direct(const OrientedGraph &g, int r, const TableView &T, const FastI
                   const uint32_t *occ, uint64_t n_r, Counters *dctr, hipStream_t st);
 void peel_round_fast(const OrientedGraph &g, int r, const TableView &T, const FastIndex &fx,
                      const uint32_t *F, uint32_t nF, uint32_t t, uint32_t k, uint32_t *Fnext,
-                     Counters *dctr, hipStream_t st);
+                     Counters *dctr, unsigned long long *stats, hipStream_t st);
 void build_slot_loc(const OrientedGraph &g, int r, const TableView &T, uint64_t n_slots,
                     FastIndex *fx, hipStream_t st);
+// round scratch of the expand/apply peel, grown on demand and kept by the run
+struct SplitBufs {
+  DevBuf<uint64_t> off;  // frontier candidate bounds, then their prefix sum
+  DevBuf<int32_t> fv;    // decoded frontier r-cliques, r ids each
+  DevBuf<int2> rec;      // (frontier index, candidate x or -1)
+};
+// returns the number of candidate records; ev0/ev1 (nullable) bracket the
+// apply kernel
+uint64_t peel_round_split(const OrientedGraph &g, int r, const TableView &T, const FastIndex &fx,
+                          const uint32_t *F, uint32_t nF, uint32_t t, uint32_t k, uint32_t *Fnext,
+                          Counters *dctr, unsigned long long *stats, SplitBufs *sb,
+                          hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
 // r = 3: clear the alive bits of the triangles peeled in this round
 void clear_alive(const OrientedGraph &g, const TableView &T, const FastIndex &fx,
                  const uint32_t *F, uint32_t nF, hipStream_t st);
@@ -125,7 +140,7 @@ void clear_alive(const OrientedGraph &g, const TableView &T, const FastIndex &fx
 void stamp_frontier(const uint32_t *F, uint32_t nF, Slot *slots, uint32_t t, hipStream_t st);
 void peel_round(const OrientedGraph &g, int r, int s, const TableView &T, const uint32_t *F,
                 uint32_t nF, uint32_t t, uint32_t k, uint32_t *Fnext, Counters *dctr,
-                hipStream_t st);
+                unsigned long long *stats, hipStream_t st);
 void live_min(const uint32_t *L, uint32_t nL, const Slot *slots, Counters *dctr,
               hipStream_t st);
 void live_partition(const uint32_t *L, uint32_t nL, const Slot *slots, uint32_t k, uint32_t *F,

@@ -326,4 +326,21 @@ struct Counters {
   uint32_t class_size[8];
 };
 
+
+
+// Statistics accumulated by many waves go to kStatLines counter lines (one
+// 128-byte line each, picked by block index) and are summed once at the
+// end: a single global counter hit by every wave serialises in one L2
+// channel across all XCDs.
+constexpr int kStatLines = 1024;
+constexpr int kStatStride = 16;  // u64 per line
+enum : int { kStatDec = 0, kStatDisc = 1, kStatNs = 2 };
+
+__device__ __forceinline__ void stat_add(unsigned long long *stats, int which, uint64_t v) {
+  const uint64_t t = wave_sum_u64(v);
+  if (lane_id() == 0 && t)
+    atomicAdd(&stats[(blockIdx.x & (kStatLines - 1)) * kStatStride + which],
+              (unsigned long long)t);
+}
+
 }  // namespace nd

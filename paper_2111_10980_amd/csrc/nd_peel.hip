@@ -38,6 +38,7 @@ struct PeelArgs {
   uint32_t t, k;
   uint32_t *Fnext;
   Counters *ctr;
+  unsigned long long *stats;  // kStatLines x kStatStride
 };
 
 struct LaneStats {
@@ -207,11 +208,8 @@ __global__ __launch_bounds__(256) void k_peel(PeelArgs a, const uint32_t *__rest
     }
   }
   ap.flush();
-  uint64_t d = wave_sum_u64(ls.dec), c = wave_sum_u64(ls.disc);
-  if (lane == 0) {
-    if (d) atomicAdd((unsigned long long *)&a.ctr->decrements, (unsigned long long)d);
-    if (c) atomicAdd((unsigned long long *)&a.ctr->discoveries, (unsigned long long)c);
-  }
+  stat_add(a.stats, kStatDec, ls.dec);
+  stat_add(a.stats, kStatDisc, ls.disc);
   if (ls.err) atomicOr(&a.ctr->err, ls.err);
 }
 
@@ -509,11 +507,237 @@ __global__ __launch_bounds__(256) void k_peel_fast(PeelArgs a, FastView fx,
     __builtin_amdgcn_wave_barrier();
   }
   ap.flush();
-  uint64_t dsum = wave_sum_u64(ls.dec), csum = wave_sum_u64(ls.disc);
-  if (lane == 0) {
-    if (dsum) atomicAdd((unsigned long long *)&a.ctr->decrements, (unsigned long long)dsum);
-    if (csum) atomicAdd((unsigned long long *)&a.ctr->discoveries, (unsigned long long)csum);
+  stat_add(a.stats, kStatDec, ls.dec);
+  stat_add(a.stats, kStatDisc, ls.disc);
+  if (ls.err) atomicOr(&a.ctr->err, ls.err);
+}
+
+// ---------------------------------------------- split round (expand/apply)
+// A round of the s = r+1 peel in three passes over the frontier:
+//   bound   thread per r-clique: decode it (slot, first vertex, local
+//           indices) and bound its candidates: popcount of the AND of the
+//           alive rows + length of the shortest apex list;
+//   expand  wave per r-clique: write one record (frontier index, x) per
+//           candidate at the prefix-summed offset, x = -1 where the apex
+//           membership test fails;
+//   apply   thread per record: Update-Func for s-clique R + x, every probe
+//           and decrement of a thread independent of the others.
+// The apply pass carries almost all memory operations of the round with a
+// dependency chain of about five accesses per thread.
+
+template <int R>
+__device__ __forceinline__ bool front_positions(const PeelArgs &a, uint64_t lc,
+                                                const int32_t (&Rv)[R], int64_t o, int d,
+                                                int64_t (&e)[R]) {
+  if (lc >> 63) {
+#pragma unroll
+    for (int i = 1; i < R; i++) e[i] = o + (int64_t)((lc >> (9 * (i - 1))) & 511u);
+    return true;
   }
+  int32_t ys[R - 1];
+  int64_t at[R - 1];
+#pragma unroll
+  for (int i = 1; i < R; i++) ys[i - 1] = Rv[i];
+  lower_bounds<R - 1>(a.g.col, o, o + d, ys, at);
+  bool found = true;
+#pragma unroll
+  for (int i = 1; i < R; i++) {
+    e[i] = at[i - 1];
+    found = found && e[i] < o + d && a.g.col[e[i]] == Rv[i];
+  }
+  return found;
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_expand_bound(PeelArgs a, FastView fx,
+                                                      const uint64_t *__restrict__ loc,
+                                                      const uint32_t *__restrict__ F, uint32_t nF,
+                                                      uint64_t *ub, int32_t *fv) {
+  for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nF;
+       f += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t p = F[f];
+    const Slot sl = a.T.slots[p];
+    int32_t Rv[R];
+    Rv[0] = a.T.v1[p];
+    decode_key<R>(sl.key, a.T.bits, Rv);
+#pragma unroll
+    for (int i = 0; i < R; i++) fv[f * R + i] = Rv[i];
+    uint64_t bound = 0;
+    if (sl.cnt != 0) {  // otherwise every s-clique of R is already gone
+      const int64_t o = a.g.up[Rv[0]];
+      const int d = (int)(a.g.rp[Rv[0] + 1] - o);
+      int64_t e[R];
+      if (front_positions<R>(a, loc[p], Rv, o, d, e)) {
+        uint64_t total1 = 0;
+        if (d <= 512) {
+          const int wd = (d + 63) >> 6;
+          const uint64_t *rows = (R == 3 ? fx.alive : fx.bm) + fx.bm_off[Rv[0]];
+          for (int w = 0; w < wd; w++) {
+            uint64_t x = ~0ull;
+#pragma unroll
+            for (int i = 1; i < R; i++) x &= rows[(e[i] - o) * wd + w];
+            total1 += (uint64_t)__popcll(x);
+          }
+        } else {
+          total1 = (uint64_t)d;
+        }
+        uint64_t len2 = fx.lptr[e[1] + 1] - fx.lptr[e[1]];
+#pragma unroll
+        for (int i = 2; i < R; i++) {
+          const uint64_t len = fx.lptr[e[i] + 1] - fx.lptr[e[i]];
+          len2 = len < len2 ? len : len2;
+        }
+        bound = total1 + len2;
+      } else {
+        atomicOr(&a.ctr->err, kErrLookup);
+      }
+    }
+    ub[f] = bound;
+  }
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_expand(PeelArgs a, FastView fx,
+                                                const uint64_t *__restrict__ loc,
+                                                const uint32_t *__restrict__ F, uint32_t nF,
+                                                const uint64_t *__restrict__ off,
+                                                const int32_t *__restrict__ fv, int2 *rec) {
+  const int wpb = blockDim.x / kWave;
+  const int wv = threadIdx.x / kWave;
+  const int lane = lane_id();
+  __shared__ int32_t lbuf[256 / kWave][R == 3 ? kListCap : 1];
+  for (int64_t f = (int64_t)blockIdx.x * wpb + wv; f < nF; f += (int64_t)gridDim.x * wpb) {
+    const uint64_t b = off[f];
+    const uint64_t total = off[f + 1] - b;
+    if (total == 0) continue;
+    const uint32_t p = F[f];
+    int32_t Rv[R];
+#pragma unroll
+    for (int i = 0; i < R; i++) Rv[i] = fv[f * R + i];
+    const int32_t v1 = Rv[0];
+    const int64_t o = a.g.up[v1];
+    const int d = (int)(a.g.rp[v1 + 1] - o);
+    int64_t e[R];
+    front_positions<R>(a, loc[p], Rv, o, d, e);  // found: the bound pass checked it
+    const bool has_bm = d <= 512;
+    uint32_t total1, iw[8];
+    uint64_t cw = 0;
+    if (has_bm) {
+      const int wd = (d + 63) >> 6;
+      const uint64_t *rows = (R == 3 ? fx.alive : fx.bm) + fx.bm_off[v1];
+      if (lane < wd) {
+        cw = ~0ull;
+#pragma unroll
+        for (int i = 1; i < R; i++) cw &= rows[(e[i] - o) * wd + lane];
+      }
+      const uint32_t incl = wave_incl_scan((uint32_t)__popcll(cw));
+      total1 = __shfl(incl, kWave - 1);
+#pragma unroll
+      for (int q = 0; q < 8; q++) iw[q] = __shfl(incl, q);
+    } else {
+      total1 = (uint32_t)d;
+#pragma unroll
+      for (int q = 0; q < 8; q++) iw[q] = 0;
+    }
+    int drv = 1;
+    uint64_t len2 = fx.lptr[e[1] + 1] - fx.lptr[e[1]];
+#pragma unroll
+    for (int i = 2; i < R; i++) {
+      const uint64_t len = fx.lptr[e[i] + 1] - fx.lptr[e[i]];
+      if (len < len2) {
+        len2 = len;
+        drv = i;
+      }
+    }
+    const uint64_t lb = fx.lptr[e[drv]];
+    int staged_len = -1;
+    uint64_t ob = 0, oe = 0;
+    if constexpr (R == 3) {
+      const int other = drv == 1 ? 2 : 1;
+      ob = fx.lptr[e[other]];
+      oe = fx.lptr[e[other] + 1];
+      if (len2 > 0 && oe - ob <= (uint64_t)kListCap) {
+        staged_len = (int)(oe - ob);
+        for (int i = lane; i < staged_len; i += kWave) lbuf[wv][i] = fx.lval[ob + i];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    for (uint64_t base = 0; base < total; base += kWave) {
+      const uint64_t k = base + lane;
+      bool in = k < total;
+      int32_t x = 0;
+      const uint32_t kk = k < total1 ? (uint32_t)k : 0u;
+      int w = 0;
+      uint32_t before = 0;
+#pragma unroll
+      for (int q = 0; q < 7; q++) {
+        if (iw[q] <= kk) {
+          w = q + 1;
+          before = iw[q];
+        }
+      }
+      const uint64_t wordw = __shfl(cw, w);
+      if (in && k < total1) {
+        if (has_bm) {
+          uint64_t m = wordw;
+          for (uint32_t q = 0; q < kk - before; q++) m &= m - 1;
+          x = a.g.col[o + w * 64 + (__ffsll((unsigned long long)m) - 1)];
+        } else {
+          x = a.g.col[o + (int64_t)k];
+#pragma unroll
+          for (int i = 1; i < R; i++) in = in && adjacent(a.g, x, Rv[i]);
+        }
+      } else if (in) {
+        x = fx.lval[lb + (k - total1)];
+        if constexpr (R == 3) {
+          in = staged_len >= 0 ? lds_contains(lbuf[wv], staged_len, x)
+                               : sorted_contains(fx.lval, ob, oe, x);
+        } else {
+#pragma unroll
+          for (int i = 1; i < R; i++)
+            if (i != drv)
+              in = in && sorted_contains(fx.lval, fx.lptr[e[i]], fx.lptr[e[i] + 1], x);
+        }
+      }
+      if (k < total) rec[b + k] = make_int2((int)f, in ? x : -1);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_apply(PeelArgs a, const int2 *__restrict__ rec,
+                                               uint64_t total, const uint32_t *__restrict__ F,
+                                               const int32_t *__restrict__ fv) {
+  const int wv = threadIdx.x / kWave;
+  const int lane = lane_id();
+  LaneStats ls;
+  __shared__ uint32_t abuf[256 / kWave][kAppendCap];
+  Appender ap{abuf[wv], 0u, a.Fnext, &a.ctr->next_size};
+  // wave-uniform trip count: every lane reaches every append
+  for (uint64_t base = ((uint64_t)blockIdx.x * blockDim.x) + (uint64_t)wv * kWave; base < total;
+       base += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t i = base + lane;
+    bool in = i < total;
+    int2 rc = make_int2(0, -1);
+    if (in) rc = rec[i];
+    in = in && rc.y >= 0;
+    int32_t Rv[R];
+    uint32_t p = 0;
+    if (in) {
+      p = F[rc.x];
+#pragma unroll
+      for (int q = 0; q < R; q++) Rv[q] = fv[(int64_t)rc.x * R + q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < R; q++) Rv[q] = q;
+    }
+    peel_candidate<R>(a, Rv, in ? rc.y : R, in, p, ls, &ap);
+  }
+  ap.flush();
+  stat_add(a.stats, kStatDec, ls.dec);
+  stat_add(a.stats, kStatDisc, ls.disc);
   if (ls.err) atomicOr(&a.ctr->err, ls.err);
 }
 
@@ -699,9 +923,9 @@ void stamp_frontier(const uint32_t *F, uint32_t nF, Slot *slots, uint32_t t, hip
 
 void peel_round(const OrientedGraph &g, int r, int s, const TableView &T, const uint32_t *F,
                 uint32_t nF, uint32_t t, uint32_t k, uint32_t *Fnext, Counters *dctr,
-                hipStream_t st) {
+                unsigned long long *stats, hipStream_t st) {
   if (!nF) return;
-  PeelArgs a{g.view(), T, t, k, Fnext, dctr};
+  PeelArgs a{g.view(), T, t, k, Fnext, dctr, stats};
   switch (r * 16 + s) {
     ND_PEEL_CASE(1, 2) ND_PEEL_CASE(1, 3) ND_PEEL_CASE(1, 4) ND_PEEL_CASE(1, 5)
     ND_PEEL_CASE(1, 6) ND_PEEL_CASE(1, 7)
@@ -733,9 +957,9 @@ void count_direct(const OrientedGraph &g, int r, const TableView &T, const FastI
 
 void peel_round_fast(const OrientedGraph &g, int r, const TableView &T, const FastIndex &fx,
                      const uint32_t *F, uint32_t nF, uint32_t t, uint32_t k, uint32_t *Fnext,
-                     Counters *dctr, hipStream_t st) {
+                     Counters *dctr, unsigned long long *stats, hipStream_t st) {
   if (!nF) return;
-  PeelArgs a{g.view(), T, t, k, Fnext, dctr};
+  PeelArgs a{g.view(), T, t, k, Fnext, dctr, stats};
   const FastView fv = fx.view();
   const uint64_t *loc = fx.loc.get();
   dim3 grid((unsigned)grid_for(nF, 4, 1 << 20)), blk(256);
@@ -747,6 +971,57 @@ void peel_round_fast(const OrientedGraph &g, int r, const TableView &T, const Fa
     case 6: hipLaunchKernelGGL(k_peel_fast<6>, grid, blk, 0, st, a, fv, loc, F, nF); break;
     default: break;
   }
+}
+
+template <int R>
+float split_impl(const PeelArgs &a, const FastIndex &fx, const uint32_t *F, uint32_t nF,
+                 SplitBufs *sb, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  const FastView fv = fx.view();
+  const uint64_t *loc = fx.loc.get();
+  if (sb->off.n < (size_t)nF + 1) sb->off.reset((size_t)nF + 1 + nF / 2);
+  if (sb->fv.n < (size_t)nF * R) sb->fv.reset(((size_t)nF + nF / 2) * R);
+  hipLaunchKernelGGL(k_expand_bound<R>, dim3((unsigned)grid_for(nF, 256)), dim3(256), 0, st, a, fv,
+                     loc, F, nF, sb->off.get(), sb->fv.get());
+  fill_u64(sb->off.get() + nF, 0, 1, st);
+  scan_exclusive_u64(sb->off.get(), sb->off.get(), (int64_t)nF + 1, st);
+  uint64_t total = 0;
+  hipMemcpyAsync(&total, sb->off.get() + nF, 8, hipMemcpyDeviceToHost, st);
+  hipStreamSynchronize(st);
+  if (total == 0) {  // keep the event pair consistent for the caller's timing
+    if (ev0) hipEventRecord(ev0, st);
+    if (ev1) hipEventRecord(ev1, st);
+    return 0.f;
+  }
+  if (sb->rec.n < total) sb->rec.reset(total + total / 2);
+  hipLaunchKernelGGL(k_expand<R>, dim3((unsigned)grid_for(nF, 4, 1 << 20)), dim3(256), 0, st, a,
+                     fv, loc, F, nF, sb->off.get(), sb->fv.get(), sb->rec.get());
+  if (ev0) hipEventRecord(ev0, st);
+  hipLaunchKernelGGL(k_apply<R>, dim3((unsigned)grid_for(total, 256, 1 << 16)), dim3(256), 0, st, a,
+                     sb->rec.get(), total, F, sb->fv.get());
+  if (ev1) hipEventRecord(ev1, st);
+  return (float)total;
+}
+
+uint64_t peel_round_split(const OrientedGraph &g, int r, const TableView &T, const FastIndex &fx,
+                          const uint32_t *F, uint32_t nF, uint32_t t, uint32_t k, uint32_t *Fnext,
+                          Counters *dctr, unsigned long long *stats, SplitBufs *sb,
+                          hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  if (!nF) {
+    if (ev0) hipEventRecord(ev0, st);
+    if (ev1) hipEventRecord(ev1, st);
+    return 0;
+  }
+  PeelArgs a{g.view(), T, t, k, Fnext, dctr, stats};
+  float tot = 0;
+  switch (r) {
+    case 2: tot = split_impl<2>(a, fx, F, nF, sb, st, ev0, ev1); break;
+    case 3: tot = split_impl<3>(a, fx, F, nF, sb, st, ev0, ev1); break;
+    case 4: tot = split_impl<4>(a, fx, F, nF, sb, st, ev0, ev1); break;
+    case 5: tot = split_impl<5>(a, fx, F, nF, sb, st, ev0, ev1); break;
+    case 6: tot = split_impl<6>(a, fx, F, nF, sb, st, ev0, ev1); break;
+    default: break;
+  }
+  return (uint64_t)tot;
 }
 
 void build_slot_loc(const OrientedGraph &g, int r, const TableView &T, uint64_t n_slots,
