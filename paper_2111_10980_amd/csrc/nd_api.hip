@@ -71,6 +71,9 @@ struct StreamScope {
   ~StreamScope() { g_stream = prev; }
 };
 
+// levels covered by the window list of the bucket structure
+constexpr uint32_t kWindowLevels = 16;
+
 int64_t grid_for(int64_t n, int threads, int64_t cap = 65536) {
   int64_t b = (n + threads - 1) / threads;
   if (b < 1) b = 1;
@@ -407,29 +410,54 @@ nd_status nd_run(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *cou
     }
     tm.mark(1, st);
     // ---- bucket init + peel
-    DevBuf<uint32_t> F(p->n_r ? p->n_r : 1), Fn(p->n_r ? p->n_r : 1), L(p->n_r ? p->n_r : 1),
-        L2(p->n_r ? p->n_r : 1);
+    // Live r-cliques are kept in two lists: Lw (count <= kw, the level
+    // window) and Lh (count > kw).  A level advance scans only Lw; Lh is
+    // re-partitioned only when the window holds no live entry.  Decrements
+    // that bring a count to kw append the r-clique to Lw, so Lw always
+    // holds every live r-clique with count <= kw.
+    const size_t cap = p->n_r ? p->n_r : 1;
+    DevBuf<uint32_t> F(cap), Fn(cap), Lh(cap), Lh2(cap), Lw(cap), Lw2(cap);
     if (p->n_r)
-      hip_check(hipMemcpyAsync(L.get(), p->occ.get(), 4 * p->n_r, hipMemcpyDeviceToDevice, st),
+      hip_check(hipMemcpyAsync(Lh.get(), p->occ.get(), 4 * p->n_r, hipMemcpyDeviceToDevice, st),
                 "copy");
     SplitBufs sb;
-    uint64_t nL = p->n_r, finished = 0;
-    uint32_t k = 0, t = 0, nF = 0;
+    uint64_t nH = p->n_r, nW = 0, finished = 0;
+    uint32_t k = 0, kw = 0, t = 0, nF = 0;
     p->round_sizes.clear();
     p->round_k.clear();
     p->k_advances = 0;
     bool first = true;
     while (finished < p->n_r) {
       if (nF == 0) {
-        live_min(L.get(), (uint32_t)nL, p->slots.get(), dc, st);
-        uint32_t m = read_dev(&dc->live_min, st);
-        if (m == 0xFFFFFFFFu) fail(ND_EHIP, "no live r-clique left before the peel finished");
-        if (m > k) k = m;
-        live_partition(L.get(), (uint32_t)nL, p->slots.get(), k, F.get(), L2.get(), dc, st);
-        Counters h2 = read_dev(dc, st);
-        nF = h2.next_size;
-        nL = h2.live_size;
-        std::swap(L.p, L2.p);
+        bool advanced = false;
+        if (nW > 0) {  // next level inside the window
+          live_min(Lw.get(), (uint32_t)nW, p->slots.get(), dc, st);
+          const uint32_t m = read_dev(&dc->live_min, st);
+          if (m != 0xFFFFFFFFu) {
+            if (m > k) k = m;
+            live_partition(Lw.get(), (uint32_t)nW, p->slots.get(), k, 0xFFFFFFFEu, F.get(),
+                           Lw2.get(), Lh2.get(), dc, st);
+            const Counters h2 = read_dev(dc, st);
+            nF = h2.next_size;
+            nW = h2.low_size;
+            std::swap(Lw.p, Lw2.p);
+            advanced = true;
+          }
+        }
+        if (!advanced) {  // window exhausted: open a new one from the high list
+          live_min(Lh.get(), (uint32_t)nH, p->slots.get(), dc, st);
+          const uint32_t m = read_dev(&dc->live_min, st);
+          if (m == 0xFFFFFFFFu) fail(ND_EHIP, "no live r-clique left before the peel finished");
+          if (m > k) k = m;
+          kw = k + kWindowLevels;
+          live_partition(Lh.get(), (uint32_t)nH, p->slots.get(), k, kw, F.get(), Lw.get(),
+                         Lh2.get(), dc, st);
+          const Counters h2 = read_dev(dc, st);
+          nF = h2.next_size;
+          nW = h2.low_size;
+          nH = h2.high_size;
+          std::swap(Lh.p, Lh2.p);
+        }
         p->k_advances++;
         if (first) tm.mark(2, st);
         first = false;
@@ -437,20 +465,26 @@ nd_status nd_run(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *cou
       }
       stamp_frontier(F.get(), nF, p->slots.get(), t, st);
       fill_u32(&dc->next_size, 0, 1, st);
+      fill_u32(&dc->low_size, (uint32_t)nW, 1, st);  // window appends continue after nW
       if (p->fast) {
-        peel_round_split(p->g, r, p->table(), p->fx, F.get(), nF, t, k, Fn.get(), dc,
-                         p->stats.get(), &sb, st, timing ? kt.ev[2] : nullptr,
+        peel_round_split(p->g, r, p->table(), p->fx, F.get(), nF, t, k, kw, Fn.get(), Lw.get(),
+                         dc, p->stats.get(), &sb, st, timing ? kt.ev[2] : nullptr,
                          timing ? kt.ev[3] : nullptr);
       } else {
         if (timing) kt.mark(2, st);
-        peel_round(p->g, r, s, p->table(), F.get(), nF, t, k, Fn.get(), dc, p->stats.get(), st);
+        peel_round(p->g, r, s, p->table(), F.get(), nF, t, k, kw, Fn.get(), Lw.get(), dc,
+                   p->stats.get(), st);
         if (timing) kt.mark(3, st);
       }
       if (p->fast && r == 3) clear_alive(p->g, p->table(), p->fx, F.get(), nF, st);
       p->round_sizes.push_back(nF);
       p->round_k.push_back(k);
       finished += nF;
-      nF = read_dev(&dc->next_size, st);
+      {
+        const Counters h3 = read_dev(dc, st);
+        nF = h3.next_size;
+        nW = h3.low_size;
+      }
       if (timing) {
         peel_kernel_ms += kt.between(2, 3);
         peel_launches++;

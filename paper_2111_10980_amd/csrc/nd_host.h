@@ -115,9 +115,6 @@ void build_fast_index(const OrientedGraph &g, FastIndex *fx, Counters *dctr, hip
 // count(R) = |common neighbourhood of R| written straight into each slot
 void count_direct(const OrientedGraph &g, int r, const TableView &T, const FastIndex &fx,
                   const uint32_t *occ, uint64_t n_r, Counters *dctr, hipStream_t st);
-void peel_round_fast(const OrientedGraph &g, int r, const TableView &T, const FastIndex &fx,
-                     const uint32_t *F, uint32_t nF, uint32_t t, uint32_t k, uint32_t *Fnext,
-                     Counters *dctr, unsigned long long *stats, hipStream_t st);
 void build_slot_loc(const OrientedGraph &g, int r, const TableView &T, uint64_t n_slots,
                     FastIndex *fx, hipStream_t st);
 // round scratch of the expand/apply peel, grown on demand and kept by the run
@@ -128,10 +125,12 @@ struct SplitBufs {
 };
 // returns the number of candidate records; ev0/ev1 (nullable) bracket the
 // apply kernel
+// Fnext receives r-cliques reaching level k, Low those entering (k, kw]
 uint64_t peel_round_split(const OrientedGraph &g, int r, const TableView &T, const FastIndex &fx,
-                          const uint32_t *F, uint32_t nF, uint32_t t, uint32_t k, uint32_t *Fnext,
-                          Counters *dctr, unsigned long long *stats, SplitBufs *sb,
-                          hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
+                          const uint32_t *F, uint32_t nF, uint32_t t, uint32_t k, uint32_t kw,
+                          uint32_t *Fnext, uint32_t *Low, Counters *dctr,
+                          unsigned long long *stats, SplitBufs *sb, hipStream_t st,
+                          hipEvent_t ev0, hipEvent_t ev1);
 // r = 3: clear the alive bits of the triangles peeled in this round
 void clear_alive(const OrientedGraph &g, const TableView &T, const FastIndex &fx,
                  const uint32_t *F, uint32_t nF, hipStream_t st);
@@ -139,12 +138,13 @@ void clear_alive(const OrientedGraph &g, const TableView &T, const FastIndex &fx
 // ---- peel (nd_peel.hip)
 void stamp_frontier(const uint32_t *F, uint32_t nF, Slot *slots, uint32_t t, hipStream_t st);
 void peel_round(const OrientedGraph &g, int r, int s, const TableView &T, const uint32_t *F,
-                uint32_t nF, uint32_t t, uint32_t k, uint32_t *Fnext, Counters *dctr,
-                unsigned long long *stats, hipStream_t st);
+                uint32_t nF, uint32_t t, uint32_t k, uint32_t kw, uint32_t *Fnext, uint32_t *Low,
+                Counters *dctr, unsigned long long *stats, hipStream_t st);
 void live_min(const uint32_t *L, uint32_t nL, const Slot *slots, Counters *dctr,
               hipStream_t st);
-void live_partition(const uint32_t *L, uint32_t nL, const Slot *slots, uint32_t k, uint32_t *F,
-                    uint32_t *Lout, Counters *dctr, hipStream_t st);
+// F: count <= k; Low: k < count <= kw; High: count > kw (peeled entries dropped)
+void live_partition(const uint32_t *L, uint32_t nL, const Slot *slots, uint32_t k, uint32_t kw,
+                    uint32_t *F, uint32_t *Low, uint32_t *High, Counters *dctr, hipStream_t st);
 void occupied_list(const Slot *slots, uint64_t n_slots, uint32_t *occ, hipStream_t st);
 void gather_counts(const uint32_t *occ, uint64_t n_r, const Slot *slots, uint32_t *out,
                    hipStream_t st);

@@ -324,6 +324,8 @@ struct Counters {
   uint32_t live_min;     // minimum live count (k-advance)
   uint32_t live_size;    // size of the compacted live list
   uint32_t class_size[8];
+  uint32_t low_size;     // size of the level-window list
+  uint32_t high_size;    // size of the list above the window
 };
 
 

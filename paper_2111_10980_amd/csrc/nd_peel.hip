@@ -39,6 +39,8 @@ struct PeelArgs {
   uint32_t *Fnext;
   Counters *ctr;
   unsigned long long *stats;  // kStatLines x kStatStride
+  uint32_t kw;                // top of the level window (> k), or 0: no window
+  uint32_t *Low;              // r-cliques whose count fell to kw (window list)
 };
 
 struct LaneStats {
@@ -95,17 +97,20 @@ __device__ __forceinline__ void update_func(const PeelArgs &a, const int32_t (&S
   const bool mine = alive && owner == p;
 #pragma unroll
   for (int q = 0; q < N; q++) {
-    bool want_append = false;
+    bool want_append = false, want_low = false;
     if (mine && live[q]) {
       uint32_t old = __hip_atomic_fetch_add(&a.T.slots[pos[q]].cnt, 0xFFFFFFFFu, __ATOMIC_RELAXED,
                                             __HIP_MEMORY_SCOPE_AGENT);
       ls.dec++;
-      want_append = old == a.k + 1;
+      want_append = old == a.k + 1;              // reaches this round's level
+      want_low = a.kw > a.k && old == a.kw + 1;  // enters the level window
     }
     if constexpr (kConvergent) {
-      ap->push(want_append, (uint32_t)pos[q]);
-    } else if (want_append) {
-      a.Fnext[atomicAdd(&a.ctr->next_size, 1u)] = (uint32_t)pos[q];
+      ap[0].push(want_append, (uint32_t)pos[q]);
+      ap[1].push(want_low, (uint32_t)pos[q]);
+    } else {
+      if (want_append) a.Fnext[atomicAdd(&a.ctr->next_size, 1u)] = (uint32_t)pos[q];
+      if (want_low) a.Low[atomicAdd(&a.ctr->low_size, 1u)] = (uint32_t)pos[q];
     }
   }
 }
@@ -153,8 +158,9 @@ __global__ __launch_bounds__(256) void k_peel(PeelArgs a, const uint32_t *__rest
   const int wpb = blockDim.x / kWave;
   const int lane = lane_id();
   LaneStats ls;
-  __shared__ uint32_t abuf[256 / kWave][kAppendCap];
-  Appender ap{abuf[threadIdx.x / kWave], 0u, a.Fnext, &a.ctr->next_size};
+  __shared__ uint32_t abuf[256 / kWave][2][kAppendCap];
+  Appender ap[2] = {{abuf[threadIdx.x / kWave][0], 0u, a.Fnext, &a.ctr->next_size},
+                    {abuf[threadIdx.x / kWave][1], 0u, a.Low, &a.ctr->low_size}};
   for (int64_t it = (int64_t)blockIdx.x * wpb + threadIdx.x / kWave; it < nF;
        it += (int64_t)gridDim.x * wpb) {
     const uint32_t p = F[it];
@@ -197,7 +203,7 @@ __global__ __launch_bounds__(256) void k_peel(PeelArgs a, const uint32_t *__rest
             rmask |= 1u << o;
           }
         }
-        update_func<R, S, true>(a, Sv, rmask, p, in, ls, &ap);
+        update_func<R, S, true>(a, Sv, rmask, p, in, ls, ap);
       } else {
         if (in) {
           int32_t Q[S - R];
@@ -207,7 +213,8 @@ __global__ __launch_bounds__(256) void k_peel(PeelArgs a, const uint32_t *__rest
       }
     }
   }
-  ap.flush();
+  ap[0].flush();
+  ap[1].flush();
   stat_add(a.stats, kStatDec, ls.dec);
   stat_add(a.stats, kStatDisc, ls.disc);
   if (ls.err) atomicOr(&a.ctr->err, ls.err);
@@ -353,12 +360,6 @@ __device__ __forceinline__ void peel_candidate(const PeelArgs &a, const int32_t 
   update_func<R, S, true>(a, Sv, rmask, p, in, ls, ap);
 }
 
-// One wave per peeled r-clique.  The critical path is kept short: the
-// local indices of v2..vr in N+(v1) come from `loc` (no search), the
-// candidates x > v1 (set bits of the AND of v1's alive rows) and x < v1
-// (the shortest apex list, membership in the other list tested in LDS) are
-// handed out in a single lane-parallel pass, and each candidate's r-subsets
-// are probed together.
 constexpr int kListCap = 1024;  // LDS entries per wave for a staged apex list
 
 __device__ __forceinline__ bool lds_contains(const int32_t *a, int n, int32_t x) {
@@ -371,145 +372,6 @@ __device__ __forceinline__ bool lds_contains(const int32_t *a, int n, int32_t x)
     else hi = mid;
   }
   return false;
-}
-
-template <int R>
-__global__ __launch_bounds__(256) void k_peel_fast(PeelArgs a, FastView fx,
-                                                   const uint64_t *__restrict__ loc,
-                                                   const uint32_t *__restrict__ F, uint32_t nF) {
-  const int wpb = blockDim.x / kWave;
-  const int wv = threadIdx.x / kWave;
-  const int lane = lane_id();
-  LaneStats ls;
-  __shared__ uint32_t abuf[256 / kWave][kAppendCap];
-  __shared__ int32_t lbuf[256 / kWave][R == 3 ? kListCap : 1];
-  Appender ap{abuf[wv], 0u, a.Fnext, &a.ctr->next_size};
-  for (int64_t it = (int64_t)blockIdx.x * wpb + wv; it < nF; it += (int64_t)gridDim.x * wpb) {
-    const uint32_t p = F[it];
-    const Slot sl = a.T.slots[p];
-    if (sl.cnt == 0) continue;  // every s-clique of R is already gone
-    int32_t Rv[R];
-    Rv[0] = a.T.v1[p];
-    const uint64_t lc = loc[p];
-    decode_key<R>(sl.key, a.T.bits, Rv);
-    const int32_t v1 = Rv[0];
-    const int64_t o = a.g.up[v1];
-    const int d = (int)(a.g.rp[v1 + 1] - o);
-    int64_t e[R];
-    if (lc >> 63) {
-#pragma unroll
-      for (int i = 1; i < R; i++) e[i] = o + (int64_t)((lc >> (9 * (i - 1))) & 511u);
-    } else {
-      int32_t ys[R - 1];
-      int64_t at[R - 1];
-      bool found = true;
-#pragma unroll
-      for (int i = 1; i < R; i++) ys[i - 1] = Rv[i];
-      lower_bounds<R - 1>(a.g.col, o, o + d, ys, at);
-#pragma unroll
-      for (int i = 1; i < R; i++) {
-        e[i] = at[i - 1];
-        found = found && e[i] < o + d && a.g.col[e[i]] == Rv[i];
-      }
-      if (!found) {  // wave-uniform
-        ls.err |= kErrLookup;
-        continue;
-      }
-    }
-    // ---- x > v1: set bits of the AND of the (alive) rows of v2..vr
-    const bool has_bm = d <= 512;
-    uint32_t total1, iw[8];
-    uint64_t cw = 0;
-    if (has_bm) {
-      const int wd = (d + 63) >> 6;
-      const uint64_t *rows = (R == 3 ? fx.alive : fx.bm) + fx.bm_off[v1];
-      if (lane < wd) {
-        cw = ~0ull;
-#pragma unroll
-        for (int i = 1; i < R; i++) cw &= rows[(e[i] - o) * wd + lane];
-      }
-      const uint32_t incl = wave_incl_scan((uint32_t)__popcll(cw));
-      total1 = __shfl(incl, kWave - 1);
-#pragma unroll
-      for (int q = 0; q < 8; q++) iw[q] = __shfl(incl, q);
-    } else {
-      total1 = (uint32_t)d;  // heavy root: every out-neighbour, edge-tested
-#pragma unroll
-      for (int q = 0; q < 8; q++) iw[q] = 0;
-    }
-    // ---- x < v1: the shortest apex list; membership in the others
-    int drv = 1;
-    uint64_t len2 = fx.lptr[e[1] + 1] - fx.lptr[e[1]];
-#pragma unroll
-    for (int i = 2; i < R; i++) {
-      const uint64_t len = fx.lptr[e[i] + 1] - fx.lptr[e[i]];
-      if (len < len2) {
-        len2 = len;
-        drv = i;
-      }
-    }
-    const uint64_t lb = fx.lptr[e[drv]];
-    int staged_len = -1;
-    uint64_t ob = 0, oe = 0;
-    if constexpr (R == 3) {
-      const int other = drv == 1 ? 2 : 1;
-      ob = fx.lptr[e[other]];
-      oe = fx.lptr[e[other] + 1];
-      if (len2 > 0 && oe - ob <= (uint64_t)kListCap) {
-        staged_len = (int)(oe - ob);
-        for (int i = lane; i < staged_len; i += kWave) lbuf[wv][i] = fx.lval[ob + i];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-      }
-    }
-    const uint64_t total = (uint64_t)total1 + len2;
-    for (uint64_t base = 0; base < total; base += kWave) {
-      const uint64_t k = base + lane;
-      bool in = k < total;
-      int32_t x = 0;
-      // word of v1's bitmap holding part-1 candidate k (computed by every
-      // lane so the shuffle runs with the whole wave active)
-      const uint32_t kk = k < total1 ? (uint32_t)k : 0u;
-      int w = 0;
-      uint32_t before = 0;
-#pragma unroll
-      for (int q = 0; q < 7; q++) {
-        if (iw[q] <= kk) {
-          w = q + 1;
-          before = iw[q];
-        }
-      }
-      const uint64_t wordw = __shfl(cw, w);
-      if (in && k < total1) {
-        if (has_bm) {
-          uint64_t m = wordw;
-          for (uint32_t q = 0; q < kk - before; q++) m &= m - 1;
-          x = a.g.col[o + w * 64 + (__ffsll((unsigned long long)m) - 1)];
-        } else {
-          x = a.g.col[o + (int64_t)k];
-#pragma unroll
-          for (int i = 1; i < R; i++) in = in && adjacent(a.g, x, Rv[i]);
-        }
-      } else if (in) {
-        x = fx.lval[lb + (k - total1)];
-        if constexpr (R == 3) {
-          in = staged_len >= 0 ? lds_contains(lbuf[wv], staged_len, x)
-                               : sorted_contains(fx.lval, ob, oe, x);
-        } else {
-#pragma unroll
-          for (int i = 1; i < R; i++)
-            if (i != drv)
-              in = in && sorted_contains(fx.lval, fx.lptr[e[i]], fx.lptr[e[i] + 1], x);
-        }
-      }
-      peel_candidate<R>(a, Rv, x, in, p, ls, &ap);
-    }
-    __builtin_amdgcn_wave_barrier();
-  }
-  ap.flush();
-  stat_add(a.stats, kStatDec, ls.dec);
-  stat_add(a.stats, kStatDisc, ls.disc);
-  if (ls.err) atomicOr(&a.ctr->err, ls.err);
 }
 
 // ---------------------------------------------- split round (expand/apply)
@@ -713,8 +575,9 @@ __global__ __launch_bounds__(256) void k_apply(PeelArgs a, const int2 *__restric
   const int wv = threadIdx.x / kWave;
   const int lane = lane_id();
   LaneStats ls;
-  __shared__ uint32_t abuf[256 / kWave][kAppendCap];
-  Appender ap{abuf[wv], 0u, a.Fnext, &a.ctr->next_size};
+  __shared__ uint32_t abuf[256 / kWave][2][kAppendCap];
+  Appender ap[2] = {{abuf[wv][0], 0u, a.Fnext, &a.ctr->next_size},
+                    {abuf[wv][1], 0u, a.Low, &a.ctr->low_size}};
   // wave-uniform trip count: every lane reaches every append
   for (uint64_t base = ((uint64_t)blockIdx.x * blockDim.x) + (uint64_t)wv * kWave; base < total;
        base += (uint64_t)gridDim.x * blockDim.x) {
@@ -733,12 +596,101 @@ __global__ __launch_bounds__(256) void k_apply(PeelArgs a, const int2 *__restric
 #pragma unroll
       for (int q = 0; q < R; q++) Rv[q] = q;
     }
-    peel_candidate<R>(a, Rv, in ? rc.y : R, in, p, ls, &ap);
+    peel_candidate<R>(a, Rv, in ? rc.y : R, in, p, ls, ap);
   }
-  ap.flush();
+  ap[0].flush();
+  ap[1].flush();
   stat_add(a.stats, kStatDec, ls.dec);
   stat_add(a.stats, kStatDisc, ls.disc);
   if (ls.err) atomicOr(&a.ctr->err, ls.err);
+}
+
+// Direct count, one wave per r-clique (r >= 3): the part x > v1 is a
+// popcount of the AND of v1's bitmap rows; the part x < v1 is the
+// intersection of the apex lists, the shortest one split across the lanes
+// and the other (r = 3) staged in LDS.
+template <int R>
+__global__ __launch_bounds__(256) void k_count_wave(PeelArgs a, FastView fx,
+                                                    const uint64_t *__restrict__ loc,
+                                                    const uint32_t *__restrict__ occ, uint64_t n_r) {
+  const int wpb = blockDim.x / kWave;
+  const int wv = threadIdx.x / kWave;
+  const int lane = lane_id();
+  __shared__ int32_t lbuf[256 / kWave][R == 3 ? kListCap : 1];
+  for (int64_t it = (int64_t)blockIdx.x * wpb + wv; it < (int64_t)n_r;
+       it += (int64_t)gridDim.x * wpb) {
+    const uint32_t p = occ[it];
+    const Slot sl = a.T.slots[p];
+    int32_t Rv[R];
+    Rv[0] = a.T.v1[p];
+    decode_key<R>(sl.key, a.T.bits, Rv);
+    const int64_t o = a.g.up[Rv[0]];
+    const int d = (int)(a.g.rp[Rv[0] + 1] - o);
+    int64_t e[R];
+    if (!front_positions<R>(a, loc[p], Rv, o, d, e)) {  // wave-uniform
+      if (lane == 0) atomicOr(&a.ctr->err, kErrLookup);
+      continue;
+    }
+    uint32_t c = 0;
+    if (d <= 512) {
+      const int wd = (d + 63) >> 6;
+      const uint64_t *rows = fx.bm + fx.bm_off[Rv[0]];
+      if (lane < wd) {
+        uint64_t x = ~0ull;
+#pragma unroll
+        for (int i = 1; i < R; i++) x &= rows[(e[i] - o) * wd + lane];
+        c = (uint32_t)__popcll(x);
+      }
+    } else {
+      for (int64_t j = o + lane; j < o + d; j += kWave) {
+        const int32_t y = a.g.col[j];
+        bool ok = true;
+#pragma unroll
+        for (int i = 1; i < R; i++) ok = ok && adjacent(a.g, y, Rv[i]);
+        c += ok ? 1u : 0u;
+      }
+    }
+    int drv = 1;
+    uint64_t len2 = fx.lptr[e[1] + 1] - fx.lptr[e[1]];
+#pragma unroll
+    for (int i = 2; i < R; i++) {
+      const uint64_t len = fx.lptr[e[i] + 1] - fx.lptr[e[i]];
+      if (len < len2) {
+        len2 = len;
+        drv = i;
+      }
+    }
+    const uint64_t lb = fx.lptr[e[drv]];
+    int staged_len = -1;
+    uint64_t ob = 0, oe = 0;
+    if constexpr (R == 3) {
+      const int other = drv == 1 ? 2 : 1;
+      ob = fx.lptr[e[other]];
+      oe = fx.lptr[e[other] + 1];
+      if (len2 > 0 && oe - ob <= (uint64_t)kListCap) {
+        staged_len = (int)(oe - ob);
+        for (int i = lane; i < staged_len; i += kWave) lbuf[wv][i] = fx.lval[ob + i];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    for (uint64_t j = lane; j < len2; j += kWave) {
+      const int32_t x = fx.lval[lb + j];
+      bool in = true;
+      if constexpr (R == 3) {
+        in = staged_len >= 0 ? lds_contains(lbuf[wv], staged_len, x)
+                             : sorted_contains(fx.lval, ob, oe, x);
+      } else {
+#pragma unroll
+        for (int i = 1; i < R; i++)
+          if (i != drv) in = in && sorted_contains(fx.lval, fx.lptr[e[i]], fx.lptr[e[i] + 1], x);
+      }
+      c += in ? 1u : 0u;
+    }
+    const uint64_t total = wave_sum_u64(c);
+    if (lane == 0) a.T.slots[p].cnt = (uint32_t)total;
+    __builtin_amdgcn_wave_barrier();
+  }
 }
 
 // Local indices of v2..vr in N+(v1) for every occupied slot of a bitmap
@@ -794,22 +746,25 @@ __global__ __launch_bounds__(256) void k_live_min(const uint32_t *__restrict__ L
   if (lane_id() == 0 && m != 0xFFFFFFFFu) atomicMin(out, m);
 }
 
-// Partition of the live list into this level's frontier and the rest.
-// Each block compacts a tile of 256 x 16 entries with one atomic per output
-// per tile (a single global counter per wave would serialise in L2).
+// Three-way partition of a list of live r-clique slots by count c:
+// c <= k -> F (this level's frontier), k < c <= kw -> Low (level window),
+// c > kw -> High; peeled entries are dropped.  Each block compacts a tile
+// of 256 x 16 entries with one atomic per output per tile (a single global
+// counter per wave would serialise in L2).
 constexpr int kPartThreads = 256;
 constexpr int kPartItems = 16;
 
 __global__ __launch_bounds__(kPartThreads) void k_live_partition(
     const uint32_t *__restrict__ L, uint32_t nL, const Slot *__restrict__ slots, uint32_t k,
-    uint32_t *F, uint32_t *nF, uint32_t *Lo, uint32_t *nLo) {
-  __shared__ uint32_t wsum[2][kPartThreads / kWave];
-  __shared__ uint32_t base[2];
+    uint32_t kw, uint32_t *F, uint32_t *nF, uint32_t *Lo, uint32_t *nLo, uint32_t *Hi,
+    uint32_t *nHi) {
+  __shared__ uint32_t wsum[3][kPartThreads / kWave];
+  __shared__ uint32_t base[3];
   const int tid = threadIdx.x, w = tid / kWave;
   for (int64_t tile = (int64_t)blockIdx.x * kPartThreads * kPartItems; tile < nL;
        tile += (int64_t)gridDim.x * kPartThreads * kPartItems) {
     uint32_t p[kPartItems];
-    uint32_t fm = 0, km = 0;  // bit j: item j goes to F / stays live
+    uint32_t m[3] = {0, 0, 0};  // bit j: item j goes to F / Low / High
 #pragma unroll
     for (int j = 0; j < kPartItems; j++) {
       const int64_t i = tile + (int64_t)j * kPartThreads + tid;
@@ -818,37 +773,39 @@ __global__ __launch_bounds__(kPartThreads) void k_live_partition(
         p[j] = L[i];
         const Slot s = slots[p[j]];
         if (s.stamp == kLive) {
-          if (s.cnt <= k) fm |= 1u << j;
-          else km |= 1u << j;
+          const int dst = s.cnt <= k ? 0 : (s.cnt <= kw ? 1 : 2);
+          m[dst] |= 1u << j;
         }
       }
     }
-    const uint32_t fc = (uint32_t)__popc(fm), kc = (uint32_t)__popc(km);
-    const uint32_t fi = wave_incl_scan(fc), ki = wave_incl_scan(kc);
-    if (lane_id() == kWave - 1) {
-      wsum[0][w] = fi;
-      wsum[1][w] = ki;
+    uint32_t cnt[3], incl[3];
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      cnt[q] = (uint32_t)__popc(m[q]);
+      incl[q] = wave_incl_scan(cnt[q]);
     }
+    if (lane_id() == kWave - 1)
+      for (int q = 0; q < 3; q++) wsum[q][w] = incl[q];
     __syncthreads();
-    if (tid == 0) {
-      uint32_t tf = 0, tk = 0;
-      for (int q = 0; q < kPartThreads / kWave; q++) {
-        uint32_t a = wsum[0][q], b = wsum[1][q];
-        wsum[0][q] = tf;
-        wsum[1][q] = tk;
-        tf += a;
-        tk += b;
+    if (tid < 3) {
+      uint32_t tot = 0;
+      for (int v = 0; v < kPartThreads / kWave; v++) {
+        const uint32_t c = wsum[tid][v];
+        wsum[tid][v] = tot;
+        tot += c;
       }
-      base[0] = tf ? atomicAdd(nF, tf) : 0u;
-      base[1] = tk ? atomicAdd(nLo, tk) : 0u;
+      uint32_t *ctr = tid == 0 ? nF : (tid == 1 ? nLo : nHi);
+      base[tid] = tot ? atomicAdd(ctr, tot) : 0u;
     }
     __syncthreads();
-    uint32_t of = base[0] + wsum[0][w] + fi - fc;
-    uint32_t ok = base[1] + wsum[1][w] + ki - kc;
+    uint32_t at[3];
+#pragma unroll
+    for (int q = 0; q < 3; q++) at[q] = base[q] + wsum[q][w] + incl[q] - cnt[q];
 #pragma unroll
     for (int j = 0; j < kPartItems; j++) {
-      if (fm >> j & 1u) F[of++] = p[j];
-      if (km >> j & 1u) Lo[ok++] = p[j];
+      if (m[0] >> j & 1u) F[at[0]++] = p[j];
+      if (m[1] >> j & 1u) Lo[at[1]++] = p[j];
+      if (m[2] >> j & 1u) Hi[at[2]++] = p[j];
     }
     __syncthreads();
   }
@@ -922,10 +879,10 @@ void stamp_frontier(const uint32_t *F, uint32_t nF, Slot *slots, uint32_t t, hip
   case (R_) * 16 + (S_): peel_impl<R_, S_>(a, F, nF, st); break;
 
 void peel_round(const OrientedGraph &g, int r, int s, const TableView &T, const uint32_t *F,
-                uint32_t nF, uint32_t t, uint32_t k, uint32_t *Fnext, Counters *dctr,
-                unsigned long long *stats, hipStream_t st) {
+                uint32_t nF, uint32_t t, uint32_t k, uint32_t kw, uint32_t *Fnext, uint32_t *Low,
+                Counters *dctr, unsigned long long *stats, hipStream_t st) {
   if (!nF) return;
-  PeelArgs a{g.view(), T, t, k, Fnext, dctr, stats};
+  PeelArgs a{g.view(), T, t, k, Fnext, dctr, stats, kw, Low};
   switch (r * 16 + s) {
     ND_PEEL_CASE(1, 2) ND_PEEL_CASE(1, 3) ND_PEEL_CASE(1, 4) ND_PEEL_CASE(1, 5)
     ND_PEEL_CASE(1, 6) ND_PEEL_CASE(1, 7)
@@ -942,33 +899,21 @@ void peel_round(const OrientedGraph &g, int r, int s, const TableView &T, const 
 void count_direct(const OrientedGraph &g, int r, const TableView &T, const FastIndex &fx,
                   const uint32_t *occ, uint64_t n_r, Counters *dctr, hipStream_t st) {
   if (!n_r) return;
-  dim3 grid((unsigned)grid_for(n_r, 256, 1 << 20)), blk(256);
   const GraphView gv = g.view();
   const FastView fv = fx.view();
-  switch (r) {
-    case 2: hipLaunchKernelGGL(k_count_direct<2>, grid, blk, 0, st, gv, T, fv, occ, n_r, &dctr->err); break;
-    case 3: hipLaunchKernelGGL(k_count_direct<3>, grid, blk, 0, st, gv, T, fv, occ, n_r, &dctr->err); break;
-    case 4: hipLaunchKernelGGL(k_count_direct<4>, grid, blk, 0, st, gv, T, fv, occ, n_r, &dctr->err); break;
-    case 5: hipLaunchKernelGGL(k_count_direct<5>, grid, blk, 0, st, gv, T, fv, occ, n_r, &dctr->err); break;
-    case 6: hipLaunchKernelGGL(k_count_direct<6>, grid, blk, 0, st, gv, T, fv, occ, n_r, &dctr->err); break;
-    default: break;
+  if (r == 2) {  // popcount of one row plus one list length: a thread per edge
+    dim3 grid((unsigned)grid_for(n_r, 256, 1 << 20)), blk(256);
+    hipLaunchKernelGGL(k_count_direct<2>, grid, blk, 0, st, gv, T, fv, occ, n_r, &dctr->err);
+    return;
   }
-}
-
-void peel_round_fast(const OrientedGraph &g, int r, const TableView &T, const FastIndex &fx,
-                     const uint32_t *F, uint32_t nF, uint32_t t, uint32_t k, uint32_t *Fnext,
-                     Counters *dctr, unsigned long long *stats, hipStream_t st) {
-  if (!nF) return;
-  PeelArgs a{g.view(), T, t, k, Fnext, dctr, stats};
-  const FastView fv = fx.view();
+  PeelArgs a{gv, T, 0u, 0u, nullptr, dctr, nullptr, 0u, nullptr};
   const uint64_t *loc = fx.loc.get();
-  dim3 grid((unsigned)grid_for(nF, 4, 1 << 20)), blk(256);
+  dim3 grid((unsigned)grid_for(n_r, 4, 1 << 20)), blk(256);
   switch (r) {
-    case 2: hipLaunchKernelGGL(k_peel_fast<2>, grid, blk, 0, st, a, fv, loc, F, nF); break;
-    case 3: hipLaunchKernelGGL(k_peel_fast<3>, grid, blk, 0, st, a, fv, loc, F, nF); break;
-    case 4: hipLaunchKernelGGL(k_peel_fast<4>, grid, blk, 0, st, a, fv, loc, F, nF); break;
-    case 5: hipLaunchKernelGGL(k_peel_fast<5>, grid, blk, 0, st, a, fv, loc, F, nF); break;
-    case 6: hipLaunchKernelGGL(k_peel_fast<6>, grid, blk, 0, st, a, fv, loc, F, nF); break;
+    case 3: hipLaunchKernelGGL(k_count_wave<3>, grid, blk, 0, st, a, fv, loc, occ, n_r); break;
+    case 4: hipLaunchKernelGGL(k_count_wave<4>, grid, blk, 0, st, a, fv, loc, occ, n_r); break;
+    case 5: hipLaunchKernelGGL(k_count_wave<5>, grid, blk, 0, st, a, fv, loc, occ, n_r); break;
+    case 6: hipLaunchKernelGGL(k_count_wave<6>, grid, blk, 0, st, a, fv, loc, occ, n_r); break;
     default: break;
   }
 }
@@ -1003,15 +948,16 @@ float split_impl(const PeelArgs &a, const FastIndex &fx, const uint32_t *F, uint
 }
 
 uint64_t peel_round_split(const OrientedGraph &g, int r, const TableView &T, const FastIndex &fx,
-                          const uint32_t *F, uint32_t nF, uint32_t t, uint32_t k, uint32_t *Fnext,
-                          Counters *dctr, unsigned long long *stats, SplitBufs *sb,
-                          hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+                          const uint32_t *F, uint32_t nF, uint32_t t, uint32_t k, uint32_t kw,
+                          uint32_t *Fnext, uint32_t *Low, Counters *dctr,
+                          unsigned long long *stats, SplitBufs *sb, hipStream_t st,
+                          hipEvent_t ev0, hipEvent_t ev1) {
   if (!nF) {
     if (ev0) hipEventRecord(ev0, st);
     if (ev1) hipEventRecord(ev1, st);
     return 0;
   }
-  PeelArgs a{g.view(), T, t, k, Fnext, dctr, stats};
+  PeelArgs a{g.view(), T, t, k, Fnext, dctr, stats, kw, Low};
   float tot = 0;
   switch (r) {
     case 2: tot = split_impl<2>(a, fx, F, nF, sb, st, ev0, ev1); break;
@@ -1054,15 +1000,15 @@ void live_min(const uint32_t *L, uint32_t nL, const Slot *slots, Counters *dctr,
                      nL, slots, &dctr->live_min);
 }
 
-void live_partition(const uint32_t *L, uint32_t nL, const Slot *slots, uint32_t k, uint32_t *F,
-                    uint32_t *Lout, Counters *dctr, hipStream_t st) {
+void live_partition(const uint32_t *L, uint32_t nL, const Slot *slots, uint32_t k, uint32_t kw,
+                    uint32_t *F, uint32_t *Low, uint32_t *High, Counters *dctr, hipStream_t st) {
   fill_u32(&dctr->next_size, 0, 1, st);
-  fill_u32(&dctr->live_size, 0, 1, st);
+  fill_u32(&dctr->low_size, 0, 2, st);  // low_size, high_size
   if (!nL) return;
   hipLaunchKernelGGL(k_live_partition,
                      dim3((unsigned)grid_for(nL, kPartThreads * kPartItems, 8192)),
-                     dim3(kPartThreads), 0, st, L, nL, slots, k, F, &dctr->next_size, Lout,
-                     &dctr->live_size);
+                     dim3(kPartThreads), 0, st, L, nL, slots, k, kw, F, &dctr->next_size, Low,
+                     &dctr->low_size, High, &dctr->high_size);
 }
 
 void occupied_list(const Slot *slots, uint64_t n_slots, uint32_t *occ, hipStream_t st) {
