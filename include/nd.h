@@ -115,6 +115,74 @@ nd_status nd_round_trace(nd_plan p, uint64_t *sizes_host, uint32_t *levels_host,
 
 nd_status nd_plan_destroy(nd_plan p);
 
+/* ---- Batched decomposition of many independent graphs ------------------
+ * The batch is decomposed as one disjoint union: kappa of an r-clique is
+ * determined by its connected component (the definition in Section 2 only
+ * involves s-cliques that contain it), so every graph's result equals its
+ * own decomposition while all graphs share each kernel launch and every
+ * peeling round.  Graphs are CSRs as in nd_plan_create (DEVICE pointers,
+ * caller-owned, may be freed after nd_batch_create returns); count may be 0
+ * and graphs may be empty. */
+typedef struct nd_batch_s *nd_batch;
+
+nd_status nd_batch_create(const nd_csr *graphs, int32_t count, int r, int s,
+                          const nd_options *opt, uint64_t hbm_budget_bytes, void *hip_stream,
+                          nd_batch *out);
+
+/* Total rows over all graphs (sum of their r-clique counts) and the count. */
+nd_status nd_batch_sizes(nd_batch b, uint64_t *n_r_total, int32_t *count);
+
+/* Runs the decomposition.  Outputs are grouped by graph: the rows of graph g
+ * are [row_offsets_host[g], row_offsets_host[g+1]) (host array of count+1),
+ * with vertex ids local to graph g (ascending within a row) and rows in no
+ * particular order within a graph.  rcliques_dev[n_r_total * r],
+ * kappa_dev[n_r_total], counts_dev (nullable) as in nd_run.  Once per batch. */
+nd_status nd_batch_run(nd_batch b, int32_t *rcliques_dev, uint32_t *kappa_dev,
+                       uint32_t *counts_dev, uint64_t *row_offsets_host, nd_stats *stats);
+
+/* Rounds of the shared peel (every graph's rounds interleaved). */
+nd_status nd_batch_round_trace(nd_batch b, uint64_t *sizes_host, uint32_t *levels_host,
+                               uint64_t cap, uint64_t *rounds);
+
+nd_status nd_batch_destroy(nd_batch b);
+
+/* ---- Serving: continuous batching of (graph, r, s) jobs ----------------
+ * A pool of `workers` threads, each with its own HIP stream on the device
+ * current at creation, takes jobs from one FIFO queue.  A job starts when a
+ * worker is idle and its device-memory estimate fits what is left of
+ * hbm_budget_bytes (0 = no budget; a job larger than the budget runs
+ * alone), so jobs that arrive while others run are admitted as slots and
+ * memory free up and their peel rounds interleave on the GPU.  The caller
+ * keeps each submitted graph's device memory alive until the job is done.
+ * Results stay on the device until nd_server_release. */
+typedef struct nd_server_s *nd_server;
+
+nd_status nd_server_create(int32_t workers, uint64_t hbm_budget_bytes, nd_server *out);
+
+/* Queue one decomposition; *job receives its id.  opt may be NULL. */
+nd_status nd_server_submit(nd_server sv, const nd_csr *g, int r, int s, const nd_options *opt,
+                           uint64_t *job);
+
+/* Wait up to timeout_ms (-1 = without limit); *done = 1 once the job ended. */
+nd_status nd_server_wait(nd_server sv, uint64_t job, int32_t timeout_ms, int32_t *done);
+
+/* Outputs of a finished job (library-owned DEVICE arrays as in nd_run:
+ * rcliques [n_r * r], kappa [n_r]), its statistics, and the time it waited
+ * in the queue and spent running.  Returns the job's own status if it failed. */
+nd_status nd_server_result(nd_server sv, uint64_t job, uint64_t *n_r,
+                           const int32_t **rcliques_dev, const uint32_t **kappa_dev,
+                           nd_stats *stats, double *queue_ms, double *service_ms);
+
+/* Copy a finished job's outputs into caller-owned device buffers of
+ * n_r * r int32 and n_r uint32 and wait for the copy. */
+nd_status nd_server_copy(nd_server sv, uint64_t job, int32_t *rcliques_dst, uint32_t *kappa_dst);
+
+/* Free a finished job's outputs. */
+nd_status nd_server_release(nd_server sv, uint64_t job);
+
+/* Finish the queued jobs, stop the workers, free everything. */
+nd_status nd_server_destroy(nd_server sv);
+
 /* Free the library's cached device blocks (its allocator keeps freed blocks
  * for reuse by later plans). */
 nd_status nd_release_cached(void);

@@ -71,6 +71,33 @@ def _load():
     lib.nd_roofline_measure.argtypes = [ctypes.c_uint64, ctypes.c_uint64, P,
                                         ctypes.POINTER(nd_roofline)]
     lib.nd_roofline_measure.restype = ctypes.c_int
+    lib.nd_batch_create.argtypes = [ctypes.POINTER(nd_csr), ctypes.c_int32, ctypes.c_int,
+                                    ctypes.c_int, ctypes.POINTER(nd_options), ctypes.c_uint64, P,
+                                    ctypes.POINTER(P)]
+    lib.nd_batch_sizes.argtypes = [P, ctypes.POINTER(ctypes.c_uint64),
+                                   ctypes.POINTER(ctypes.c_int32)]
+    lib.nd_batch_run.argtypes = [P, P, P, P, P, ctypes.POINTER(nd_stats)]
+    lib.nd_batch_round_trace.argtypes = [P, P, P, ctypes.c_uint64,
+                                         ctypes.POINTER(ctypes.c_uint64)]
+    lib.nd_batch_destroy.argtypes = [P]
+    for name in ("nd_batch_create", "nd_batch_sizes", "nd_batch_run", "nd_batch_round_trace",
+                 "nd_batch_destroy"):
+        getattr(lib, name).restype = ctypes.c_int
+    lib.nd_server_create.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(P)]
+    lib.nd_server_submit.argtypes = [P, ctypes.POINTER(nd_csr), ctypes.c_int, ctypes.c_int,
+                                     ctypes.POINTER(nd_options), ctypes.POINTER(ctypes.c_uint64)]
+    lib.nd_server_wait.argtypes = [P, ctypes.c_uint64, ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_int32)]
+    lib.nd_server_result.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64),
+                                     ctypes.POINTER(P), ctypes.POINTER(P),
+                                     ctypes.POINTER(nd_stats), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
+    lib.nd_server_copy.argtypes = [P, ctypes.c_uint64, P, P]
+    lib.nd_server_release.argtypes = [P, ctypes.c_uint64]
+    lib.nd_server_destroy.argtypes = [P]
+    for name in ("nd_server_create", "nd_server_submit", "nd_server_wait", "nd_server_result",
+                 "nd_server_copy", "nd_server_release", "nd_server_destroy"):
+        getattr(lib, name).restype = ctypes.c_int
     lib.nd_status_str.argtypes = [ctypes.c_int]
     lib.nd_status_str.restype = ctypes.c_char_p
     lib.nd_last_error.argtypes = []
@@ -102,7 +129,10 @@ def library():
     return _Lazy._h
 
 EXPORTED = ("nd_plan_create", "nd_plan_sizes", "nd_run", "nd_round_trace", "nd_plan_destroy",
-            "nd_release_cached", "nd_status_str", "nd_last_error", "nd_roofline_measure")
+            "nd_release_cached", "nd_status_str", "nd_last_error", "nd_roofline_measure",
+            "nd_batch_create", "nd_batch_sizes", "nd_batch_run", "nd_batch_round_trace",
+            "nd_batch_destroy", "nd_server_create", "nd_server_submit", "nd_server_wait",
+            "nd_server_result", "nd_server_copy", "nd_server_release", "nd_server_destroy")
 
 
 def _check(rc: int):
@@ -171,6 +201,123 @@ def nd_plan_destroy(plan):
     _check(_lib.nd_plan_destroy(plan))
 
 
+def nd_batch_create(graphs, r: int, s: int, orient: int = 0, load_factor: float = 0.0,
+                    hbm_budget_bytes: int = 0, stream=None, timing: bool = False,
+                    generic: bool = False):
+    """graphs: sequence of (row_ptr int64, col int32) device tensor pairs."""
+    arr = (nd_csr * max(1, len(graphs)))()
+    keep = []
+    for i, (rp, col) in enumerate(graphs):
+        rp = rp.contiguous()
+        col = col.contiguous()
+        keep.append((rp, col))
+        arr[i] = nd_csr(int(rp.numel() - 1), int(col.numel()), rp.data_ptr(),
+                        col.data_ptr() if col.numel() else None)
+    opt = nd_options(int(orient), int(bool(timing)), float(load_factor), int(bool(generic)))
+    h = ctypes.c_void_p()
+    _check(_lib.nd_batch_create(arr, len(graphs), int(r), int(s), ctypes.byref(opt),
+                                int(hbm_budget_bytes), _stream_handle(stream), ctypes.byref(h)))
+    return h
+
+
+def nd_batch_sizes(batch):
+    n_r = ctypes.c_uint64()
+    count = ctypes.c_int32()
+    _check(_lib.nd_batch_sizes(batch, ctypes.byref(n_r), ctypes.byref(count)))
+    return int(n_r.value), int(count.value)
+
+
+def nd_batch_run(batch, rcliques, kappa, counts=None):
+    """Returns (row_offsets numpy uint64[count+1], stats dict)."""
+    import numpy as np
+    _, count = nd_batch_sizes(batch)
+    off = np.zeros(count + 1, dtype=np.uint64)
+    st = nd_stats()
+    _check(_lib.nd_batch_run(batch, rcliques.data_ptr() if rcliques.numel() else None,
+                             kappa.data_ptr() if kappa.numel() else None,
+                             counts.data_ptr() if counts is not None and counts.numel() else None,
+                             off.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st)))
+    return off, stats_dict(st)
+
+
+def nd_batch_round_trace(batch):
+    import numpy as np
+    rounds = ctypes.c_uint64()
+    _check(_lib.nd_batch_round_trace(batch, None, None, 0, ctypes.byref(rounds)))
+    n = int(rounds.value)
+    sizes = np.zeros(max(n, 1), dtype=np.uint64)
+    levels = np.zeros(max(n, 1), dtype=np.uint32)
+    _check(_lib.nd_batch_round_trace(batch, sizes.ctypes.data_as(ctypes.c_void_p),
+                                     levels.ctypes.data_as(ctypes.c_void_p), n,
+                                     ctypes.byref(rounds)))
+    return sizes[:n], levels[:n]
+
+
+def nd_batch_destroy(batch):
+    _check(_lib.nd_batch_destroy(batch))
+
+
+def nd_server_create(workers: int, hbm_budget_bytes: int = 0):
+    h = ctypes.c_void_p()
+    _check(_lib.nd_server_create(int(workers), int(hbm_budget_bytes), ctypes.byref(h)))
+    return h
+
+
+def nd_server_submit(server, row_ptr, col, r: int, s: int, orient: int = 0,
+                     generic: bool = False) -> int:
+    """The caller keeps row_ptr / col alive until the job is done."""
+    g = nd_csr(int(row_ptr.numel() - 1), int(col.numel()), row_ptr.data_ptr(),
+               col.data_ptr() if col.numel() else None)
+    opt = nd_options(int(orient), 0, 0.0, int(bool(generic)))
+    job = ctypes.c_uint64()
+    _check(_lib.nd_server_submit(server, ctypes.byref(g), int(r), int(s), ctypes.byref(opt),
+                                 ctypes.byref(job)))
+    return int(job.value)
+
+
+def nd_server_wait(server, job: int, timeout_ms: int = -1) -> bool:
+    done = ctypes.c_int32()
+    _check(_lib.nd_server_wait(server, ctypes.c_uint64(job), int(timeout_ms), ctypes.byref(done)))
+    return bool(done.value)
+
+
+def nd_server_result(server, job: int, r: int, copy: bool = True):
+    """(rcliques, kappa, stats, queue_ms, service_ms); with copy=True the
+    device outputs are copied into new torch tensors."""
+    import torch
+    n_r = ctypes.c_uint64()
+    rp = ctypes.c_void_p()
+    kp = ctypes.c_void_p()
+    st = nd_stats()
+    qms = ctypes.c_double()
+    sms = ctypes.c_double()
+    _check(_lib.nd_server_result(server, ctypes.c_uint64(job), ctypes.byref(n_r),
+                                 ctypes.byref(rp), ctypes.byref(kp), ctypes.byref(st),
+                                 ctypes.byref(qms), ctypes.byref(sms)))
+    n = int(n_r.value)
+    rcl = kap = None
+    if copy:
+        rcl = torch.empty((n, r), dtype=torch.int32, device="cuda")
+        kap = torch.empty((n,), dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        nd_server_copy(server, job, rcl, kap)
+    return rcl, kap, stats_dict(st), float(qms.value), float(sms.value)
+
+
+def nd_server_copy(server, job: int, rcliques_dst, kappa_dst):
+    """Device-to-device copy of a finished job's outputs into torch tensors."""
+    _check(_lib.nd_server_copy(server, ctypes.c_uint64(job), ctypes.c_void_p(rcliques_dst.data_ptr()),
+                               ctypes.c_void_p(kappa_dst.data_ptr())))
+
+
+def nd_server_release(server, job: int):
+    _check(_lib.nd_server_release(server, ctypes.c_uint64(job)))
+
+
+def nd_server_destroy(server):
+    _check(_lib.nd_server_destroy(server))
+
+
 def nd_release_cached():
     _check(_lib.nd_release_cached())
 
@@ -232,6 +379,91 @@ def decompose(row_ptr, col, r: int, s: int, with_counts: bool = False, orient: i
     finally:
         nd_plan_destroy(plan)
     return Decomposition(r, s, rcl, kap, cnt, stats, sizes, levels)
+
+
+@dataclass
+class BatchDecomposition:
+    r: int
+    s: int
+    rcliques: object          # int32 [n_r_total, r] device, graph-local ids
+    kappa: object             # int32 view of uint32 [n_r_total] device
+    counts: object | None
+    row_offsets: object       # numpy uint64 [count+1]
+    stats: dict = field(default_factory=dict)
+
+    def graph(self, g: int):
+        a, b = int(self.row_offsets[g]), int(self.row_offsets[g + 1])
+        cnt = self.counts[a:b] if self.counts is not None else None
+        return self.rcliques[a:b], self.kappa[a:b], cnt
+
+
+def decompose_batch(graphs, r: int, s: int, with_counts: bool = False, orient: int = 0,
+                    load_factor: float = 0.0, hbm_budget_bytes: int = 0, stream=None,
+                    timing: bool = False, generic: bool = False) -> BatchDecomposition:
+    """All graphs in one fused decomposition (graphs: (row_ptr, col) device pairs)."""
+    import torch
+    b = nd_batch_create(graphs, r, s, orient, load_factor, hbm_budget_bytes, stream, timing,
+                        generic)
+    try:
+        n_r, _ = nd_batch_sizes(b)
+        dev = graphs[0][0].device if graphs else torch.device("cuda")
+        rcl = torch.empty((n_r, r), dtype=torch.int32, device=dev)
+        kap = torch.empty((n_r,), dtype=torch.int32, device=dev)
+        cnt = torch.empty((n_r,), dtype=torch.int32, device=dev) if with_counts else None
+        off, stats = nd_batch_run(b, rcl, kap, cnt)
+    finally:
+        nd_batch_destroy(b)
+    return BatchDecomposition(r, s, rcl, kap, cnt, off, stats)
+
+
+@dataclass
+class Served:
+    job: int
+    decomposition: Decomposition
+    queue_ms: float      # submit -> start of service
+    service_ms: float    # start -> end of service
+
+
+class Server:
+    """Continuous-batching request loop: jobs are admitted by the memory
+    budget onto a pool of worker streams and run concurrently on the device.
+    The graph tensors of a job are kept referenced until its result is taken."""
+
+    def __init__(self, workers: int = 4, hbm_budget_bytes: int = 0):
+        self.handle = nd_server_create(workers, hbm_budget_bytes)
+        self._keep = {}
+
+    def submit(self, row_ptr, col, r: int, s: int, orient: int = 0, generic: bool = False) -> int:
+        job = nd_server_submit(self.handle, row_ptr, col, r, s, orient, generic)
+        self._keep[job] = (row_ptr, col, r, s)
+        return job
+
+    def wait(self, job: int, timeout_ms: int = -1) -> bool:
+        return nd_server_wait(self.handle, job, timeout_ms)
+
+    def result(self, job: int) -> Served:
+        """Wait for the job, copy its outputs into new tensors, free its
+        device outputs; raises NdError with the job's own status if it failed."""
+        _, _, r, s = self._keep[job]
+        nd_server_wait(self.handle, job, -1)
+        try:
+            rcl, kap, stats, qms, sms = nd_server_result(self.handle, job, r, copy=True)
+        finally:
+            nd_server_release(self.handle, job)
+            del self._keep[job]
+        return Served(job, Decomposition(r, s, rcl, kap, None, stats), qms, sms)
+
+    def close(self):
+        if self.handle is not None:
+            nd_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def to_device(g, device="cuda"):

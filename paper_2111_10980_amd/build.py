@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnd.so")
 SOURCES = ["nd_prims.hip", "nd_graph.hip", "nd_clique.hip", "nd_peel.hip", "nd_fast.hip",
-           "nd_api.hip", "nd_roofline.hip"]
+           "nd_api.hip", "nd_roofline.hip", "nd_server.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -106,6 +106,86 @@ __global__ __launch_bounds__(256) void k_sum_slot_counts(const Slot *__restrict_
   if (lane_id() == 0 && acc) atomicAdd(out, (unsigned long long)acc);
 }
 
+// ---- batched decomposition: the batch is one disjoint union (kappa is a
+// property of each connected component, so the union's kappa of an r-clique
+// equals its kappa in its own graph).
+struct GraphDesc {
+  const int64_t *rp;
+  const int32_t *col;
+  int32_t n;
+  int32_t vo;  // first union id of the graph
+  int64_t nnz;
+  int64_t eo;  // first union arc of the graph
+};
+
+// last g in [0, count) with key[g] <= x (empty graphs share offsets; the
+// last of equal offsets is the non-empty one that owns x)
+template <class T>
+__device__ __forceinline__ int owner_of(const T *__restrict__ key, int count, T x) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (key[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_union_rows(const GraphDesc *__restrict__ gd, const int32_t *__restrict__ vo,
+                             int count, int32_t n_total, int64_t nnz_total, int64_t *rp) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= n_total;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    if (v == n_total) {
+      rp[v] = nnz_total;
+      continue;
+    }
+    const int g = owner_of<int32_t>(vo, count, (int32_t)v);
+    rp[v] = gd[g].eo + gd[g].rp[v - gd[g].vo];
+  }
+}
+
+__global__ void k_union_cols(const GraphDesc *__restrict__ gd, const int64_t *__restrict__ eo,
+                             int count, int64_t nnz_total, int32_t *col, uint32_t *err) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz_total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int g = owner_of<int64_t>(eo, count, i);
+    const int32_t c = gd[g].col[i - gd[g].eo];
+    if (c < 0 || c >= gd[g].n) {
+      atomicOr(err, kErrGraph);
+      col[i] = 0;
+    } else {
+      col[i] = c + gd[g].vo;
+    }
+  }
+}
+
+// graph of every output row (its first vertex's graph) and rows per graph
+__global__ void k_row_graph(const int32_t *__restrict__ rcl, int r, uint64_t n_r,
+                            const int32_t *__restrict__ vo, int count, int32_t *gid,
+                            unsigned long long *per_graph) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)n_r;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int g = owner_of<int32_t>(vo, count, rcl[i * r]);
+    gid[i] = g;
+    atomicAdd(&per_graph[g], 1ull);
+  }
+}
+
+__global__ void k_regroup(const int32_t *__restrict__ rcl, const uint32_t *__restrict__ kap,
+                          const uint32_t *__restrict__ cnt, int r, uint64_t n_r,
+                          const int32_t *__restrict__ gid, const int32_t *__restrict__ vo,
+                          const unsigned long long *__restrict__ off, unsigned long long *cursor,
+                          int32_t *rcl_out, uint32_t *kap_out, uint32_t *cnt_out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)n_r;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int g = gid[i];
+    const uint64_t at = off[g] + atomicAdd(&cursor[g], 1ull);
+    for (int q = 0; q < r; q++) rcl_out[at * r + q] = rcl[i * r + q] - vo[g];
+    kap_out[at] = kap[i];
+    if (cnt_out) cnt_out[at] = cnt[i];
+  }
+}
+
 uint64_t binom_u64(int n, int k) {
   uint64_t r = 1;
   for (int i = 1; i <= k; i++) r = r * (uint64_t)(n - k + i) / (uint64_t)i;
@@ -559,6 +639,165 @@ nd_status nd_plan_destroy(nd_plan p) {
   hipStream_t st = p->st;
   StreamScope scope(st);
   delete p;
+  hipStreamSynchronize(st);
+  return ND_OK;
+}
+
+struct nd_batch_s {
+  hipStream_t st = nullptr;
+  int r = 0, s = 0;
+  int32_t count = 0, n_total = 0;
+  int64_t nnz_total = 0;
+  DevBuf<int64_t> rp;
+  DevBuf<int32_t> col, vo;
+  nd_plan plan = nullptr;
+  uint64_t n_r = 0;
+  bool ran = false;
+};
+
+nd_status nd_batch_create(const nd_csr *graphs, int32_t count, int r, int s,
+                          const nd_options *opt, uint64_t hbm_budget_bytes, void *hip_stream,
+                          nd_batch *out) {
+  if (!out || (count > 0 && !graphs) || count < 0) {
+    g_last_error = "bad batch arguments";
+    return ND_EINVAL;
+  }
+  *out = nullptr;
+  hipStream_t st = (hipStream_t)hip_stream;
+  nd_batch b = new (std::nothrow) nd_batch_s();
+  if (!b) return ND_ENOMEM;
+  nd_status rc = guarded(st, [&] {
+    b->st = st;
+    b->r = r;
+    b->s = s;
+    b->count = count;
+    std::vector<GraphDesc> gd((size_t)(count > 0 ? count : 1));
+    std::vector<int32_t> vo((size_t)count + 1);
+    std::vector<int64_t> eo((size_t)count + 1);
+    int64_t nv = 0, ne = 0;
+    for (int32_t g = 0; g < count; g++) {
+      const nd_csr &c = graphs[g];
+      if (c.n < 0 || c.nnz < 0 || (c.n > 0 && !c.row_ptr) || (c.nnz > 0 && !c.col))
+        fail(ND_EINVAL, "graph %d has a bad CSR header", g);
+      vo[g] = (int32_t)nv;
+      eo[g] = ne;
+      gd[g] = GraphDesc{c.row_ptr, c.col, c.n, (int32_t)nv, c.nnz, ne};
+      nv += c.n;
+      ne += c.nnz;
+      if (nv > INT32_MAX - 1) fail(ND_EOVERFLOW, "the batch has more than 2^31 vertices");
+    }
+    vo[count] = (int32_t)nv;
+    eo[count] = ne;
+    b->n_total = (int32_t)nv;
+    b->nnz_total = ne;
+    b->rp.reset((size_t)nv + 1);
+    b->col.reset(ne > 0 ? (size_t)ne : 1);
+    b->vo.reset((size_t)count + 1);
+    DevBuf<GraphDesc> gdd(gd.size());
+    DevBuf<int64_t> eod((size_t)count + 1);
+    DevBuf<uint32_t> err(1);
+    fill_u32(err.get(), 0, 1, st);
+    hip_check(hipMemcpyAsync(gdd.get(), gd.data(), sizeof(GraphDesc) * gd.size(),
+                             hipMemcpyHostToDevice, st), "copy descriptors");
+    hip_check(hipMemcpyAsync(b->vo.get(), vo.data(), 4 * vo.size(), hipMemcpyHostToDevice, st),
+              "copy offsets");
+    hip_check(hipMemcpyAsync(eod.get(), eo.data(), 8 * eo.size(), hipMemcpyHostToDevice, st),
+              "copy offsets");
+    if (count > 0) {
+      hipLaunchKernelGGL(k_union_rows, dim3((unsigned)grid_for(nv + 1, 256)), dim3(256), 0, st,
+                         gdd.get(), b->vo.get(), (int)count, (int32_t)nv, ne, b->rp.get());
+      if (ne > 0)
+        hipLaunchKernelGGL(k_union_cols, dim3((unsigned)grid_for(ne, 256)), dim3(256), 0, st,
+                           gdd.get(), eod.get(), (int)count, ne, b->col.get(), err.get());
+    } else {
+      fill_u64((uint64_t *)b->rp.get(), 0, 1, st);
+    }
+    if (read_dev(err.get(), st)) fail(ND_EGRAPH, "a batch graph has a vertex id out of range");
+    nd_csr u{(int32_t)nv, ne, b->rp.get(), b->col.get()};
+    nd_status prc = nd_plan_create(&u, r, s, opt, hbm_budget_bytes, hip_stream, &b->plan);
+    if (prc != ND_OK) throw Failure{prc};
+    uint64_t bytes = 0;
+    nd_plan_sizes(b->plan, &b->n_r, &bytes);
+  });
+  if (rc != ND_OK) {
+    nd_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return ND_OK;
+}
+
+nd_status nd_batch_sizes(nd_batch b, uint64_t *n_r_total, int32_t *count) {
+  if (!b) {
+    g_last_error = "batch is null";
+    return ND_EINVAL;
+  }
+  if (n_r_total) *n_r_total = b->n_r;
+  if (count) *count = b->count;
+  return ND_OK;
+}
+
+nd_status nd_batch_run(nd_batch b, int32_t *rcliques_dev, uint32_t *kappa_dev,
+                       uint32_t *counts_dev, uint64_t *row_offsets_host, nd_stats *stats) {
+  if (!b || !row_offsets_host) {
+    g_last_error = "batch or row_offsets is null";
+    return ND_EINVAL;
+  }
+  if (b->ran) {
+    g_last_error = "nd_batch_run was already called on this batch";
+    return ND_ESTATE;
+  }
+  if (b->n_r && (!rcliques_dev || !kappa_dev)) {
+    g_last_error = "output pointer is null";
+    return ND_EINVAL;
+  }
+  hipStream_t st = b->st;
+  return guarded(st, [&] {
+    b->ran = true;
+    const int r = b->r;
+    const uint64_t n_r = b->n_r;
+    DevBuf<int32_t> rcl(n_r ? n_r * r : 1);
+    DevBuf<uint32_t> kap(n_r ? n_r : 1), cnt(counts_dev && n_r ? n_r : 1);
+    nd_status prc = nd_run(b->plan, rcl.get(), kap.get(), counts_dev ? cnt.get() : nullptr, stats);
+    if (prc != ND_OK) throw Failure{prc};
+    const int count = b->count;
+    DevBuf<unsigned long long> per((size_t)count + 1), cur((size_t)count + 1);
+    fill_u64((uint64_t *)per.get(), 0, count + 1, st);
+    fill_u64((uint64_t *)cur.get(), 0, count + 1, st);
+    DevBuf<int32_t> gid(n_r ? n_r : 1);
+    if (n_r && count > 0)
+      hipLaunchKernelGGL(k_row_graph, dim3((unsigned)grid_for(n_r, 256)), dim3(256), 0, st,
+                         rcl.get(), r, n_r, b->vo.get(), count, gid.get(), per.get());
+    scan_exclusive_u64((uint64_t *)per.get(), (uint64_t *)per.get(), (int64_t)count + 1, st);
+    if (n_r && count > 0)
+      hipLaunchKernelGGL(k_regroup, dim3((unsigned)grid_for(n_r, 256)), dim3(256), 0, st,
+                         rcl.get(), kap.get(), cnt.get(), r, n_r, gid.get(), b->vo.get(),
+                         per.get(), cur.get(), rcliques_dev, kappa_dev,
+                         counts_dev ? counts_dev : nullptr);
+    hip_check(hipMemcpyAsync(row_offsets_host, per.get(), 8 * ((size_t)count + 1),
+                             hipMemcpyDeviceToHost, st), "copy row offsets");
+    hip_check(hipStreamSynchronize(st), "synchronize");
+    hip_check(hipGetLastError(), "kernel launch");
+  });
+}
+
+nd_status nd_batch_round_trace(nd_batch b, uint64_t *sizes_host, uint32_t *levels_host,
+                               uint64_t cap, uint64_t *rounds) {
+  if (!b || !b->plan) {
+    g_last_error = "batch is null";
+    return ND_EINVAL;
+  }
+  return nd_round_trace(b->plan, sizes_host, levels_host, cap, rounds);
+}
+
+nd_status nd_batch_destroy(nd_batch b) {
+  if (!b) return ND_OK;
+  hipStream_t st = b->st;
+  if (b->plan) nd_plan_destroy(b->plan);
+  {
+    StreamScope scope(st);
+    delete b;
+  }
   hipStreamSynchronize(st);
   return ND_OK;
 }

@@ -58,11 +58,11 @@ def csr_from_edges(n: int, u, v) -> CSR:
     key = np.unique(lo * np.int64(n) + hi)
     lo = key // n
     hi = key % n
-    src = np.concatenate([lo, hi])
-    dst = np.concatenate([hi, lo])
-    order = np.lexsort((dst, src))
-    src = src[order]
-    dst = dst[order]
+    # both arc directions, ordered by (src, dst): the keys are distinct
+    arcs = np.concatenate([key, hi * np.int64(n) + lo])
+    arcs.sort()
+    src = arcs // n
+    dst = arcs % n
     counts = np.bincount(src, minlength=n).astype(np.int64)
     row_ptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(counts, out=row_ptr[1:])
