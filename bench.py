@@ -29,6 +29,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 SLOT_BYTES = 16                # one r-clique table slot {key, count, stamp}
 
 BATCH_WORKLOAD = "batch4096_34"
+SERVE_WORKLOAD = "serve_rmat"
 
 WORKLOADS = {
     # name: (generator, r, s, description)
@@ -66,8 +67,15 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat18_34",
-                    choices=sorted(WORKLOADS) + [BATCH_WORKLOAD])
+                    choices=sorted(WORKLOADS) + [BATCH_WORKLOAD, SERVE_WORKLOAD])
     ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--rates", default="50,100,200,400",
+                    help="serving: Poisson arrival rates (jobs/s) to sweep")
+    ap.add_argument("--serve-jobs", type=int, default=1000, help="serving: measured jobs per rate")
+    ap.add_argument("--serve-warmup", type=int, default=100, help="serving: warm-up jobs per rate")
+    ap.add_argument("--max-scale", type=int, default=14, help="serving: largest rMAT scale")
+    ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--hbm-budget-gb", type=float, default=200.0)
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--orient", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -83,6 +91,8 @@ def main():
 
     if args.workload == BATCH_WORKLOAD:
         return bench_batch(args)
+    if args.workload == SERVE_WORKLOAD:
+        return bench_serve(args)
     gen, r, s, desc = WORKLOADS[args.workload]
     t0 = time.perf_counter()
     g = getattr(inputs, gen)() if args.seed is None else getattr(inputs, gen)(args.seed)
@@ -253,6 +263,132 @@ def bench_batch(args):
                    "sum_n": int(sum(g.n for g in gs)), "sum_m": int(sum(g.m for g in gs)),
                    "n_r": st["n_r"], "n_s": st["n_s"], "rounds": st["rounds"],
                    "phase_ms": st["ms"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _serve_graph(job):
+    from paper_2111_10980_amd import inputs
+    return inputs.rmat(job.scale, job.edge_factor, job.graph_seed)
+
+
+def _replay(nd, jobs, dev, workers, budget):
+    """Submit each job at its arrival time; per job (latency ms, completion s,
+    stats).  Latency = queueing + service, both timed inside the library."""
+    import threading
+    out = [None] * len(jobs)
+    ids = [None] * len(jobs)
+    submitted = threading.Semaphore(0)
+    sv = nd.Server(workers, budget)
+
+    def collect():
+        for i in range(len(jobs)):
+            submitted.acquire()
+            j = ids[i]
+            nd.nd_server_wait(sv.handle, j, -1)
+            _, _, st, qms, sms = nd.nd_server_result(sv.handle, j, jobs[i].r, copy=False)
+            nd.nd_server_release(sv.handle, j)
+            out[i] = (qms + sms, st, sms)
+
+    th = threading.Thread(target=collect)
+    th.start()
+    t0 = time.perf_counter()
+    sub_t = [0.0] * len(jobs)
+    for i, jb in enumerate(jobs):
+        wait = t0 + jb.arrival_s - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        sub_t[i] = time.perf_counter() - t0
+        ids[i] = nd.nd_server_submit(sv.handle, *dev[i], jb.r, jb.s)
+        submitted.release()
+    th.join()
+    sv.close()
+    return [(lat, sub_t[i] + lat / 1000.0, st, sms) for i, (lat, st, sms) in enumerate(out)]
+
+
+def bench_serve(args):
+    """Poisson stream of (rMAT graph, r, s) jobs replayed against the server:
+    continuous batching (several worker streams) against one job at a time,
+    at the same arrival times; p50/p99 latency and completed jobs/s."""
+    import numpy as np
+    import torch
+    import paper_2111_10980_amd as nd
+    from paper_2111_10980_amd import inputs
+    rates = [float(x) for x in args.rates.split(",")]
+    total = args.serve_warmup + args.serve_jobs
+    base = inputs.serving_stream(1.0, total, seed=7, min_scale=10, max_scale=args.max_scale)
+    t0 = time.perf_counter()
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(min(8, os.cpu_count() or 1)) as pool:
+        gs = pool.map(_serve_graph, base, chunksize=16)
+    log(f"[bench] generated {total} serving graphs in {time.perf_counter() - t0:.1f}s "
+        f"(scales 10..{args.max_scale}), sum m={sum(g.m for g in gs)}")
+    torch.cuda.set_device(0)
+    dev = [nd.to_device(g, "cuda:0") for g in gs]
+    torch.cuda.synchronize()
+    budget = int(args.hbm_budget_gb * (1 << 30))
+    # warm the library (kernels loaded, pool grown) outside the measurement
+    d = nd.decompose(*dev[0], base[0].r, base[0].s)
+    torch.cuda.synchronize()
+    sweep = []
+    ref_stats = None
+    for lam in rates:
+        jobs = [inputs.Job(j.arrival_s / lam, j.scale, j.edge_factor, j.r, j.s, j.graph_seed)
+                for j in base]
+        row = {"rate": lam}
+        for mode, workers in (("continuous", args.serve_workers), ("one_at_a_time", 1)):
+            res = _replay(nd, jobs, dev, workers, budget)
+            meas = res[args.serve_warmup:]
+            lat = np.array([x[0] for x in meas])
+            start = jobs[args.serve_warmup].arrival_s
+            end = max(x[1] for x in meas)
+            stats = [(x[2]["n_r"], x[2]["n_s"], x[2]["max_kappa"]) for x in res]
+            if ref_stats is None:
+                ref_stats = stats
+            if mode == "one_at_a_time" and lam == rates[0]:
+                per = {}
+                for jb, x in zip(jobs, res):
+                    per.setdefault((jb.scale, jb.r, jb.s), []).append(x[3])
+                log("[bench] service ms by (scale,r,s), one at a time: " + ", ".join(
+                    f"{k}:{np.mean(v):.1f}x{len(v)}" for k, v in sorted(per.items())))
+            # the same jobs give the same results whatever the mode and rate
+            assert stats == ref_stats, "served results differ between runs"
+            row[mode] = {"workers": workers, "p50_ms": float(np.percentile(lat, 50)),
+                         "p99_ms": float(np.percentile(lat, 99)),
+                         "mean_ms": float(lat.mean()),
+                         "jobs_per_s": len(meas) / max(end - start, 1e-9)}
+            log(f"[bench] rate {lam:g}/s {mode:14s} p50 {row[mode]['p50_ms']:8.1f} ms  "
+                f"p99 {row[mode]['p99_ms']:8.1f} ms  {row[mode]['jobs_per_s']:7.1f} jobs/s")
+        sweep.append(row)
+    # headline: the highest rate at which continuous batching keeps up with
+    # the arrivals (completed rate >= 90% of offered), else the lowest rate
+    ok = [r_ for r_ in sweep if r_["continuous"]["jobs_per_s"] >= 0.9 * r_["rate"]]
+    head = ok[-1] if ok else sweep[0]
+    c = head["continuous"]
+    classes = {}
+    for jb in base:
+        classes.setdefault(f"s{jb.scale}", 0)
+        classes[f"s{jb.scale}"] += 1
+    out = {
+        "metric": "serving throughput at p50/p99 latency",
+        "value": c["jobs_per_s"],
+        "unit": "jobs/s",
+        "n_gpus": 1,
+        "steps": args.serve_jobs,
+        "warmup": args.serve_warmup,
+        "ms_per_step": 1000.0 / c["jobs_per_s"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "p50_ms": c["p50_ms"],
+        "p99_ms": c["p99_ms"],
+        "config": {"workload": SERVE_WORKLOAD, "rate": head["rate"],
+                   "jobs": args.serve_jobs, "warmup_jobs": args.serve_warmup,
+                   "scales": [10, args.max_scale], "edge_factor": [8, 16], "r": [1, 3],
+                   "s": "r+1..r+2", "hbm_budget_gb": args.hbm_budget_gb,
+                   "workers": args.serve_workers, "sweep": sweep},
     }
     print(json.dumps(out), flush=True)
 

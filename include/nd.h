@@ -62,8 +62,9 @@ typedef struct {
   int32_t orient;        /* 0 = degree order (ties by id), 1 = exact core (degeneracy) order */
   int32_t timing;        /* 1 = time the count-listing and peel kernels with HIP events */
   float load_factor;     /* r-clique table load factor in (0, 0.9]; 0 = 0.5 */
-  int32_t path;          /* 0 = auto; 1 = force the generic path (Count-Func atomics and
-                            intersection by edge tests) even when s = r+1 */
+  int32_t path;          /* 0 = auto; 1 = force the one-wave generic walker (Count-Func
+                            atomics; each peeled r-clique's s-cliques listed by one wave
+                            with edge tests) for every (r, s) */
 } nd_options;
 
 typedef struct {

@@ -501,6 +501,10 @@ nd_status nd_run(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *cou
       hip_check(hipMemcpyAsync(Lh.get(), p->occ.get(), 4 * p->n_r, hipMemcpyDeviceToDevice, st),
                 "copy");
     SplitBufs sb;
+    GenBufs gb;
+    // s >= r + 2 peels through the flattened passes unless the one-wave
+    // walker is asked for
+    const bool gen = !p->fast && s >= r + 2 && p->opt.path == 0;
     uint64_t nH = p->n_r, nW = 0, finished = 0;
     uint32_t k = 0, kw = 0, t = 0, nF = 0;
     p->round_sizes.clear();
@@ -550,6 +554,10 @@ nd_status nd_run(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *cou
         peel_round_split(p->g, r, p->table(), p->fx, F.get(), nF, t, k, kw, Fn.get(), Lw.get(),
                          dc, p->stats.get(), &sb, st, timing ? kt.ev[2] : nullptr,
                          timing ? kt.ev[3] : nullptr);
+      } else if (gen) {
+        peel_round_gen(p->g, r, s, p->table(), F.get(), nF, t, k, kw, Fn.get(), Lw.get(), dc,
+                       p->stats.get(), &gb, st, timing ? kt.ev[2] : nullptr,
+                       timing ? kt.ev[3] : nullptr);
       } else {
         if (timing) kt.mark(2, st);
         peel_round(p->g, r, s, p->table(), F.get(), nF, t, k, kw, Fn.get(), Lw.get(), dc,

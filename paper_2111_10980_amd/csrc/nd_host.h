@@ -118,6 +118,22 @@ void count_direct(const OrientedGraph &g, int r, const TableView &T, const FastI
 void build_slot_loc(const OrientedGraph &g, int r, const TableView &T, uint64_t n_slots,
                     FastIndex *fx, hipStream_t st);
 // round scratch of the expand/apply peel, grown on demand and kept by the run
+// s >= r + 2: a round's update flattened over candidates and out-arcs
+struct GenBufs {
+  DevBuf<uint64_t> ioff;  // candidate bounds per frontier entry, then offsets
+  DevBuf<int32_t> fv;     // decoded frontier r-cliques
+  DevBuf<int32_t> drv;    // driver (fewest neighbours) of each
+  DevBuf<uint8_t> flag;   // candidate in the common neighbourhood
+  DevBuf<uint64_t> aoff;  // out-degree of each member, then offsets
+};
+// returns the number of out-arcs examined; ev0/ev1 (nullable) bracket the
+// apply kernel
+uint64_t peel_round_gen(const OrientedGraph &g, int r, int s, const TableView &T,
+                        const uint32_t *F, uint32_t nF, uint32_t t, uint32_t k, uint32_t kw,
+                        uint32_t *Fnext, uint32_t *Low, Counters *dctr,
+                        unsigned long long *stats, GenBufs *gb, hipStream_t st, hipEvent_t ev0,
+                        hipEvent_t ev1);
+
 struct SplitBufs {
   DevBuf<uint64_t> off;  // frontier candidate bounds, then their prefix sum
   DevBuf<int32_t> fv;    // decoded frontier r-cliques, r ids each

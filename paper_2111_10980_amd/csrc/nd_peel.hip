@@ -861,6 +861,226 @@ __global__ void k_emit(const uint32_t *__restrict__ occ, uint64_t n_r, TableView
   }
 }
 
+// ------------------------------------------------------------ s >= r + 2
+// Update for s - r >= 2, flattened over the whole round so that one heavy
+// r-clique is shared by many waves instead of being walked by one.  The
+// s-cliques containing a peeled R are R plus an (s-r)-clique Q of I(R), the
+// common neighbourhood of R.  I(R) is the part of the row of R's driver (the
+// member with the fewest neighbours) adjacent to every other member, kept
+// as one flag per position of that row.  Q is listed from its lowest vertex
+// x along the out-arcs of x, so each s-clique of R is met exactly once.
+//   bound:  candidates of each peeled R = the driver's degree;
+//   member: a thread per candidate x: x in I(R)? and its out-degree;
+//   apply:  a thread per out-arc (x, y) of a member: y in I(R) closes
+//           R + {x, y} (s = r + 2) or starts a deeper extension.
+
+// Segment of x in a nondecreasing offset array: the last i < n with
+// off[i] <= x (empty segments are skipped).
+__device__ __forceinline__ int64_t seg_find(const uint64_t *__restrict__ off, int64_t n,
+                                            uint64_t x) {
+  int64_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+struct GenView {
+  const uint64_t *__restrict__ ioff;  // nF + 1 candidate offsets
+  const int32_t *__restrict__ fv;     // nF * R decoded r-cliques
+  const int32_t *__restrict__ drv;    // nF drivers
+  const uint8_t *__restrict__ flag;   // C1 membership flags
+  const uint64_t *__restrict__ aoff;  // C1 + 1 arc offsets
+  uint32_t nF;
+  uint64_t C1;
+};
+
+template <int R>
+__global__ __launch_bounds__(256) void k_gen_bound(PeelArgs a, const uint32_t *__restrict__ F,
+                                                   uint32_t nF, uint64_t *ub, int32_t *fv,
+                                                   int32_t *drv) {
+  for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nF;
+       f += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t p = F[f];
+    const Slot sl = a.T.slots[p];
+    int32_t Rv[R];
+    Rv[0] = a.T.v1[p];
+    decode_key<R>(sl.key, a.T.bits, Rv);
+    int32_t best_v = Rv[0];
+    int64_t best = a.g.rp[Rv[0] + 1] - a.g.rp[Rv[0]];
+#pragma unroll
+    for (int i = 0; i < R; i++) {
+      fv[f * R + i] = Rv[i];
+      const int64_t d = a.g.rp[Rv[i] + 1] - a.g.rp[Rv[i]];
+      if (d < best) {
+        best = d;
+        best_v = Rv[i];
+      }
+    }
+    drv[f] = best_v;
+    ub[f] = sl.cnt != 0 ? (uint64_t)best : 0;  // cnt 0: every s-clique of R is gone
+  }
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_gen_member(GraphView g, GenView gv, uint8_t *flag,
+                                                    uint64_t *arcs) {
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < gv.C1;
+       k += (uint64_t)gridDim.x * blockDim.x) {
+    const int64_t f = seg_find(gv.ioff, gv.nF, k);
+    const int32_t v = gv.drv[f];
+    const int32_t x = g.col[g.rp[v] + (int64_t)(k - gv.ioff[f])];
+    bool in = true;
+#pragma unroll
+    for (int i = 0; i < R; i++) {
+      const int32_t u = gv.fv[f * R + i];
+      if (u != v) in = in && adjacent(g, x, u);
+    }
+    flag[k] = in ? 1 : 0;
+    arcs[k] = in ? (uint64_t)(g.rp[x + 1] - g.up[x]) : 0;
+  }
+}
+
+// y in I(R): a position of the driver's row whose flag is set
+__device__ __forceinline__ bool gen_in(const GraphView &g, const GenView &gv, int64_t lo,
+                                       int64_t hi, uint64_t fbase, int32_t y) {
+  const int64_t at = lower_pos(g.col, lo, hi, y);
+  return at < hi && g.col[at] == y && gv.flag[fbase + (uint64_t)(at - lo)] != 0;
+}
+
+template <int R, int Q>
+__device__ __forceinline__ void merge_rq(const int32_t (&Rv)[R], const int32_t (&Qv)[Q],
+                                         int32_t (&Sv)[R + Q], uint32_t &rmask) {
+  rmask = 0;
+  int i = 0, j = 0;
+#pragma unroll
+  for (int o = 0; o < R + Q; o++) {
+    if (j >= Q || (i < R && Rv[i] < Qv[j])) {
+      Sv[o] = Rv[i++];
+      rmask |= 1u << o;
+    } else {
+      Sv[o] = Qv[j++];
+    }
+  }
+}
+
+// Q[0..L-1] is a clique inside I(R); extend it by out-neighbours of Q[L-1]
+// that lie in I(R) and are adjacent to Q[0..L-2].
+template <int L, int R, int S>
+__device__ void gen_extend(const PeelArgs &a, const GenView &gv, int64_t lo, int64_t hi,
+                           uint64_t fbase, const int32_t (&Rv)[R], int32_t (&Qv)[S - R],
+                           uint32_t p, LaneStats &ls) {
+  const int32_t x = Qv[L - 1];
+  for (int64_t e = a.g.up[x]; e < a.g.rp[x + 1]; e++) {
+    const int32_t z = a.g.col[e];
+    bool ok = gen_in(a.g, gv, lo, hi, fbase, z);
+#pragma unroll
+    for (int j = 0; j < L - 1; j++) ok = ok && adjacent(a.g, Qv[j], z);
+    if (!ok) continue;
+    Qv[L] = z;
+    if constexpr (L + 1 == S - R) {
+      int32_t Sv[S];
+      uint32_t rmask;
+      merge_rq<R, S - R>(Rv, Qv, Sv, rmask);
+      update_func<R, S, false>(a, Sv, rmask, p, true, ls, nullptr);
+    } else {
+      gen_extend<L + 1, R, S>(a, gv, lo, hi, fbase, Rv, Qv, p, ls);
+    }
+  }
+}
+
+template <int R, int S>
+__global__ __launch_bounds__(256) void k_gen_apply(PeelArgs a, GenView gv,
+                                                   const uint32_t *__restrict__ F, uint64_t A) {
+  const int wv = threadIdx.x / kWave;
+  const int lane = lane_id();
+  LaneStats ls;
+  __shared__ uint32_t abuf[256 / kWave][2][kAppendCap];
+  Appender ap[2] = {{abuf[wv][0], 0u, a.Fnext, &a.ctr->next_size},
+                    {abuf[wv][1], 0u, a.Low, &a.ctr->low_size}};
+  // wave-uniform trip count: every lane reaches every append
+  for (uint64_t base = ((uint64_t)blockIdx.x * blockDim.x) + (uint64_t)wv * kWave; base < A;
+       base += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t i = base + lane;
+    bool in = i < A;
+    int32_t Rv[R];
+#pragma unroll
+    for (int q = 0; q < R; q++) Rv[q] = q;
+    int32_t Qv[S - R];
+#pragma unroll
+    for (int q = 0; q < S - R; q++) Qv[q] = R + q;
+    uint32_t p = 0;
+    int64_t lo = 0, hi = 0;
+    uint64_t fbase = 0;
+    if (in) {
+      const int64_t kx = seg_find(gv.aoff, (int64_t)gv.C1, i);
+      const int64_t f = seg_find(gv.ioff, gv.nF, (uint64_t)kx);
+      const int32_t v = gv.drv[f];
+      lo = a.g.rp[v];
+      hi = a.g.rp[v + 1];
+      fbase = gv.ioff[f];
+      const int32_t x = a.g.col[lo + (int64_t)((uint64_t)kx - fbase)];
+      const int32_t y = a.g.col[a.g.up[x] + (int64_t)(i - gv.aoff[kx])];
+      in = gen_in(a.g, gv, lo, hi, fbase, y);
+      p = F[f];
+#pragma unroll
+      for (int q = 0; q < R; q++) Rv[q] = gv.fv[f * R + q];
+      Qv[0] = x;
+      Qv[1] = y;
+    }
+    if constexpr (S - R == 2) {
+      int32_t Sv[S];
+      uint32_t rmask;
+      merge_rq<R, 2>(Rv, Qv, Sv, rmask);
+      update_func<R, S, true>(a, Sv, rmask, p, in, ls, ap);
+    } else {
+      if (in) gen_extend<2, R, S>(a, gv, lo, hi, fbase, Rv, Qv, p, ls);
+    }
+  }
+  ap[0].flush();
+  ap[1].flush();
+  stat_add(a.stats, kStatDec, ls.dec);
+  stat_add(a.stats, kStatDisc, ls.disc);
+  if (ls.err) atomicOr(&a.ctr->err, ls.err);
+}
+
+template <int R, int S>
+uint64_t gen_impl(const PeelArgs &a, const uint32_t *F, uint32_t nF, GenBufs *gb, hipStream_t st,
+                  hipEvent_t ev0, hipEvent_t ev1) {
+  if (gb->ioff.n < (size_t)nF + 1) gb->ioff.reset((size_t)nF + 1 + nF / 2);
+  if (gb->fv.n < (size_t)nF * R) gb->fv.reset(((size_t)nF + nF / 2) * R);
+  if (gb->drv.n < (size_t)nF) gb->drv.reset((size_t)nF + nF / 2);
+  hipLaunchKernelGGL(k_gen_bound<R>, dim3((unsigned)grid_for(nF, 256)), dim3(256), 0, st, a, F, nF,
+                     gb->ioff.get(), gb->fv.get(), gb->drv.get());
+  fill_u64(gb->ioff.get() + nF, 0, 1, st);
+  scan_exclusive_u64(gb->ioff.get(), gb->ioff.get(), (int64_t)nF + 1, st);
+  uint64_t C1 = 0;
+  hipMemcpyAsync(&C1, gb->ioff.get() + nF, 8, hipMemcpyDeviceToHost, st);
+  hipStreamSynchronize(st);
+  uint64_t A = 0;
+  GenView gv{gb->ioff.get(), gb->fv.get(), gb->drv.get(), nullptr, nullptr, nF, C1};
+  if (C1 > 0) {
+    if (gb->flag.n < C1) gb->flag.reset(C1 + C1 / 2);
+    if (gb->aoff.n < C1 + 1) gb->aoff.reset(C1 + 1 + C1 / 2);
+    gv.flag = gb->flag.get();
+    gv.aoff = gb->aoff.get();
+    hipLaunchKernelGGL(k_gen_member<R>, dim3((unsigned)grid_for(C1, 256, 1 << 16)), dim3(256), 0,
+                       st, a.g, gv, gb->flag.get(), gb->aoff.get());
+    fill_u64(gb->aoff.get() + C1, 0, 1, st);
+    scan_exclusive_u64(gb->aoff.get(), gb->aoff.get(), (int64_t)C1 + 1, st);
+    hipMemcpyAsync(&A, gb->aoff.get() + C1, 8, hipMemcpyDeviceToHost, st);
+    hipStreamSynchronize(st);
+  }
+  if (ev0) hipEventRecord(ev0, st);
+  if (A > 0)
+    hipLaunchKernelGGL((k_gen_apply<R, S>), dim3((unsigned)grid_for(A, 256, 1 << 16)), dim3(256),
+                       0, st, a, gv, F, A);
+  if (ev1) hipEventRecord(ev1, st);
+  return A;
+}
+
 template <int R, int S>
 void peel_impl(const PeelArgs &a, const uint32_t *F, uint32_t nF, hipStream_t st) {
   hipLaunchKernelGGL((k_peel<R, S>), dim3((unsigned)grid_for(nF, 4, 1 << 20)), dim3(256), 0, st,
@@ -894,6 +1114,31 @@ void peel_round(const OrientedGraph &g, int r, int s, const TableView &T, const 
     ND_PEEL_CASE(6, 7)
     default: break;
   }
+}
+
+#define ND_GEN_CASE(R_, S_) \
+  case (R_) * 16 + (S_): return gen_impl<R_, S_>(a, F, nF, gb, st, ev0, ev1);
+
+uint64_t peel_round_gen(const OrientedGraph &g, int r, int s, const TableView &T,
+                        const uint32_t *F, uint32_t nF, uint32_t t, uint32_t k, uint32_t kw,
+                        uint32_t *Fnext, uint32_t *Low, Counters *dctr,
+                        unsigned long long *stats, GenBufs *gb, hipStream_t st, hipEvent_t ev0,
+                        hipEvent_t ev1) {
+  if (!nF) {
+    if (ev0) hipEventRecord(ev0, st);
+    if (ev1) hipEventRecord(ev1, st);
+    return 0;
+  }
+  PeelArgs a{g.view(), T, t, k, Fnext, dctr, stats, kw, Low};
+  switch (r * 16 + s) {
+    ND_GEN_CASE(1, 3) ND_GEN_CASE(1, 4) ND_GEN_CASE(1, 5) ND_GEN_CASE(1, 6) ND_GEN_CASE(1, 7)
+    ND_GEN_CASE(2, 4) ND_GEN_CASE(2, 5) ND_GEN_CASE(2, 6) ND_GEN_CASE(2, 7)
+    ND_GEN_CASE(3, 5) ND_GEN_CASE(3, 6) ND_GEN_CASE(3, 7)
+    ND_GEN_CASE(4, 6) ND_GEN_CASE(4, 7)
+    ND_GEN_CASE(5, 7)
+    default: break;
+  }
+  return 0;
 }
 
 void count_direct(const OrientedGraph &g, int r, const TableView &T, const FastIndex &fx,

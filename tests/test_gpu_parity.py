@@ -136,6 +136,14 @@ def test_rmat_small(r, s, generic):
     check_against_oracle(g, r, s, generic=generic)
 
 
+@pytest.mark.parametrize("r,s", [(1, 3), (2, 4), (3, 5), (1, 4), (2, 5), (3, 6)])
+def test_rmat_flattened_update(r, s):
+    """s >= r+2 peels through the flattened candidate / out-arc passes; hub
+    r-cliques with large common neighbourhoods are shared across waves."""
+    g = inputs.rmat(11, 8, 77)
+    check_against_oracle(g, r, s)
+
+
 @pytest.mark.parametrize("r,s", [(3, 4), (4, 5), (2, 4)])
 def test_chung_lu_small(r, s):
     g = inputs.chung_lu_planted(3000, 8.0, 2.1, 4, 8, 16, 77)
