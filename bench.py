@@ -132,9 +132,15 @@ def main():
     c = comb(s, r)
     count_bytes = SLOT_BYTES * c * n_s * len(runs)
     peel_bytes = SLOT_BYTES * (c - 1) * n_s * len(runs)
-    fast = s == r + 1 and r >= 2
-    peel_name = f"k_peel_fast<{r}>" if fast else f"k_peel<{r},{s}>"
-    count_name = f"k_count_direct<{r}>" if fast else f"k_list_bitmap<{s},*,CountOp<{r},{s}>>"
+    # the kernels the library times with HIP events on its own stream:
+    # s = r+1 (r >= 2) peels through k_apply and counts directly; s >= r+2
+    # peels through k_gen_apply and counts by listing; (1,2) uses k_peel
+    if s == r + 1 and r >= 2:
+        peel_name = f"k_apply<{r}>"
+        count_name = "k_count_direct<2>" if r == 2 else f"k_count_wave<{r}>"
+    else:
+        peel_name = f"k_gen_apply<{r}, {s}>" if s >= r + 2 else f"k_peel<{r}, {s}>"
+        count_name = f"k_list_bitmap<{s}, W, CountOp<{r}, {s}>>"
     if peel_ms >= cnt_ms:
         kern, t_ms, nbytes, launches = peel_name, peel_ms, peel_bytes, peel_launches
     else:
