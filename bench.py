@@ -69,11 +69,11 @@ def main():
     ap.add_argument("--workload", default="rmat18_34",
                     choices=sorted(WORKLOADS) + [BATCH_WORKLOAD, SERVE_WORKLOAD])
     ap.add_argument("--batch-count", type=int, default=4096)
-    ap.add_argument("--rates", default="50,100,200,400",
+    ap.add_argument("--rates", default="5,10,20,40",
                     help="serving: Poisson arrival rates (jobs/s) to sweep")
-    ap.add_argument("--serve-jobs", type=int, default=1000, help="serving: measured jobs per rate")
-    ap.add_argument("--serve-warmup", type=int, default=100, help="serving: warm-up jobs per rate")
-    ap.add_argument("--max-scale", type=int, default=14, help="serving: largest rMAT scale")
+    ap.add_argument("--serve-jobs", type=int, default=300, help="serving: measured jobs per rate")
+    ap.add_argument("--serve-warmup", type=int, default=30, help="serving: warm-up jobs per rate")
+    ap.add_argument("--max-scale", type=int, default=11, help="serving: largest rMAT scale")
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--hbm-budget-gb", type=float, default=200.0)
     ap.add_argument("--seed", type=int, default=None)
@@ -295,6 +295,8 @@ def _replay(nd, jobs, dev, workers, budget):
             _, _, st, qms, sms = nd.nd_server_result(sv.handle, j, jobs[i].r, copy=False)
             nd.nd_server_release(sv.handle, j)
             out[i] = (qms + sms, st, sms)
+            if (i + 1) % 100 == 0:
+                log(f"[bench]   {i + 1}/{len(jobs)} jobs done ({workers} workers)")
 
     th = threading.Thread(target=collect)
     th.start()
