@@ -72,7 +72,6 @@ struct StreamScope {
 };
 
 // levels covered by the window list of the bucket structure
-constexpr uint32_t kWindowLevels = 16;
 
 int64_t grid_for(int64_t n, int threads, int64_t cap = 65536) {
   int64_t b = (n + threads - 1) / threads;
@@ -489,105 +488,24 @@ nd_status nd_run(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *cou
                   "copy bitmaps");
     }
     tm.mark(1, st);
-    // ---- bucket init + peel
-    // Live r-cliques are kept in two lists: Lw (count <= kw, the level
-    // window) and Lh (count > kw).  A level advance scans only Lw; Lh is
-    // re-partitioned only when the window holds no live entry.  Decrements
-    // that bring a count to kw append the r-clique to Lw, so Lw always
-    // holds every live r-clique with count <= kw.
-    const size_t cap = p->n_r ? p->n_r : 1;
-    DevBuf<uint32_t> F(cap), Fn(cap), Lh(cap), Lh2(cap), Lw(cap), Lw2(cap);
-    if (p->n_r)
-      hip_check(hipMemcpyAsync(Lh.get(), p->occ.get(), 4 * p->n_r, hipMemcpyDeviceToDevice, st),
-                "copy");
-    SplitBufs sb;
-    GenBufs gb;
-    // s >= r + 2 peels through the flattened passes unless the one-wave
-    // walker is asked for
-    const bool gen = !p->fast && s >= r + 2 && p->opt.path == 0;
-    uint64_t nH = p->n_r, nW = 0, finished = 0;
-    uint32_t k = 0, kw = 0, t = 0, nF = 0;
-    p->round_sizes.clear();
-    p->round_k.clear();
-    p->k_advances = 0;
-    bool first = true;
-    while (finished < p->n_r) {
-      if (nF == 0) {
-        bool advanced = false;
-        if (nW > 0) {  // next level inside the window
-          live_min(Lw.get(), (uint32_t)nW, p->slots.get(), dc, st);
-          const uint32_t m = read_dev(&dc->live_min, st);
-          if (m != 0xFFFFFFFFu) {
-            if (m > k) k = m;
-            live_partition(Lw.get(), (uint32_t)nW, p->slots.get(), k, 0xFFFFFFFEu, F.get(),
-                           Lw2.get(), Lh2.get(), dc, st);
-            const Counters h2 = read_dev(dc, st);
-            nF = h2.next_size;
-            nW = h2.low_size;
-            std::swap(Lw.p, Lw2.p);
-            advanced = true;
-          }
-        }
-        if (!advanced) {  // window exhausted: open a new one from the high list
-          live_min(Lh.get(), (uint32_t)nH, p->slots.get(), dc, st);
-          const uint32_t m = read_dev(&dc->live_min, st);
-          if (m == 0xFFFFFFFFu) fail(ND_EHIP, "no live r-clique left before the peel finished");
-          if (m > k) k = m;
-          kw = k + kWindowLevels;
-          live_partition(Lh.get(), (uint32_t)nH, p->slots.get(), k, kw, F.get(), Lw.get(),
-                         Lh2.get(), dc, st);
-          const Counters h2 = read_dev(dc, st);
-          nF = h2.next_size;
-          nW = h2.low_size;
-          nH = h2.high_size;
-          std::swap(Lh.p, Lh2.p);
-        }
-        p->k_advances++;
-        if (first) tm.mark(2, st);
-        first = false;
-        if (nF == 0) fail(ND_EHIP, "empty bucket after a level advance");
-      }
-      stamp_frontier(F.get(), nF, p->slots.get(), t, st);
-      fill_u32(&dc->next_size, 0, 1, st);
-      fill_u32(&dc->low_size, (uint32_t)nW, 1, st);  // window appends continue after nW
-      if (p->fast) {
-        peel_round_split(p->g, r, p->table(), p->fx, F.get(), nF, t, k, kw, Fn.get(), Lw.get(),
-                         dc, p->stats.get(), &sb, st, timing ? kt.ev[2] : nullptr,
-                         timing ? kt.ev[3] : nullptr);
-      } else if (gen) {
-        peel_round_gen(p->g, r, s, p->table(), F.get(), nF, t, k, kw, Fn.get(), Lw.get(), dc,
-                       p->stats.get(), &gb, st, timing ? kt.ev[2] : nullptr,
-                       timing ? kt.ev[3] : nullptr);
-      } else {
-        if (timing) kt.mark(2, st);
-        peel_round(p->g, r, s, p->table(), F.get(), nF, t, k, kw, Fn.get(), Lw.get(), dc,
-                   p->stats.get(), st);
-        if (timing) kt.mark(3, st);
-      }
-      if (p->fast && r == 3) clear_alive(p->g, p->table(), p->fx, F.get(), nF, st);
-      p->round_sizes.push_back(nF);
-      p->round_k.push_back(k);
-      finished += nF;
-      {
-        const Counters h3 = read_dev(dc, st);
-        nF = h3.next_size;
-        nW = h3.low_size;
-      }
-      if (timing) {
-        peel_kernel_ms += kt.between(2, 3);
-        peel_launches++;
-      }
-      std::swap(F.p, Fn.p);
-      t++;
+    // ---- bucket init + peel, driven by the device (the host polls the
+    // round state every few rounds)
+    const int path = p->fast ? 1 : (s >= r + 2 && p->opt.path == 0 ? 2 : 0);
+    PeelResult pr;
+    DevBuf<uint32_t> kround;
+    const uint32_t perr =
+        peel_all(p->g, r, s, path, p->table(), p->fast ? &p->fx : nullptr, p->occ.get(), p->n_r,
+                 dc, p->stats.get(), timing, st, tm.ev[2], &kround, &pr);
+    if (perr) fail(ND_EHIP, "peel failed (flags %u)", perr);
+    p->round_sizes = pr.sizes;
+    p->round_k = pr.levels;
+    p->k_advances = pr.advances;
+    if (timing) {
+      peel_kernel_ms = pr.apply_ms;
+      peel_launches = pr.apply_launches;
     }
-    if (first) tm.mark(2, st);
     tm.mark(3, st);
     // ---- emit
-    DevBuf<uint32_t> kround(p->round_k.size() ? p->round_k.size() : 1);
-    if (!p->round_k.empty())
-      hip_check(hipMemcpyAsync(kround.get(), p->round_k.data(), 4 * p->round_k.size(),
-                               hipMemcpyHostToDevice, st),
-                "copy levels");
     stats_collect(p->stats.get(), dc, st);
     emit(r, p->occ.get(), p->n_r, p->table(), p->g.new2old.get(), kround.get(),
          (uint32_t)p->round_k.size(), rcl_dev, kappa_dev, st);

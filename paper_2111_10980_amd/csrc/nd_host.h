@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "nd_internal.h"
 
 namespace nd {
@@ -117,50 +119,22 @@ void count_direct(const OrientedGraph &g, int r, const TableView &T, const FastI
                   const uint32_t *occ, uint64_t n_r, Counters *dctr, hipStream_t st);
 void build_slot_loc(const OrientedGraph &g, int r, const TableView &T, uint64_t n_slots,
                     FastIndex *fx, hipStream_t st);
-// round scratch of the expand/apply peel, grown on demand and kept by the run
-// s >= r + 2: a round's update flattened over candidates and out-arcs
-struct GenBufs {
-  DevBuf<uint64_t> ioff;  // candidate bounds per frontier entry, then offsets
-  DevBuf<int32_t> fv;     // decoded frontier r-cliques
-  DevBuf<int32_t> drv;    // driver (fewest neighbours) of each
-  DevBuf<uint8_t> flag;   // candidate in the common neighbourhood
-  DevBuf<uint64_t> aoff;  // out-degree of each member, then offsets
+// ---- peel loop (nd_peel.hip)
+struct PeelResult {
+  std::vector<uint64_t> sizes;   // |A_t| per round
+  std::vector<uint32_t> levels;  // k per round
+  uint32_t advances = 0;         // level advances
+  float apply_ms = 0;            // update-pass kernel time (timing only)
+  uint32_t apply_launches = 0;
 };
-// returns the number of out-arcs examined; ev0/ev1 (nullable) bracket the
-// apply kernel
-uint64_t peel_round_gen(const OrientedGraph &g, int r, int s, const TableView &T,
-                        const uint32_t *F, uint32_t nF, uint32_t t, uint32_t k, uint32_t kw,
-                        uint32_t *Fnext, uint32_t *Low, Counters *dctr,
-                        unsigned long long *stats, GenBufs *gb, hipStream_t st, hipEvent_t ev0,
-                        hipEvent_t ev1);
-
-struct SplitBufs {
-  DevBuf<uint64_t> off;  // frontier candidate bounds, then their prefix sum
-  DevBuf<int32_t> fv;    // decoded frontier r-cliques, r ids each
-  DevBuf<int2> rec;      // (frontier index, candidate x or -1)
-};
-// returns the number of candidate records; ev0/ev1 (nullable) bracket the
-// apply kernel
-// Fnext receives r-cliques reaching level k, Low those entering (k, kw]
-uint64_t peel_round_split(const OrientedGraph &g, int r, const TableView &T, const FastIndex &fx,
-                          const uint32_t *F, uint32_t nF, uint32_t t, uint32_t k, uint32_t kw,
-                          uint32_t *Fnext, uint32_t *Low, Counters *dctr,
-                          unsigned long long *stats, SplitBufs *sb, hipStream_t st,
-                          hipEvent_t ev0, hipEvent_t ev1);
-// r = 3: clear the alive bits of the triangles peeled in this round
-void clear_alive(const OrientedGraph &g, const TableView &T, const FastIndex &fx,
-                 const uint32_t *F, uint32_t nF, hipStream_t st);
-
-// ---- peel (nd_peel.hip)
-void stamp_frontier(const uint32_t *F, uint32_t nF, Slot *slots, uint32_t t, hipStream_t st);
-void peel_round(const OrientedGraph &g, int r, int s, const TableView &T, const uint32_t *F,
-                uint32_t nF, uint32_t t, uint32_t k, uint32_t kw, uint32_t *Fnext, uint32_t *Low,
-                Counters *dctr, unsigned long long *stats, hipStream_t st);
-void live_min(const uint32_t *L, uint32_t nL, const Slot *slots, Counters *dctr,
-              hipStream_t st);
-// F: count <= k; Low: k < count <= kw; High: count > kw (peeled entries dropped)
-void live_partition(const uint32_t *L, uint32_t nL, const Slot *slots, uint32_t k, uint32_t kw,
-                    uint32_t *F, uint32_t *Low, uint32_t *High, Counters *dctr, hipStream_t st);
+// Whole bucketed peel (Algorithm 2 after the count) on the device.  path: 0
+// the one-wave walker, 1 the s = r+1 expand/apply passes (needs fx), 2 the
+// flattened s >= r+2 passes.  kround receives the level of every round (for
+// emit).  Returns 0 or kErr* bits.
+uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableView &T,
+                  const FastIndex *fx, const uint32_t *occ, uint64_t n_r, Counters *dc,
+                  unsigned long long *stats, bool timing, hipStream_t st, hipEvent_t ev_first,
+                  DevBuf<uint32_t> *kround, PeelResult *res);
 void occupied_list(const Slot *slots, uint64_t n_slots, uint32_t *occ, hipStream_t st);
 void gather_counts(const uint32_t *occ, uint64_t n_r, const Slot *slots, uint32_t *out,
                    hipStream_t st);

@@ -43,7 +43,13 @@ struct TableView {
 };
 
 // Device-side error flags (bit set in a device word, read by the host).
-enum : uint32_t { kErrGraph = 1u, kErrLookup = 2u, kErrOverflow = 4u, kErrTable = 8u };
+enum : uint32_t {
+  kErrGraph = 1u,
+  kErrLookup = 2u,
+  kErrOverflow = 4u,
+  kErrTable = 8u,
+  kErrBucket = 16u,  // a level advance found no live r-clique, or an empty bucket
+};
 
 // ----------------------------------------------------------------- helpers
 
@@ -329,6 +335,39 @@ struct Counters {
 };
 
 
+
+// Device-resident state of the peel loop (Algorithm 2's bucket structure B,
+// the level k, the round number and the frontier).  Small control kernels
+// advance it and every round kernel reads its parameters from it, so the
+// host can queue rounds back to back and only read it now and then.
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint32_t kWindowLevels = 16;  // levels k+1..k+16 kept in the window list
+
+struct RoundCtl {
+  // parameters of the current round, set by k_round_begin
+  const uint32_t *F;   // frontier A_t
+  uint32_t *Fnext;     // r-cliques whose count reaches k (next frontier)
+  uint32_t *Low;       // r-cliques whose count enters the window (k, kw]
+  // list storage: two buffers each, the live one picked by sel*
+  uint32_t *bufF[2], *bufW[2], *bufH[2];
+  uint32_t *trace_size;  // per round: |A_t|
+  uint32_t *trace_k;     // per round: k
+  uint64_t n_r, finished;
+  uint64_t total, cap;     // record slots allocated this round / capacity
+  uint64_t total2;         // second record list (member records)
+  uint64_t total3, cap3;   // third list (out-arcs of members) / capacity
+  uint64_t need;           // capacity asked for when a round halted (halt 1: total, 4: total3)
+  uint32_t t, k, kw, nF;   // round, level, window top, |A_t|
+  uint32_t nW, nH;         // window list and high list sizes
+  uint32_t selF, selW, selH;
+  uint32_t done;           // every r-clique peeled
+  uint32_t halt;           // 1: records, 2: trace, 4: arcs; kernels skip until cleared
+  uint32_t err;            // kErr* bits
+  uint32_t mw, mh;         // live minima of the window / high list (advance)
+  uint32_t cF, cW, cH;     // partition output sizes (advance)
+  uint32_t advances;
+  uint32_t trace_cap;
+};
 
 // Statistics accumulated by many waves go to kStatLines counter lines (one
 // 128-byte line each, picked by block index) and are summed once at the

@@ -20,6 +20,13 @@
 // wave (the role of the paper's per-thread list buffer).  When a round
 // leaves no frontier, the level advances to the minimum live count, found by
 // a reduction over a compacted list of live r-cliques.
+#include <stddef.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <chrono>
+#include <vector>
+
 #include "nd_host.h"
 
 namespace nd {
@@ -50,6 +57,57 @@ struct LaneStats {
 
 constexpr int kAppendCap = 512;  // LDS entries per wave for next-frontier appends
 using Appender = WaveAppender<kAppendCap>;
+
+// Round kernels run only while rounds remain and the host has not been asked
+// to step in (the test is uniform over the grid).
+__device__ __forceinline__ bool rc_idle(const RoundCtl *rc) { return (rc->done | rc->halt) != 0; }
+
+// The constant part of the arguments (graph, table, counters) comes by value;
+// the round's level, window, round number and output lists from the control
+// block.
+__device__ __forceinline__ PeelArgs round_args(PeelArgs a, const RoundCtl *rc) {
+  a.t = rc->t;
+  a.k = rc->k;
+  a.kw = rc->kw;
+  a.Fnext = rc->Fnext;
+  a.Low = rc->Low;
+  return a;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint64_t y = __shfl_up(v, off);
+    if (lane >= off) v += y;
+  }
+  return v;
+}
+
+// Block-wide allocation from a global counter with one atomic per block:
+// every thread of the (256-thread) block asks for `want` entries and gets
+// the start of its own range.  Called by all threads of the block together.
+__device__ __forceinline__ uint64_t block_alloc(uint64_t want, unsigned long long *counter) {
+  __shared__ uint64_t wsum[256 / kWave];
+  __shared__ uint64_t base;
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  const uint64_t incl = wave_incl_scan_u64(want);
+  if (lane == kWave - 1) wsum[w] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t tot = 0;
+    for (int v = 0; v < 256 / kWave; v++) {
+      const uint64_t c = wsum[v];
+      wsum[v] = tot;
+      tot += c;
+    }
+    base = tot ? atomicAdd(counter, (unsigned long long)tot) : 0ull;
+  }
+  __syncthreads();
+  const uint64_t r = base + wsum[w] + incl - want;
+  __syncthreads();
+  return r;
+}
 
 // Update-Func for one s-clique S (sorted) found from the peeled r-clique at
 // slot p, whose vertices occupy the positions in rmask.  Called by every
@@ -153,8 +211,11 @@ __device__ void extend_q(const PeelArgs &a, const int32_t (&Rv)[R], int32_t (&Q)
 
 // One wave per peeled r-clique (Algorithm 2, Update).
 template <int R, int S>
-__global__ __launch_bounds__(256) void k_peel(PeelArgs a, const uint32_t *__restrict__ F,
-                                              uint32_t nF) {
+__global__ __launch_bounds__(256) void k_peel(PeelArgs base, const RoundCtl *__restrict__ rc) {
+  if (rc_idle(rc)) return;
+  const PeelArgs a = round_args(base, rc);
+  const uint32_t *__restrict__ F = rc->F;
+  const uint32_t nF = rc->nF;
   const int wpb = blockDim.x / kWave;
   const int lane = lane_id();
   LaneStats ls;
@@ -240,7 +301,10 @@ __device__ __forceinline__ int64_t lower_pos(const int32_t *__restrict__ a, int6
 // cleared after the round that peels it, so the AND of two alive rows lists
 // only candidates whose two triangles through v1 were not peeled earlier.
 __global__ void k_clear_alive(GraphView g, TableView T, FastView fx,
-                              const uint32_t *__restrict__ F, uint32_t nF) {
+                              const RoundCtl *__restrict__ rc) {
+  if (rc_idle(rc)) return;
+  const uint32_t *__restrict__ F = rc->F;
+  const uint32_t nF = rc->nF;
   for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < nF;
        it += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t p = F[it];
@@ -410,21 +474,28 @@ __device__ __forceinline__ bool front_positions(const PeelArgs &a, uint64_t lc,
   return found;
 }
 
+// Also stamps A_t with t (the apply pass of the same round reads the stamps)
+// and allocates each r-clique's record range with one atomic per block.
 template <int R>
-__global__ __launch_bounds__(256) void k_expand_bound(PeelArgs a, FastView fx,
+__global__ __launch_bounds__(256) void k_expand_bound(PeelArgs base, RoundCtl *rc, FastView fx,
                                                       const uint64_t *__restrict__ loc,
-                                                      const uint32_t *__restrict__ F, uint32_t nF,
-                                                      uint64_t *ub, int32_t *fv) {
-  for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nF;
-       f += (int64_t)gridDim.x * blockDim.x) {
+                                                      uint64_t *off, uint32_t *len, int32_t *fv) {
+  if (rc_idle(rc)) return;
+  const PeelArgs a = round_args(base, rc);
+  const uint32_t *__restrict__ F = rc->F;
+  const uint32_t nF = rc->nF;
+  for (int64_t f0 = (int64_t)blockIdx.x * 256; f0 < nF; f0 += (int64_t)gridDim.x * 256) {
+    const int64_t f = f0 + threadIdx.x;
+    uint64_t bound = 0;
+    if (f < nF) {
     const uint32_t p = F[f];
     const Slot sl = a.T.slots[p];
+    a.T.slots[p].stamp = a.t;
     int32_t Rv[R];
     Rv[0] = a.T.v1[p];
     decode_key<R>(sl.key, a.T.bits, Rv);
 #pragma unroll
     for (int i = 0; i < R; i++) fv[f * R + i] = Rv[i];
-    uint64_t bound = 0;
     if (sl.cnt != 0) {  // otherwise every s-clique of R is already gone
       const int64_t o = a.g.up[Rv[0]];
       const int d = (int)(a.g.rp[Rv[0] + 1] - o);
@@ -454,23 +525,39 @@ __global__ __launch_bounds__(256) void k_expand_bound(PeelArgs a, FastView fx,
         atomicOr(&a.ctr->err, kErrLookup);
       }
     }
-    ub[f] = bound;
+    }
+    const uint64_t at = block_alloc(bound, (unsigned long long *)&rc->total);
+    if (f < nF) {
+      off[f] = at;
+      len[f] = (uint32_t)bound;
+    }
   }
 }
 
 template <int R>
-__global__ __launch_bounds__(256) void k_expand(PeelArgs a, FastView fx,
+__global__ __launch_bounds__(256) void k_expand(PeelArgs base, RoundCtl *rc, FastView fx,
                                                 const uint64_t *__restrict__ loc,
-                                                const uint32_t *__restrict__ F, uint32_t nF,
                                                 const uint64_t *__restrict__ off,
+                                                const uint32_t *__restrict__ len,
                                                 const int32_t *__restrict__ fv, int2 *rec) {
+  if (rc_idle(rc)) return;
+  if (rc->total > rc->cap) {  // records do not fit: the host grows the buffer, reruns the round
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      rc->need = rc->total;
+      rc->halt = 1;
+    }
+    return;
+  }
+  const PeelArgs a = round_args(base, rc);
+  const uint32_t *__restrict__ F = rc->F;
+  const uint32_t nF = rc->nF;
   const int wpb = blockDim.x / kWave;
   const int wv = threadIdx.x / kWave;
   const int lane = lane_id();
   __shared__ int32_t lbuf[256 / kWave][R == 3 ? kListCap : 1];
   for (int64_t f = (int64_t)blockIdx.x * wpb + wv; f < nF; f += (int64_t)gridDim.x * wpb) {
     const uint64_t b = off[f];
-    const uint64_t total = off[f + 1] - b;
+    const uint64_t total = len[f];
     if (total == 0) continue;
     const uint32_t p = F[f];
     int32_t Rv[R];
@@ -569,9 +656,13 @@ __global__ __launch_bounds__(256) void k_expand(PeelArgs a, FastView fx,
 }
 
 template <int R>
-__global__ __launch_bounds__(256) void k_apply(PeelArgs a, const int2 *__restrict__ rec,
-                                               uint64_t total, const uint32_t *__restrict__ F,
+__global__ __launch_bounds__(256) void k_apply(PeelArgs base, const RoundCtl *__restrict__ rc,
+                                               const int2 *__restrict__ rec,
                                                const int32_t *__restrict__ fv) {
+  if (rc_idle(rc)) return;
+  const PeelArgs a = round_args(base, rc);
+  const uint32_t *__restrict__ F = rc->F;
+  const uint64_t total = rc->total;
   const int wv = threadIdx.x / kWave;
   const int lane = lane_id();
   LaneStats ls;
@@ -728,36 +819,70 @@ __global__ void k_make_loc(GraphView g, TableView T, uint64_t n_slots, uint64_t 
   }
 }
 
-__global__ void k_stamp(const uint32_t *__restrict__ F, uint32_t nF, Slot *slots, uint32_t t) {
+// ---------------------------------------------------------- round control
+// One round is queued as
+//   k_adv_min<false>, k_adv_min<true>, k_adv_partition, k_adv_finish
+//       level advance; they act only when the round starts with an empty
+//       frontier (B.next_bucket of Algorithm 2);
+//   k_round_begin            one thread: the round's lists and counters;
+//   the update passes of the path (the first one stamps A_t with t);
+//   [k_clear_alive]          r = 3 liveness bitmaps;
+//   k_round_end              one thread: trace, finished += |A_t|, next frontier.
+// Every kernel returns at once once the peel has finished or halted, so the
+// host may queue rounds past the last one and read the state only now and
+// then.
+
+__global__ void k_stamp(const RoundCtl *__restrict__ rc, Slot *slots) {
+  if (rc_idle(rc)) return;
+  const uint32_t *__restrict__ F = rc->F;
+  const uint32_t nF = rc->nF, t = rc->t;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nF;
        i += (int64_t)gridDim.x * blockDim.x)
     slots[F[i]].stamp = t;
 }
 
-__global__ __launch_bounds__(256) void k_live_min(const uint32_t *__restrict__ L, uint32_t nL,
-                                                  const Slot *__restrict__ slots, uint32_t *out) {
-  uint32_t m = 0xFFFFFFFFu;
+// Minimum count over the live entries of the window list (kHigh = false),
+// or of the high list once the window holds no live entry.
+template <bool kHigh>
+__global__ __launch_bounds__(256) void k_adv_min(RoundCtl *rc, const Slot *__restrict__ slots) {
+  if (rc_idle(rc) || rc->nF != 0) return;
+  if (kHigh ? (rc->nW != 0 && rc->mw != kNone) : rc->nW == 0) return;
+  const uint32_t *__restrict__ L = kHigh ? rc->bufH[rc->selH] : rc->bufW[rc->selW];
+  const uint32_t nL = kHigh ? rc->nH : rc->nW;
+  uint32_t m = kNone;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nL;
        i += (int64_t)gridDim.x * blockDim.x) {
     const Slot s = slots[L[i]];
     if (s.stamp == kLive && s.cnt < m) m = s.cnt;
   }
   m = wave_min_u32(m);
-  if (lane_id() == 0 && m != 0xFFFFFFFFu) atomicMin(out, m);
+  if (lane_id() == 0 && m != kNone) atomicMin(kHigh ? &rc->mh : &rc->mw, m);
 }
 
-// Three-way partition of a list of live r-clique slots by count c:
-// c <= k -> F (this level's frontier), k < c <= kw -> Low (level window),
-// c > kw -> High; peeled entries are dropped.  Each block compacts a tile
-// of 256 x 16 entries with one atomic per output per tile (a single global
-// counter per wave would serialise in L2).
+// Three-way partition of the list the advance works on, by count c:
+// c <= k -> the frontier, k < c <= kw -> the window list, c > kw -> the
+// high list; peeled entries are dropped.  Inside the window (kw = max) the
+// window list is compacted into its other buffer; when a new window is
+// opened the high list is split.  Each block compacts a tile of 256 x 16
+// entries with one atomic per output per tile (a single global counter per
+// wave would serialise in L2).
 constexpr int kPartThreads = 256;
 constexpr int kPartItems = 16;
 
-__global__ __launch_bounds__(kPartThreads) void k_live_partition(
-    const uint32_t *__restrict__ L, uint32_t nL, const Slot *__restrict__ slots, uint32_t k,
-    uint32_t kw, uint32_t *F, uint32_t *nF, uint32_t *Lo, uint32_t *nLo, uint32_t *Hi,
-    uint32_t *nHi) {
+__global__ __launch_bounds__(kPartThreads) void k_adv_partition(RoundCtl *rc,
+                                                                const Slot *__restrict__ slots) {
+  if (rc_idle(rc) || rc->nF != 0) return;
+  const bool win = rc->nW != 0 && rc->mw != kNone;
+  const uint32_t mn = win ? rc->mw : rc->mh;
+  if (mn == kNone) return;  // k_adv_finish reports it
+  const uint32_t k = rc->k > mn ? rc->k : mn;
+  const uint32_t kw = win ? 0xFFFFFFFEu : k + kWindowLevels;
+  const uint32_t *__restrict__ L = win ? rc->bufW[rc->selW] : rc->bufH[rc->selH];
+  const uint32_t nL = win ? rc->nW : rc->nH;
+  uint32_t *F = rc->bufF[rc->selF];
+  uint32_t *Lo = win ? rc->bufW[rc->selW ^ 1u] : rc->bufW[rc->selW];
+  uint32_t *Hi = rc->bufH[rc->selH ^ 1u];
+  uint32_t *ctr3[3] = {&rc->cF, &rc->cW, &rc->cH};
   __shared__ uint32_t wsum[3][kPartThreads / kWave];
   __shared__ uint32_t base[3];
   const int tid = threadIdx.x, w = tid / kWave;
@@ -794,8 +919,7 @@ __global__ __launch_bounds__(kPartThreads) void k_live_partition(
         wsum[tid][v] = tot;
         tot += c;
       }
-      uint32_t *ctr = tid == 0 ? nF : (tid == 1 ? nLo : nHi);
-      base[tid] = tot ? atomicAdd(ctr, tot) : 0u;
+      base[tid] = tot ? atomicAdd(ctr3[tid], tot) : 0u;
     }
     __syncthreads();
     uint32_t at[3];
@@ -808,6 +932,66 @@ __global__ __launch_bounds__(kPartThreads) void k_live_partition(
       if (m[2] >> j & 1u) Hi[at[2]++] = p[j];
     }
     __syncthreads();
+  }
+}
+
+// One thread: k <- max(k, minimum), new list sizes, swap the list buffers.
+__global__ void k_adv_finish(RoundCtl *rc) {
+  if (rc_idle(rc) || rc->nF != 0) return;
+  const bool win = rc->nW != 0 && rc->mw != kNone;
+  const uint32_t mn = win ? rc->mw : rc->mh;
+  if (mn == kNone || rc->cF == 0) {  // no live r-clique left, or an empty bucket
+    rc->err |= kErrBucket;
+    rc->halt = 3;
+    return;
+  }
+  rc->k = rc->k > mn ? rc->k : mn;
+  if (win) {
+    rc->selW ^= 1u;
+  } else {
+    rc->kw = rc->k + kWindowLevels;
+    rc->nH = rc->cH;
+    rc->selH ^= 1u;
+  }
+  rc->nW = rc->cW;
+  rc->nF = rc->cF;
+  rc->advances++;
+  rc->mw = kNone;
+  rc->mh = kNone;
+  rc->cF = rc->cW = rc->cH = 0;
+}
+
+__global__ void k_round_begin(RoundCtl *rc, Counters *dc) {
+  if (rc_idle(rc)) return;
+  if (rc->t >= rc->trace_cap) {  // the host grows the round trace
+    rc->halt = 2;
+    return;
+  }
+  const uint32_t sF = rc->selF;
+  rc->F = rc->bufF[sF];
+  rc->Fnext = rc->bufF[sF ^ 1u];
+  rc->Low = rc->bufW[rc->selW];
+  rc->total = 0;
+  rc->total2 = 0;
+  rc->total3 = 0;
+  dc->next_size = 0;
+  dc->low_size = rc->nW;  // window appends continue after the live entries
+}
+
+__global__ void k_round_end(RoundCtl *rc, const Counters *dc) {
+  if (rc_idle(rc)) return;
+  rc->trace_size[rc->t] = rc->nF;
+  rc->trace_k[rc->t] = rc->k;
+  rc->finished += rc->nF;
+  rc->t++;
+  rc->nF = dc->next_size;
+  rc->nW = dc->low_size;
+  rc->selF ^= 1u;
+  if (rc->finished > rc->n_r) {
+    rc->err |= kErrBucket;
+    rc->halt = 3;
+  } else if (rc->finished == rc->n_r) {
+    rc->done = 1;
   }
 }
 
@@ -869,85 +1053,137 @@ __global__ void k_emit(const uint32_t *__restrict__ occ, uint64_t n_r, TableView
 // member with the fewest neighbours) adjacent to every other member, kept
 // as one flag per position of that row.  Q is listed from its lowest vertex
 // x along the out-arcs of x, so each s-clique of R is met exactly once.
-//   bound:  candidates of each peeled R = the driver's degree;
-//   member: a thread per candidate x: x in I(R)? and its out-degree;
-//   apply:  a thread per out-arc (x, y) of a member: y in I(R) closes
-//           R + {x, y} (s = r + 2) or starts a deeper extension.
-
-// Segment of x in a nondecreasing offset array: the last i < n with
-// off[i] <= x (empty segments are skipped).
-__device__ __forceinline__ int64_t seg_find(const uint64_t *__restrict__ off, int64_t n,
-                                            uint64_t x) {
-  int64_t lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (off[mid] <= x) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
-struct GenView {
-  const uint64_t *__restrict__ ioff;  // nF + 1 candidate offsets
-  const int32_t *__restrict__ fv;     // nF * R decoded r-cliques
-  const int32_t *__restrict__ drv;    // nF drivers
-  const uint8_t *__restrict__ flag;   // C1 membership flags
-  const uint64_t *__restrict__ aoff;  // C1 + 1 arc offsets
-  uint32_t nF;
-  uint64_t C1;
-};
+//   bound:  thread per peeled R: stamp it, pick the driver, allocate one
+//           flag per position of the driver's row;
+//   member: wave per peeled R: flag the positions in I(R), list the
+//           members that have out-arcs;
+//   apply:  the out-arcs (x, y) of 64 members spread over a wave: y in I(R)
+//           closes R + {x, y} (s = r + 2) or starts a deeper extension.
 
 template <int R>
-__global__ __launch_bounds__(256) void k_gen_bound(PeelArgs a, const uint32_t *__restrict__ F,
-                                                   uint32_t nF, uint64_t *ub, int32_t *fv,
-                                                   int32_t *drv) {
-  for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nF;
-       f += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t p = F[f];
-    const Slot sl = a.T.slots[p];
-    int32_t Rv[R];
-    Rv[0] = a.T.v1[p];
-    decode_key<R>(sl.key, a.T.bits, Rv);
-    int32_t best_v = Rv[0];
-    int64_t best = a.g.rp[Rv[0] + 1] - a.g.rp[Rv[0]];
+__global__ __launch_bounds__(256) void k_gen_bound(PeelArgs base, RoundCtl *rc, uint64_t *ioff,
+                                                   uint32_t *ilen, int32_t *fv, int32_t *drv) {
+  if (rc_idle(rc)) return;
+  const PeelArgs a = round_args(base, rc);
+  const uint32_t *__restrict__ F = rc->F;
+  const uint32_t nF = rc->nF;
+  for (int64_t f0 = (int64_t)blockIdx.x * 256; f0 < nF; f0 += (int64_t)gridDim.x * 256) {
+    const int64_t f = f0 + threadIdx.x;
+    uint64_t bound = 0;
+    if (f < nF) {
+      const uint32_t p = F[f];
+      const Slot sl = a.T.slots[p];
+      a.T.slots[p].stamp = a.t;
+      int32_t Rv[R];
+      Rv[0] = a.T.v1[p];
+      decode_key<R>(sl.key, a.T.bits, Rv);
+      int32_t best_v = Rv[0];
+      int64_t best = a.g.rp[Rv[0] + 1] - a.g.rp[Rv[0]];
 #pragma unroll
-    for (int i = 0; i < R; i++) {
-      fv[f * R + i] = Rv[i];
-      const int64_t d = a.g.rp[Rv[i] + 1] - a.g.rp[Rv[i]];
-      if (d < best) {
-        best = d;
-        best_v = Rv[i];
+      for (int i = 0; i < R; i++) {
+        fv[f * R + i] = Rv[i];
+        const int64_t d = a.g.rp[Rv[i] + 1] - a.g.rp[Rv[i]];
+        if (d < best) {
+          best = d;
+          best_v = Rv[i];
+        }
+      }
+      drv[f] = best_v;
+      bound = sl.cnt != 0 ? (uint64_t)best : 0;  // cnt 0: every s-clique of R is gone
+    }
+    const uint64_t at = block_alloc(bound, (unsigned long long *)&rc->total);
+    if (f < nF) {
+      ioff[f] = at;
+      ilen[f] = (uint32_t)bound;
+    }
+  }
+}
+
+// One wave per peeled r-clique writes its index over its candidate range, so
+// the member pass can be flattened over all candidates of the round.
+__global__ __launch_bounds__(256) void k_gen_spread(RoundCtl *rc, const uint64_t *__restrict__ ioff,
+                                                    const uint32_t *__restrict__ ilen,
+                                                    uint32_t *owner) {
+  if (rc_idle(rc)) return;
+  if (rc->total > rc->cap) {  // candidates do not fit: the host grows the buffers, reruns
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      rc->need = rc->total;
+      rc->halt = 1;
+    }
+    return;
+  }
+  const uint32_t nF = rc->nF;
+  const int wpb = blockDim.x / kWave;
+  for (int64_t f = (int64_t)blockIdx.x * wpb + threadIdx.x / kWave; f < nF;
+       f += (int64_t)gridDim.x * wpb) {
+    const uint32_t len = ilen[f];
+    const uint64_t fb = ioff[f];
+    for (uint32_t c = lane_id(); c < len; c += kWave) owner[fb + c] = (uint32_t)f;
+  }
+}
+
+// A thread per candidate x of the round: flag x when it lies in I(R) and
+// list the members that have out-arcs as (frontier index, x).
+template <int R>
+__global__ __launch_bounds__(256) void k_gen_member(GraphView g, RoundCtl *rc,
+                                                    const uint64_t *__restrict__ ioff,
+                                                    const uint32_t *__restrict__ owner,
+                                                    const int32_t *__restrict__ fv,
+                                                    const int32_t *__restrict__ drv, uint8_t *flag,
+                                                    int2 *mrec, uint64_t *mbeg, uint32_t *aown) {
+  if (rc_idle(rc)) return;
+  const uint64_t C = rc->total;
+  const uint64_t cap3 = rc->cap3;
+  const int lane = lane_id();
+  // wave-uniform trip count for the ballot below
+  for (uint64_t k0 = ((uint64_t)blockIdx.x * blockDim.x) + (threadIdx.x / kWave) * kWave; k0 < C;
+       k0 += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = k0 + lane;
+    bool in = k < C;
+    int32_t x = 0;
+    uint32_t f = 0;
+    if (in) {
+      f = owner[k];
+      const int32_t v = drv[f];
+      x = g.col[g.rp[v] + (int64_t)(k - ioff[f])];
+#pragma unroll
+      for (int i = 0; i < R; i++) {
+        const int32_t u = fv[(int64_t)f * R + i];
+        if (in && u != v) in = adjacent(g, x, u);
+      }
+      flag[k] = in ? 1 : 0;
+    }
+    const uint64_t deg = in ? (uint64_t)(g.rp[x + 1] - g.up[x]) : 0;
+    const bool emit = deg != 0;
+    const uint64_t m = __ballot(emit);
+    if (m) {
+      // member index and out-arc range, one atomic each per wave
+      const uint64_t incl = wave_incl_scan_u64(deg);
+      const uint64_t tot = __shfl(incl, kWave - 1);
+      unsigned long long at = 0, arc = 0;
+      if (lane == 0) {
+        at = atomicAdd((unsigned long long *)&rc->total2, (unsigned long long)__popcll(m));
+        arc = atomicAdd((unsigned long long *)&rc->total3, (unsigned long long)tot);
+      }
+      at = __shfl(at, 0);
+      arc = __shfl(arc, 0);
+      if (emit) {
+        const uint64_t i = at + (uint64_t)__popcll(m & lanes_below());
+        const uint64_t a0 = arc + incl - deg;
+        mrec[i] = make_int2((int)f, x);
+        mbeg[i] = a0;
+        if (a0 + deg <= cap3)  // otherwise the apply pass halts the round
+          for (uint64_t q = 0; q < deg; q++) aown[a0 + q] = (uint32_t)i;
       }
     }
-    drv[f] = best_v;
-    ub[f] = sl.cnt != 0 ? (uint64_t)best : 0;  // cnt 0: every s-clique of R is gone
-  }
-}
-
-template <int R>
-__global__ __launch_bounds__(256) void k_gen_member(GraphView g, GenView gv, uint8_t *flag,
-                                                    uint64_t *arcs) {
-  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < gv.C1;
-       k += (uint64_t)gridDim.x * blockDim.x) {
-    const int64_t f = seg_find(gv.ioff, gv.nF, k);
-    const int32_t v = gv.drv[f];
-    const int32_t x = g.col[g.rp[v] + (int64_t)(k - gv.ioff[f])];
-    bool in = true;
-#pragma unroll
-    for (int i = 0; i < R; i++) {
-      const int32_t u = gv.fv[f * R + i];
-      if (u != v) in = in && adjacent(g, x, u);
-    }
-    flag[k] = in ? 1 : 0;
-    arcs[k] = in ? (uint64_t)(g.rp[x + 1] - g.up[x]) : 0;
   }
 }
 
 // y in I(R): a position of the driver's row whose flag is set
-__device__ __forceinline__ bool gen_in(const GraphView &g, const GenView &gv, int64_t lo,
-                                       int64_t hi, uint64_t fbase, int32_t y) {
+__device__ __forceinline__ bool gen_in(const GraphView &g, const uint8_t *__restrict__ flag,
+                                       int64_t lo, int64_t hi, uint64_t fbase, int32_t y) {
   const int64_t at = lower_pos(g.col, lo, hi, y);
-  return at < hi && g.col[at] == y && gv.flag[fbase + (uint64_t)(at - lo)] != 0;
+  return at < hi && g.col[at] == y && flag[fbase + (uint64_t)(at - lo)] != 0;
 }
 
 template <int R, int Q>
@@ -969,13 +1205,13 @@ __device__ __forceinline__ void merge_rq(const int32_t (&Rv)[R], const int32_t (
 // Q[0..L-1] is a clique inside I(R); extend it by out-neighbours of Q[L-1]
 // that lie in I(R) and are adjacent to Q[0..L-2].
 template <int L, int R, int S>
-__device__ void gen_extend(const PeelArgs &a, const GenView &gv, int64_t lo, int64_t hi,
-                           uint64_t fbase, const int32_t (&Rv)[R], int32_t (&Qv)[S - R],
-                           uint32_t p, LaneStats &ls) {
+__device__ void gen_extend(const PeelArgs &a, const uint8_t *__restrict__ flag, int64_t lo,
+                           int64_t hi, uint64_t fbase, const int32_t (&Rv)[R],
+                           int32_t (&Qv)[S - R], uint32_t p, LaneStats &ls) {
   const int32_t x = Qv[L - 1];
   for (int64_t e = a.g.up[x]; e < a.g.rp[x + 1]; e++) {
     const int32_t z = a.g.col[e];
-    bool ok = gen_in(a.g, gv, lo, hi, fbase, z);
+    bool ok = gen_in(a.g, flag, lo, hi, fbase, z);
 #pragma unroll
     for (int j = 0; j < L - 1; j++) ok = ok && adjacent(a.g, Qv[j], z);
     if (!ok) continue;
@@ -986,14 +1222,33 @@ __device__ void gen_extend(const PeelArgs &a, const GenView &gv, int64_t lo, int
       merge_rq<R, S - R>(Rv, Qv, Sv, rmask);
       update_func<R, S, false>(a, Sv, rmask, p, true, ls, nullptr);
     } else {
-      gen_extend<L + 1, R, S>(a, gv, lo, hi, fbase, Rv, Qv, p, ls);
+      gen_extend<L + 1, R, S>(a, flag, lo, hi, fbase, Rv, Qv, p, ls);
     }
   }
 }
 
+// A thread per out-arc (x, y) of a member x of I(R): y in I(R) closes
+// R + {x, y} (s = r+2) or starts a deeper extension.
 template <int R, int S>
-__global__ __launch_bounds__(256) void k_gen_apply(PeelArgs a, GenView gv,
-                                                   const uint32_t *__restrict__ F, uint64_t A) {
+__global__ __launch_bounds__(256) void k_gen_apply(PeelArgs base, RoundCtl *rc,
+                                                   const uint64_t *__restrict__ ioff,
+                                                   const int32_t *__restrict__ fv,
+                                                   const int32_t *__restrict__ drv,
+                                                   const uint8_t *__restrict__ flag,
+                                                   const int2 *__restrict__ mrec,
+                                                   const uint64_t *__restrict__ mbeg,
+                                                   const uint32_t *__restrict__ aown) {
+  if (rc_idle(rc)) return;
+  if (rc->total3 > rc->cap3) {  // arcs did not fit: the host grows the buffer, reruns the round
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      rc->need = rc->total3;
+      rc->halt = 4;
+    }
+    return;
+  }
+  const PeelArgs a = round_args(base, rc);
+  const uint32_t *__restrict__ F = rc->F;
+  const uint64_t A = rc->total3;
   const int wv = threadIdx.x / kWave;
   const int lane = lane_id();
   LaneStats ls;
@@ -1001,10 +1256,10 @@ __global__ __launch_bounds__(256) void k_gen_apply(PeelArgs a, GenView gv,
   Appender ap[2] = {{abuf[wv][0], 0u, a.Fnext, &a.ctr->next_size},
                     {abuf[wv][1], 0u, a.Low, &a.ctr->low_size}};
   // wave-uniform trip count: every lane reaches every append
-  for (uint64_t base = ((uint64_t)blockIdx.x * blockDim.x) + (uint64_t)wv * kWave; base < A;
-       base += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t i = base + lane;
-    bool in = i < A;
+  for (uint64_t b0 = ((uint64_t)blockIdx.x * blockDim.x) + (uint64_t)wv * kWave; b0 < A;
+       b0 += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t j = b0 + lane;
+    bool in = j < A;
     int32_t Rv[R];
 #pragma unroll
     for (int q = 0; q < R; q++) Rv[q] = q;
@@ -1015,18 +1270,18 @@ __global__ __launch_bounds__(256) void k_gen_apply(PeelArgs a, GenView gv,
     int64_t lo = 0, hi = 0;
     uint64_t fbase = 0;
     if (in) {
-      const int64_t kx = seg_find(gv.aoff, (int64_t)gv.C1, i);
-      const int64_t f = seg_find(gv.ioff, gv.nF, (uint64_t)kx);
-      const int32_t v = gv.drv[f];
+      const uint32_t i = aown[j];
+      const int2 mr = mrec[i];
+      const int32_t f = mr.x, x = mr.y;
+      const int32_t v = drv[f];
       lo = a.g.rp[v];
       hi = a.g.rp[v + 1];
-      fbase = gv.ioff[f];
-      const int32_t x = a.g.col[lo + (int64_t)((uint64_t)kx - fbase)];
-      const int32_t y = a.g.col[a.g.up[x] + (int64_t)(i - gv.aoff[kx])];
-      in = gen_in(a.g, gv, lo, hi, fbase, y);
+      fbase = ioff[f];
+      const int32_t y = a.g.col[a.g.up[x] + (int64_t)(j - mbeg[i])];
+      in = gen_in(a.g, flag, lo, hi, fbase, y);
       p = F[f];
 #pragma unroll
-      for (int q = 0; q < R; q++) Rv[q] = gv.fv[f * R + q];
+      for (int q = 0; q < R; q++) Rv[q] = fv[(int64_t)f * R + q];
       Qv[0] = x;
       Qv[1] = y;
     }
@@ -1036,7 +1291,7 @@ __global__ __launch_bounds__(256) void k_gen_apply(PeelArgs a, GenView gv,
       merge_rq<R, 2>(Rv, Qv, Sv, rmask);
       update_func<R, S, true>(a, Sv, rmask, p, in, ls, ap);
     } else {
-      if (in) gen_extend<2, R, S>(a, gv, lo, hi, fbase, Rv, Qv, p, ls);
+      if (in) gen_extend<2, R, S>(a, flag, lo, hi, fbase, Rv, Qv, p, ls);
     }
   }
   ap[0].flush();
@@ -1046,98 +1301,348 @@ __global__ __launch_bounds__(256) void k_gen_apply(PeelArgs a, GenView gv,
   if (ls.err) atomicOr(&a.ctr->err, ls.err);
 }
 
+dim3 blocks_for(uint64_t n, uint64_t per, uint64_t lo, uint64_t hi) {
+  uint64_t b = (n + per - 1) / per;
+  b = b < lo ? lo : b;
+  b = b > hi ? hi : b;
+  return dim3((unsigned)b);
+}
+
+// Buffers and launch parameters of one peel loop.
+struct Engine {
+  int r = 0, s = 0, path = 0;
+  GraphView gv{};
+  TableView T{};
+  FastView fxv{};
+  const uint64_t *loc = nullptr;
+  Counters *dc = nullptr;
+  unsigned long long *stats = nullptr;
+  hipStream_t st = nullptr;
+  DevBuf<RoundCtl> rc;
+  DevBuf<uint32_t> lists;  // F, F', W, W', H, H' (n_r each)
+  DevBuf<uint64_t> off;    // per frontier entry: first record / flag
+  DevBuf<uint32_t> len;    // per frontier entry: records / flags
+  DevBuf<int32_t> fv;      // per frontier entry: its r vertices
+  DevBuf<int32_t> drv;     // per frontier entry: driver (s >= r+2)
+  DevBuf<int2> rec;        // candidate records (s = r+1) or member records (s >= r+2)
+  DevBuf<uint8_t> flag;    // s >= r+2: membership flags
+  DevBuf<uint32_t> owner;  // s >= r+2: frontier index of each candidate
+  DevBuf<uint64_t> mbeg;   // s >= r+2: first out-arc of each member
+  DevBuf<uint32_t> aown;   // s >= r+2: member of each out-arc
+  uint64_t cap3 = 0;
+  DevBuf<uint32_t> tsize, tk;
+  uint64_t cap = 0;
+  uint32_t tcap = 0;
+};
+
 template <int R, int S>
-uint64_t gen_impl(const PeelArgs &a, const uint32_t *F, uint32_t nF, GenBufs *gb, hipStream_t st,
-                  hipEvent_t ev0, hipEvent_t ev1) {
-  if (gb->ioff.n < (size_t)nF + 1) gb->ioff.reset((size_t)nF + 1 + nF / 2);
-  if (gb->fv.n < (size_t)nF * R) gb->fv.reset(((size_t)nF + nF / 2) * R);
-  if (gb->drv.n < (size_t)nF) gb->drv.reset((size_t)nF + nF / 2);
-  hipLaunchKernelGGL(k_gen_bound<R>, dim3((unsigned)grid_for(nF, 256)), dim3(256), 0, st, a, F, nF,
-                     gb->ioff.get(), gb->fv.get(), gb->drv.get());
-  fill_u64(gb->ioff.get() + nF, 0, 1, st);
-  scan_exclusive_u64(gb->ioff.get(), gb->ioff.get(), (int64_t)nF + 1, st);
-  uint64_t C1 = 0;
-  hipMemcpyAsync(&C1, gb->ioff.get() + nF, 8, hipMemcpyDeviceToHost, st);
-  hipStreamSynchronize(st);
-  uint64_t A = 0;
-  GenView gv{gb->ioff.get(), gb->fv.get(), gb->drv.get(), nullptr, nullptr, nF, C1};
-  if (C1 > 0) {
-    if (gb->flag.n < C1) gb->flag.reset(C1 + C1 / 2);
-    if (gb->aoff.n < C1 + 1) gb->aoff.reset(C1 + 1 + C1 / 2);
-    gv.flag = gb->flag.get();
-    gv.aoff = gb->aoff.get();
-    hipLaunchKernelGGL(k_gen_member<R>, dim3((unsigned)grid_for(C1, 256, 1 << 16)), dim3(256), 0,
-                       st, a.g, gv, gb->flag.get(), gb->aoff.get());
-    fill_u64(gb->aoff.get() + C1, 0, 1, st);
-    scan_exclusive_u64(gb->aoff.get(), gb->aoff.get(), (int64_t)C1 + 1, st);
-    hipMemcpyAsync(&A, gb->aoff.get() + C1, 8, hipMemcpyDeviceToHost, st);
-    hipStreamSynchronize(st);
-  }
-  if (ev0) hipEventRecord(ev0, st);
-  if (A > 0)
-    hipLaunchKernelGGL((k_gen_apply<R, S>), dim3((unsigned)grid_for(A, 256, 1 << 16)), dim3(256),
-                       0, st, a, gv, F, A);
-  if (ev1) hipEventRecord(ev1, st);
-  return A;
+void launch_walker(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, hipEvent_t e0,
+                   hipEvent_t e1) {
+  hipLaunchKernelGGL(k_stamp, gf, dim3(256), 0, E.st, E.rc.get(), E.T.slots);
+  if (e0) hipEventRecord(e0, E.st);
+  hipLaunchKernelGGL((k_peel<R, S>), gw, dim3(256), 0, E.st, base, E.rc.get());
+  if (e1) hipEventRecord(e1, E.st);
+}
+
+template <int R>
+void launch_fast(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, dim3 ga, hipEvent_t e0,
+                 hipEvent_t e1) {
+  hipLaunchKernelGGL(k_expand_bound<R>, gf, dim3(256), 0, E.st, base, E.rc.get(), E.fxv, E.loc,
+                     E.off.get(), E.len.get(), E.fv.get());
+  hipLaunchKernelGGL(k_expand<R>, gw, dim3(256), 0, E.st, base, E.rc.get(), E.fxv, E.loc,
+                     E.off.get(), E.len.get(), E.fv.get(), E.rec.get());
+  if (e0) hipEventRecord(e0, E.st);
+  hipLaunchKernelGGL(k_apply<R>, ga, dim3(256), 0, E.st, base, E.rc.get(), E.rec.get(),
+                     E.fv.get());
+  if (e1) hipEventRecord(e1, E.st);
+  if (R == 3)
+    hipLaunchKernelGGL(k_clear_alive, gf, dim3(256), 0, E.st, E.gv, E.T, E.fxv, E.rc.get());
 }
 
 template <int R, int S>
-void peel_impl(const PeelArgs &a, const uint32_t *F, uint32_t nF, hipStream_t st) {
-  hipLaunchKernelGGL((k_peel<R, S>), dim3((unsigned)grid_for(nF, 4, 1 << 20)), dim3(256), 0, st,
-                     a, F, nF);
+void launch_gen(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, dim3 gc, dim3 ga,
+                hipEvent_t e0, hipEvent_t e1) {
+  hipLaunchKernelGGL(k_gen_bound<R>, gf, dim3(256), 0, E.st, base, E.rc.get(), E.off.get(),
+                     E.len.get(), E.fv.get(), E.drv.get());
+  hipLaunchKernelGGL(k_gen_spread, gw, dim3(256), 0, E.st, E.rc.get(), E.off.get(), E.len.get(),
+                     E.owner.get());
+  hipLaunchKernelGGL(k_gen_member<R>, gc, dim3(256), 0, E.st, E.gv, E.rc.get(), E.off.get(),
+                     E.owner.get(), E.fv.get(), E.drv.get(), E.flag.get(), E.rec.get(),
+                     E.mbeg.get(), E.aown.get());
+  if (e0) hipEventRecord(e0, E.st);
+  hipLaunchKernelGGL((k_gen_apply<R, S>), ga, dim3(256), 0, E.st, base, E.rc.get(), E.off.get(),
+                     E.fv.get(), E.drv.get(), E.flag.get(), E.rec.get(), E.mbeg.get(),
+                     E.aown.get());
+  if (e1) hipEventRecord(e1, E.st);
+}
+
+#define ND_WALK(R_, S_) \
+  case (R_) * 16 + (S_): launch_walker<R_, S_>(E, base, gf, gw, e0, e1); break;
+#define ND_GEN(R_, S_) \
+  case (R_) * 16 + (S_): launch_gen<R_, S_>(E, base, gf, gw, gc, ga, e0, e1); break;
+
+// Queue one round.  m is the last state read back: exact when nothing is in
+// flight (the first round of a batch), otherwise only a guide for the grid
+// sizes (every kernel loops over the true sizes it reads on the device).
+void enqueue_round(Engine &E, const RoundCtl &m, bool exact, hipEvent_t e0, hipEvent_t e1,
+                   hipEvent_t e_adv) {
+  const hipStream_t st = E.st;
+  RoundCtl *rc = E.rc.get();
+  if (!exact || m.nF == 0) {
+    const uint64_t cap_b = exact ? 8192 : 1024;
+    hipLaunchKernelGGL(k_adv_min<false>, blocks_for(m.nW, 256 * 8, 1, cap_b), dim3(256), 0, st, rc,
+                       E.T.slots);
+    hipLaunchKernelGGL(k_adv_min<true>, blocks_for(m.nH, 256 * 8, 1, cap_b), dim3(256), 0, st, rc,
+                       E.T.slots);
+    hipLaunchKernelGGL(k_adv_partition,
+                       blocks_for(m.nW > m.nH ? m.nW : m.nH, kPartThreads * kPartItems, 1, cap_b),
+                       dim3(kPartThreads), 0, st, rc, E.T.slots);
+    hipLaunchKernelGGL(k_adv_finish, dim3(1), dim3(1), 0, st, rc);
+  }
+  if (e_adv) hipEventRecord(e_adv, st);
+  hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, st, rc, E.dc);
+  // Grids: sized to the frontier when it is known (nothing in flight and no
+  // level advance), otherwise wide enough to fill the chip, so that a large
+  // round queued behind small ones never runs on a small grid.
+  const bool known = exact && m.nF != 0;
+  const dim3 gf = known ? blocks_for(m.nF, 256, 1, 4096) : dim3(1024);
+  const dim3 gw = known ? blocks_for(m.nF, 256 / kWave, 1, 1u << 16) : dim3(4096);
+  const PeelArgs base{E.gv, E.T, 0u, 0u, nullptr, E.dc, E.stats, 0u, nullptr};
+  if (E.path == 1) {
+    const dim3 ga = blocks_for(2 * m.total, 256, 1024, 8192);
+    switch (E.r) {
+      case 2: launch_fast<2>(E, base, gf, gw, ga, e0, e1); break;
+      case 3: launch_fast<3>(E, base, gf, gw, ga, e0, e1); break;
+      case 4: launch_fast<4>(E, base, gf, gw, ga, e0, e1); break;
+      case 5: launch_fast<5>(E, base, gf, gw, ga, e0, e1); break;
+      case 6: launch_fast<6>(E, base, gf, gw, ga, e0, e1); break;
+      default: break;
+    }
+  } else if (E.path == 2) {
+    const dim3 gc = blocks_for(2 * m.total, 256, 1024, 8192);
+    const dim3 ga = blocks_for(2 * m.total3, 256, 1024, 8192);
+    switch (E.r * 16 + E.s) {
+      ND_GEN(1, 3) ND_GEN(1, 4) ND_GEN(1, 5) ND_GEN(1, 6) ND_GEN(1, 7)
+      ND_GEN(2, 4) ND_GEN(2, 5) ND_GEN(2, 6) ND_GEN(2, 7)
+      ND_GEN(3, 5) ND_GEN(3, 6) ND_GEN(3, 7)
+      ND_GEN(4, 6) ND_GEN(4, 7)
+      ND_GEN(5, 7)
+      default: break;
+    }
+  } else {
+    switch (E.r * 16 + E.s) {
+      ND_WALK(1, 2) ND_WALK(1, 3) ND_WALK(1, 4) ND_WALK(1, 5) ND_WALK(1, 6) ND_WALK(1, 7)
+      ND_WALK(2, 3) ND_WALK(2, 4) ND_WALK(2, 5) ND_WALK(2, 6) ND_WALK(2, 7)
+      ND_WALK(3, 4) ND_WALK(3, 5) ND_WALK(3, 6) ND_WALK(3, 7)
+      ND_WALK(4, 5) ND_WALK(4, 6) ND_WALK(4, 7)
+      ND_WALK(5, 6) ND_WALK(5, 7)
+      ND_WALK(6, 7)
+      default: break;
+    }
+  }
+  hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, st, rc, E.dc);
+}
+
+template <class T>
+void set_field(RoundCtl *rc, size_t offset, T value, hipStream_t st) {
+  hipMemcpyAsync((char *)rc + offset, &value, sizeof(T), hipMemcpyHostToDevice, st);
+  hipStreamSynchronize(st);
+}
+
+void alloc_records(Engine &E, uint64_t cap) {
+  E.rec.reset(cap);
+  if (E.path == 2) {
+    E.flag.reset(cap);
+    E.owner.reset(cap);
+    E.mbeg.reset(cap);
+  }
+  E.cap = cap;
+}
+
+constexpr int kMaxDepth = 32;
+
+// Most rounds queued between two reads of the round state (ND_PEEL_DEPTH,
+// 1..32, default 32).
+int max_depth() {
+  const char *e = getenv("ND_PEEL_DEPTH");
+  const int d = e ? atoi(e) : kMaxDepth;
+  return d < 1 ? 1 : (d > kMaxDepth ? kMaxDepth : d);
 }
 
 }  // namespace
 
-void stamp_frontier(const uint32_t *F, uint32_t nF, Slot *slots, uint32_t t, hipStream_t st) {
-  if (!nF) return;
-  hipLaunchKernelGGL(k_stamp, dim3((unsigned)grid_for(nF, 256)), dim3(256), 0, st, F, nF, slots,
-                     t);
-}
-
-#define ND_PEEL_CASE(R_, S_) \
-  case (R_) * 16 + (S_): peel_impl<R_, S_>(a, F, nF, st); break;
-
-void peel_round(const OrientedGraph &g, int r, int s, const TableView &T, const uint32_t *F,
-                uint32_t nF, uint32_t t, uint32_t k, uint32_t kw, uint32_t *Fnext, uint32_t *Low,
-                Counters *dctr, unsigned long long *stats, hipStream_t st) {
-  if (!nF) return;
-  PeelArgs a{g.view(), T, t, k, Fnext, dctr, stats, kw, Low};
-  switch (r * 16 + s) {
-    ND_PEEL_CASE(1, 2) ND_PEEL_CASE(1, 3) ND_PEEL_CASE(1, 4) ND_PEEL_CASE(1, 5)
-    ND_PEEL_CASE(1, 6) ND_PEEL_CASE(1, 7)
-    ND_PEEL_CASE(2, 3) ND_PEEL_CASE(2, 4) ND_PEEL_CASE(2, 5) ND_PEEL_CASE(2, 6)
-    ND_PEEL_CASE(2, 7)
-    ND_PEEL_CASE(3, 4) ND_PEEL_CASE(3, 5) ND_PEEL_CASE(3, 6) ND_PEEL_CASE(3, 7)
-    ND_PEEL_CASE(4, 5) ND_PEEL_CASE(4, 6) ND_PEEL_CASE(4, 7)
-    ND_PEEL_CASE(5, 6) ND_PEEL_CASE(5, 7)
-    ND_PEEL_CASE(6, 7)
-    default: break;
-  }
-}
-
-#define ND_GEN_CASE(R_, S_) \
-  case (R_) * 16 + (S_): return gen_impl<R_, S_>(a, F, nF, gb, st, ev0, ev1);
-
-uint64_t peel_round_gen(const OrientedGraph &g, int r, int s, const TableView &T,
-                        const uint32_t *F, uint32_t nF, uint32_t t, uint32_t k, uint32_t kw,
-                        uint32_t *Fnext, uint32_t *Low, Counters *dctr,
-                        unsigned long long *stats, GenBufs *gb, hipStream_t st, hipEvent_t ev0,
-                        hipEvent_t ev1) {
-  if (!nF) {
-    if (ev0) hipEventRecord(ev0, st);
-    if (ev1) hipEventRecord(ev1, st);
+uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableView &T,
+                  const FastIndex *fx, const uint32_t *occ, uint64_t n_r, Counters *dc,
+                  unsigned long long *stats, bool timing, hipStream_t st, hipEvent_t ev_first,
+                  DevBuf<uint32_t> *kround, PeelResult *res) {
+  res->sizes.clear();
+  res->levels.clear();
+  res->advances = 0;
+  res->apply_ms = 0;
+  res->apply_launches = 0;
+  if (n_r == 0) {
+    if (ev_first) hipEventRecord(ev_first, st);
+    kround->reset(1);
     return 0;
   }
-  PeelArgs a{g.view(), T, t, k, Fnext, dctr, stats, kw, Low};
-  switch (r * 16 + s) {
-    ND_GEN_CASE(1, 3) ND_GEN_CASE(1, 4) ND_GEN_CASE(1, 5) ND_GEN_CASE(1, 6) ND_GEN_CASE(1, 7)
-    ND_GEN_CASE(2, 4) ND_GEN_CASE(2, 5) ND_GEN_CASE(2, 6) ND_GEN_CASE(2, 7)
-    ND_GEN_CASE(3, 5) ND_GEN_CASE(3, 6) ND_GEN_CASE(3, 7)
-    ND_GEN_CASE(4, 6) ND_GEN_CASE(4, 7)
-    ND_GEN_CASE(5, 7)
-    default: break;
+  Engine E;
+  E.r = r;
+  E.s = s;
+  E.path = path;
+  E.gv = g.view();
+  E.T = T;
+  if (fx) {
+    E.fxv = fx->view();
+    E.loc = fx->loc.get();
   }
+  E.dc = dc;
+  E.stats = stats;
+  E.st = st;
+  E.rc.reset(1);
+  E.lists.reset(6 * n_r);
+  uint32_t *L = E.lists.get();
+  hipMemcpyAsync(L + 4 * n_r, occ, 4 * n_r, hipMemcpyDeviceToDevice, st);  // H = every r-clique
+  E.off.reset(n_r);
+  E.len.reset(n_r);
+  E.fv.reset(n_r * (uint64_t)r);
+  if (path == 2) E.drv.reset(n_r);
+  // initial capacities; ND_PEEL_CAP / ND_PEEL_TRACE_CAP override them (small
+  // values exercise the grow-and-rerun path)
+  uint64_t cap0 = n_r > (1u << 20) ? n_r : (1u << 20);
+  E.tcap = 1024;
+  if (const char *e = getenv("ND_PEEL_CAP")) cap0 = strtoull(e, nullptr, 10) > 0 ? strtoull(e, nullptr, 10) : cap0;
+  if (const char *e = getenv("ND_PEEL_TRACE_CAP")) E.tcap = atoi(e) > 0 ? (uint32_t)atoi(e) : E.tcap;
+  if (path != 0) alloc_records(E, cap0);
+  if (path == 2) {
+    E.cap3 = 4 * E.cap;
+    E.aown.reset(E.cap3);
+  }
+  E.tsize.reset(E.tcap);
+  E.tk.reset(E.tcap);
+
+  RoundCtl h;
+  memset(&h, 0, sizeof(h));
+  for (int i = 0; i < 2; i++) {
+    h.bufF[i] = L + (uint64_t)i * n_r;
+    h.bufW[i] = L + (uint64_t)(2 + i) * n_r;
+    h.bufH[i] = L + (uint64_t)(4 + i) * n_r;
+  }
+  h.trace_size = E.tsize.get();
+  h.trace_k = E.tk.get();
+  h.trace_cap = E.tcap;
+  h.n_r = n_r;
+  h.cap = E.cap;
+  h.cap3 = E.cap3;
+  h.nH = (uint32_t)n_r;
+  h.mw = kNone;
+  h.mh = kNone;
+  hipMemcpyAsync(E.rc.get(), &h, sizeof(h), hipMemcpyHostToDevice, st);
+
+  RoundCtl *mirror = nullptr;
+  if (hipHostMalloc((void **)&mirror, sizeof(RoundCtl), hipHostMallocDefault) != hipSuccess)
+    throw OutOfMemory{};
+  hipEvent_t ev[2 * kMaxDepth] = {};
+  if (timing)
+    for (auto &e : ev) hipEventCreate(&e);
+  uint32_t status = 0;
+  RoundCtl m = h;
+  int depth = 1;
+  const int dmax = max_depth();
+  bool first = true;
+  for (;;) {
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int d = 0; d < depth; d++) {
+      enqueue_round(E, m, d == 0, timing ? ev[2 * d] : nullptr, timing ? ev[2 * d + 1] : nullptr,
+                    first && d == 0 ? ev_first : nullptr);
+    }
+    first = false;
+    hipMemcpyAsync(mirror, E.rc.get(), sizeof(RoundCtl), hipMemcpyDeviceToHost, st);
+    if (hipStreamSynchronize(st) != hipSuccess) {
+      status = kErrOverflow;  // reported by the caller's launch check
+      break;
+    }
+    const RoundCtl prev = m;
+    m = *mirror;
+    if (timing) {
+      for (int d = 0; d < depth; d++) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, ev[2 * d], ev[2 * d + 1]) == hipSuccess) res->apply_ms += ms;
+      }
+    }
+    if (m.err) {
+      status = m.err;
+      break;
+    }
+    if (m.halt == 1) {  // grow the record buffers and run the round again
+      uint64_t want = m.need + m.need / 4;
+      if (want < 2 * E.cap) want = 2 * E.cap;
+      E.rec.release();
+      E.flag.release();
+      E.owner.release();
+      E.mbeg.release();
+      alloc_records(E, want);
+      set_field(E.rc.get(), offsetof(RoundCtl, cap), E.cap, st);
+      set_field(E.rc.get(), offsetof(RoundCtl, halt), 0u, st);
+      m.cap = E.cap;
+      m.halt = 0;
+      depth = 1;
+      continue;
+    }
+    if (m.halt == 4) {  // grow the out-arc buffer and run the round again
+      uint64_t want = m.need + m.need / 4;
+      if (want < 2 * E.cap3) want = 2 * E.cap3;
+      E.aown.release();
+      E.aown.reset(want);
+      E.cap3 = want;
+      set_field(E.rc.get(), offsetof(RoundCtl, cap3), E.cap3, st);
+      set_field(E.rc.get(), offsetof(RoundCtl, halt), 0u, st);
+      m.cap3 = E.cap3;
+      m.halt = 0;
+      depth = 1;
+      continue;
+    }
+    if (m.halt == 2) {  // grow the round trace
+      const uint32_t nt = E.tcap * 2;
+      DevBuf<uint32_t> ns(nt), nk(nt);
+      hipMemcpyAsync(ns.get(), E.tsize.get(), 4ull * E.tcap, hipMemcpyDeviceToDevice, st);
+      hipMemcpyAsync(nk.get(), E.tk.get(), 4ull * E.tcap, hipMemcpyDeviceToDevice, st);
+      E.tsize = std::move(ns);
+      E.tk = std::move(nk);
+      E.tcap = nt;
+      set_field(E.rc.get(), offsetof(RoundCtl, trace_size), E.tsize.get(), st);
+      set_field(E.rc.get(), offsetof(RoundCtl, trace_k), E.tk.get(), st);
+      set_field(E.rc.get(), offsetof(RoundCtl, trace_cap), E.tcap, st);
+      set_field(E.rc.get(), offsetof(RoundCtl, halt), 0u, st);
+      m.halt = 0;
+      continue;
+    }
+    if (m.halt) {
+      status = kErrBucket;
+      break;
+    }
+    if (m.done) break;
+    // deepen the queue while rounds are short, back off while they are long
+    const double dt =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (m.t == prev.t) depth = 1;
+    else if (dt < 2.0 && depth < dmax) depth = depth * 2 < dmax ? depth * 2 : dmax;
+    else if (dt > 20.0 && depth > 1) depth /= 2;
+  }
+  if (timing)
+    for (auto &e : ev) hipEventDestroy(e);
+  hipHostFree(mirror);
+  if (status) return status;
+  res->advances = m.advances;
+  res->apply_launches = m.t;
+  std::vector<uint32_t> sz(m.t);
+  res->levels.resize(m.t);
+  if (m.t) {
+    hipMemcpyAsync(sz.data(), E.tsize.get(), 4ull * m.t, hipMemcpyDeviceToHost, st);
+    hipMemcpyAsync(res->levels.data(), E.tk.get(), 4ull * m.t, hipMemcpyDeviceToHost, st);
+    hipStreamSynchronize(st);
+  }
+  res->sizes.assign(sz.begin(), sz.end());
+  *kround = std::move(E.tk);
   return 0;
 }
 
@@ -1163,58 +1668,6 @@ void count_direct(const OrientedGraph &g, int r, const TableView &T, const FastI
   }
 }
 
-template <int R>
-float split_impl(const PeelArgs &a, const FastIndex &fx, const uint32_t *F, uint32_t nF,
-                 SplitBufs *sb, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  const FastView fv = fx.view();
-  const uint64_t *loc = fx.loc.get();
-  if (sb->off.n < (size_t)nF + 1) sb->off.reset((size_t)nF + 1 + nF / 2);
-  if (sb->fv.n < (size_t)nF * R) sb->fv.reset(((size_t)nF + nF / 2) * R);
-  hipLaunchKernelGGL(k_expand_bound<R>, dim3((unsigned)grid_for(nF, 256)), dim3(256), 0, st, a, fv,
-                     loc, F, nF, sb->off.get(), sb->fv.get());
-  fill_u64(sb->off.get() + nF, 0, 1, st);
-  scan_exclusive_u64(sb->off.get(), sb->off.get(), (int64_t)nF + 1, st);
-  uint64_t total = 0;
-  hipMemcpyAsync(&total, sb->off.get() + nF, 8, hipMemcpyDeviceToHost, st);
-  hipStreamSynchronize(st);
-  if (total == 0) {  // keep the event pair consistent for the caller's timing
-    if (ev0) hipEventRecord(ev0, st);
-    if (ev1) hipEventRecord(ev1, st);
-    return 0.f;
-  }
-  if (sb->rec.n < total) sb->rec.reset(total + total / 2);
-  hipLaunchKernelGGL(k_expand<R>, dim3((unsigned)grid_for(nF, 4, 1 << 20)), dim3(256), 0, st, a,
-                     fv, loc, F, nF, sb->off.get(), sb->fv.get(), sb->rec.get());
-  if (ev0) hipEventRecord(ev0, st);
-  hipLaunchKernelGGL(k_apply<R>, dim3((unsigned)grid_for(total, 256, 1 << 16)), dim3(256), 0, st, a,
-                     sb->rec.get(), total, F, sb->fv.get());
-  if (ev1) hipEventRecord(ev1, st);
-  return (float)total;
-}
-
-uint64_t peel_round_split(const OrientedGraph &g, int r, const TableView &T, const FastIndex &fx,
-                          const uint32_t *F, uint32_t nF, uint32_t t, uint32_t k, uint32_t kw,
-                          uint32_t *Fnext, uint32_t *Low, Counters *dctr,
-                          unsigned long long *stats, SplitBufs *sb, hipStream_t st,
-                          hipEvent_t ev0, hipEvent_t ev1) {
-  if (!nF) {
-    if (ev0) hipEventRecord(ev0, st);
-    if (ev1) hipEventRecord(ev1, st);
-    return 0;
-  }
-  PeelArgs a{g.view(), T, t, k, Fnext, dctr, stats, kw, Low};
-  float tot = 0;
-  switch (r) {
-    case 2: tot = split_impl<2>(a, fx, F, nF, sb, st, ev0, ev1); break;
-    case 3: tot = split_impl<3>(a, fx, F, nF, sb, st, ev0, ev1); break;
-    case 4: tot = split_impl<4>(a, fx, F, nF, sb, st, ev0, ev1); break;
-    case 5: tot = split_impl<5>(a, fx, F, nF, sb, st, ev0, ev1); break;
-    case 6: tot = split_impl<6>(a, fx, F, nF, sb, st, ev0, ev1); break;
-    default: break;
-  }
-  return (uint64_t)tot;
-}
-
 void build_slot_loc(const OrientedGraph &g, int r, const TableView &T, uint64_t n_slots,
                     FastIndex *fx, hipStream_t st) {
   fx->loc.reset(n_slots ? n_slots : 1);
@@ -1229,31 +1682,6 @@ void build_slot_loc(const OrientedGraph &g, int r, const TableView &T, uint64_t 
     case 6: hipLaunchKernelGGL(k_make_loc<6>, grid, blk, 0, st, gv, T, n_slots, fx->loc.get()); break;
     default: break;
   }
-}
-
-void clear_alive(const OrientedGraph &g, const TableView &T, const FastIndex &fx,
-                 const uint32_t *F, uint32_t nF, hipStream_t st) {
-  if (!nF) return;
-  hipLaunchKernelGGL(k_clear_alive, dim3((unsigned)grid_for(nF, 256)), dim3(256), 0, st,
-                     g.view(), T, fx.view(), F, nF);
-}
-
-void live_min(const uint32_t *L, uint32_t nL, const Slot *slots, Counters *dctr, hipStream_t st) {
-  fill_u32(&dctr->live_min, 0xFFFFFFFFu, 1, st);
-  if (!nL) return;
-  hipLaunchKernelGGL(k_live_min, dim3((unsigned)grid_for(nL, 256 * 8, 8192)), dim3(256), 0, st, L,
-                     nL, slots, &dctr->live_min);
-}
-
-void live_partition(const uint32_t *L, uint32_t nL, const Slot *slots, uint32_t k, uint32_t kw,
-                    uint32_t *F, uint32_t *Low, uint32_t *High, Counters *dctr, hipStream_t st) {
-  fill_u32(&dctr->next_size, 0, 1, st);
-  fill_u32(&dctr->low_size, 0, 2, st);  // low_size, high_size
-  if (!nL) return;
-  hipLaunchKernelGGL(k_live_partition,
-                     dim3((unsigned)grid_for(nL, kPartThreads * kPartItems, 8192)),
-                     dim3(kPartThreads), 0, st, L, nL, slots, k, kw, F, &dctr->next_size, Low,
-                     &dctr->low_size, High, &dctr->high_size);
 }
 
 void occupied_list(const Slot *slots, uint64_t n_slots, uint32_t *occ, hipStream_t st) {

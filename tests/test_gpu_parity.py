@@ -275,3 +275,21 @@ def test_plan_lifecycle():
     assert sizes.tolist() == [1, 3, 10] and levels.tolist() == [0, 1, 2]
     nd.nd_plan_destroy(plan)
     nd.nd_release_cached()
+
+
+@pytest.mark.parametrize("r,s", [(3, 4), (2, 4), (1, 3), (2, 3), (3, 5)])
+def test_round_buffers_grow_and_rerun(r, s, monkeypatch):
+    """Tiny initial record / arc / round-trace capacities: rounds halt, the
+    host grows the buffers and reruns them; results stay exact."""
+    monkeypatch.setenv("ND_PEEL_CAP", "64")
+    monkeypatch.setenv("ND_PEEL_TRACE_CAP", "2")
+    g = inputs.rmat(10, 8, 321)
+    check_against_oracle(g, r, s)
+
+
+@pytest.mark.parametrize("depth", ["1", "4"])
+def test_round_queue_depth(depth, monkeypatch):
+    """Results do not depend on how many rounds are queued between reads of
+    the device round state."""
+    monkeypatch.setenv("ND_PEEL_DEPTH", depth)
+    check_against_oracle(inputs.rmat(10, 8, 55), 2, 4)
