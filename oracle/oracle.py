@@ -183,13 +183,37 @@ def count_one(n: int, row_ptr, col, r: int, s: int, R) -> int:
     return int(lib.ndo_count_one(int(n), _ptr(rp), _ptr(cl), int(r), int(s), _ptr(Rv)))
 
 
+def _pack(cols, bits):
+    key = np.zeros(cols[0].shape[0], dtype=np.uint64)
+    for c in cols:
+        key = (key << np.uint64(bits)) | c.astype(np.uint64)
+    return key
+
+
+def _kappa_lex_order(rc: np.ndarray, n: int) -> np.ndarray:
+    """Row order of rc sorted lexicographically; vertex ids are packed into
+    at most two 64-bit keys so large tables sort in one or two passes."""
+    m, r = rc.shape
+    if m == 0:
+        return np.zeros(0, dtype=np.int64)
+    bits = max(1, int(n - 1).bit_length())
+    per = 64 // bits
+    if r <= per:
+        return np.argsort(_pack([rc[:, i] for i in range(r)], bits), kind="stable")
+    if r <= 2 * per:
+        hi = _pack([rc[:, i] for i in range(per)], bits)
+        lo = _pack([rc[:, i] for i in range(per, r)], bits)
+        return np.lexsort((lo, hi))
+    return np.lexsort(rc.T[::-1])
+
+
 class KappaTable:
     """A kappa assignment over r-cliques, sorted for lookup by the local
     certificate (the assignment under test may come from anywhere)."""
 
     def __init__(self, n: int, rcliques: np.ndarray, kappa: np.ndarray):
         rc = np.sort(np.asarray(rcliques, dtype=np.int32), axis=1)
-        order = np.lexsort(rc.T[::-1]) if rc.shape[0] else np.zeros(0, dtype=np.int64)
+        order = _kappa_lex_order(rc, n)
         self.tab = np.ascontiguousarray(rc[order], dtype=np.int32)
         self.kap = np.ascontiguousarray(np.asarray(kappa)[order], dtype=np.uint32)
         first = np.zeros(n + 1, dtype=np.int64)
