@@ -221,21 +221,35 @@ struct CountOp {
   __device__ void lane_init(Lane &l) const { l.ns = 0; l.err = 0; }
   __device__ void root_begin(Lane &, int32_t) const {}
   __device__ void root_end(Lane &, int32_t) const {}
+  // all C(s,r) probes are issued together (independent lookups), then the
+  // increments
   __device__ void operator()(Lane &l, const int32_t (&Sv)[S]) const {
     constexpr Combos<S, R> cb{};
+    constexpr int N = cb.N;
     l.ns++;
+    int32_t v1[N];
+    uint64_t key[N];
+    bool want[N];
 #pragma unroll
-    for (int q = 0; q < cb.N; q++) {
+    for (int q = 0; q < N; q++) {
       int32_t Rv[R];
 #pragma unroll
       for (int i = 0; i < R; i++) Rv[i] = Sv[cb.idx[q][i]];
-      Slot tmp;
-      int64_t pos = table_find(T, Rv[0], make_key<R>(Rv, T.bits), &tmp);
-      if (pos < 0) {
+      v1[q] = Rv[0];
+      key[q] = make_key<R>(Rv, T.bits);
+      want[q] = true;
+    }
+    int64_t pos[N];
+    Slot sl[N];
+    table_find_n<N>(T, v1, key, want, pos, sl);
+#pragma unroll
+    for (int q = 0; q < N; q++) {
+      if (pos[q] < 0) {
         l.err |= kErrLookup;
         continue;
       }
-      __hip_atomic_fetch_add(&T.slots[pos].cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&T.slots[pos[q]].cnt, 1u, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
     }
   }
   __device__ void lane_finish(Lane &l) const {
