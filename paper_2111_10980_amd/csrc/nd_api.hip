@@ -486,6 +486,9 @@ nd_status nd_run(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *cou
         hip_check(hipMemcpyAsync(p->fx.alive.get(), p->fx.bm.get(), 8 * p->fx.bm_words,
                                  hipMemcpyDeviceToDevice, st),
                   "copy bitmaps");
+      const uint64_t aw = (p->fx.n_tri + 63) / 64;  // every triangle alive
+      p->fx.alive_apex.reset(aw ? aw : 1);
+      fill_u64(p->fx.alive_apex.get(), ~0ull, (int64_t)(aw ? aw : 1), st);
     }
     tm.mark(1, st);
     // ---- bucket init + peel, driven by the device (the host polls the

@@ -103,14 +103,17 @@ struct FastView {
   const int32_t *__restrict__ lval;     // apex vertices, ascending within a list
   uint64_t *alive;                      // r = 3: bitmap copy, a triangle's bits cleared
                                         // after the round that peels it (else null)
+  uint64_t *alive_apex;                 // r = 3: one bit per apex-list entry (= per
+                                        // triangle), cleared with the triangle (else null)
 };
 struct FastIndex {
-  DevBuf<uint64_t> bm_off, bm, lptr, alive;
+  DevBuf<uint64_t> bm_off, bm, lptr, alive, alive_apex;
   DevBuf<uint64_t> loc;  // per slot: local indices of v2..vr in N+(v1), 9 bits each
   DevBuf<int32_t> lval;
   uint64_t bm_words = 0, n_tri = 0;
   FastView view() const {
-    return FastView{bm_off.get(), bm.get(), lptr.get(), lval.get(), alive.get()};
+    return FastView{bm_off.get(), bm.get(), lptr.get(), lval.get(), alive.get(),
+                    alive_apex.get()};
   }
 };
 void build_fast_index(const OrientedGraph &g, FastIndex *fx, Counters *dctr, hipStream_t st);

@@ -311,6 +311,13 @@ __global__ void k_clear_alive(GraphView g, TableView T, FastView fx,
     int32_t Rv[3];
     Rv[0] = T.v1[p];
     decode_key<3>(T.slots[p].key, T.bits, Rv);
+    {  // the triangle's apex entry: Rv[0] in the list of the arc (Rv[1], Rv[2])
+      const int64_t arc = lower_pos(g.col, g.up[Rv[1]], g.rp[Rv[1] + 1], Rv[2]);
+      const int64_t lb = (int64_t)fx.lptr[arc], le = (int64_t)fx.lptr[arc + 1];
+      const int64_t q = lower_pos(fx.lval, lb, le, Rv[0]);
+      if (q < le && fx.lval[q] == Rv[0])
+        atomicAnd((unsigned long long *)&fx.alive_apex[q >> 6], ~(1ull << (q & 63)));
+    }
     const int64_t o = g.up[Rv[0]];
     const int d = (int)(g.rp[Rv[0] + 1] - o);
     if (d > 512) continue;
@@ -425,6 +432,23 @@ __device__ __forceinline__ void peel_candidate(const PeelArgs &a, const int32_t 
 }
 
 constexpr int kListCap = 1024;  // LDS entries per wave for a staged apex list
+
+// position of x in the sorted LDS array a[0..n), or -1
+__device__ __forceinline__ int lds_find(const int32_t *a, int n, int32_t x) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const int32_t v = a[mid];
+    if (v == x) return mid;
+    if (v < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return -1;
+}
+
+__device__ __forceinline__ bool apex_alive(const uint64_t *__restrict__ bits, uint64_t q) {
+  return (bits[q >> 6] >> (q & 63)) & 1ull;
+}
 
 __device__ __forceinline__ bool lds_contains(const int32_t *a, int n, int32_t x) {
   int lo = 0, hi = n;
@@ -638,10 +662,20 @@ __global__ __launch_bounds__(256) void k_expand(PeelArgs base, RoundCtl *rc, Fas
           for (int i = 1; i < R; i++) in = in && adjacent(a.g, x, Rv[i]);
         }
       } else if (in) {
-        x = fx.lval[lb + (k - total1)];
+        const uint64_t q1 = lb + (k - total1);
+        x = fx.lval[q1];
         if constexpr (R == 3) {
-          in = staged_len >= 0 ? lds_contains(lbuf[wv], staged_len, x)
-                               : sorted_contains(fx.lval, ob, oe, x);
+          // x < v1: S = {x, v1, v2, v3}; the triangles {x, v1, v2} and {x, v1, v3}
+          // are the apex entries at q1 and at x's place in the other list
+          int64_t q2 = -1;
+          if (staged_len >= 0) {
+            const int at = lds_find(lbuf[wv], staged_len, x);
+            q2 = at >= 0 ? (int64_t)ob + at : -1;
+          } else {
+            const int64_t at = lower_pos(fx.lval, (int64_t)ob, (int64_t)oe, x);
+            q2 = at < (int64_t)oe && fx.lval[at] == x ? at : -1;
+          }
+          in = q2 >= 0 && apex_alive(fx.alive_apex, q1) && apex_alive(fx.alive_apex, (uint64_t)q2);
         } else {
 #pragma unroll
           for (int i = 1; i < R; i++)
