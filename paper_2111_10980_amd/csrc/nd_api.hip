@@ -489,6 +489,11 @@ nd_status nd_run(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *cou
       const uint64_t aw = (p->fx.n_tri + 63) / 64;  // every triangle alive
       p->fx.alive_apex.reset(aw ? aw : 1);
       fill_u64(p->fx.alive_apex.get(), ~0ull, (int64_t)(aw ? aw : 1), st);
+      // no triangle in a frontier yet
+      p->fx.front.reset(p->fx.bm_words ? p->fx.bm_words : 1);
+      fill_u64(p->fx.front.get(), 0, (int64_t)(p->fx.bm_words ? p->fx.bm_words : 1), st);
+      p->fx.front_apex.reset(aw ? aw : 1);
+      fill_u64(p->fx.front_apex.get(), 0, (int64_t)(aw ? aw : 1), st);
     }
     tm.mark(1, st);
     // ---- bucket init + peel, driven by the device (the host polls the

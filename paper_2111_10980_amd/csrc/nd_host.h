@@ -105,15 +105,18 @@ struct FastView {
                                         // after the round that peels it (else null)
   uint64_t *alive_apex;                 // r = 3: one bit per apex-list entry (= per
                                         // triangle), cleared with the triangle (else null)
+  uint64_t *front;                      // r = 3: bitmap layout, bits of the triangles
+                                        // of the current frontier (else null)
+  uint64_t *front_apex;                 // r = 3: apex-entry bits of the same (else null)
 };
 struct FastIndex {
-  DevBuf<uint64_t> bm_off, bm, lptr, alive, alive_apex;
+  DevBuf<uint64_t> bm_off, bm, lptr, alive, alive_apex, front, front_apex;
   DevBuf<uint64_t> loc;  // per slot: local indices of v2..vr in N+(v1), 9 bits each
   DevBuf<int32_t> lval;
   uint64_t bm_words = 0, n_tri = 0;
   FastView view() const {
-    return FastView{bm_off.get(), bm.get(), lptr.get(), lval.get(), alive.get(),
-                    alive_apex.get()};
+    return FastView{bm_off.get(), bm.get(),        lptr.get(),  lval.get(),
+                    alive.get(),  alive_apex.get(), front.get(), front_apex.get()};
   }
 };
 void build_fast_index(const OrientedGraph &g, FastIndex *fx, Counters *dctr, hipStream_t st);

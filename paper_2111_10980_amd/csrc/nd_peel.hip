@@ -10,8 +10,11 @@
 //
 // Update-Func subtracts 1/a from each unpeeled r-subset, a being the number
 // of peeled r-subsets of the s-clique.  Here exactly one of those a subsets,
-// the one with the smallest table index (the owner), subtracts 1; the other
-// a-1 do nothing.  The total is the same and all counts stay 32-bit integers.
+// the owner, subtracts 1; the other a-1 do nothing.  The total is the same and
+// all counts stay 32-bit integers.  The owner is the peeled subset that comes
+// first in lexicographic order of positions in the sorted s-clique (for
+// s = r+1: the one that omits the largest vertex), which the s = r+1 expand
+// pass can often decide from bitmaps before probing any slot.
 //
 // The set U of updated r-cliques is never materialised.  The only members of
 // U the bucket structure needs are those that reach the current level, and
@@ -133,8 +136,12 @@ __device__ __forceinline__ void update_func(const PeelArgs &a, const int32_t (&S
   int64_t pos[N];
   Slot sl[N];
   table_find_n<N>(a.T, v1, key, want, pos, sl);
+  int self = 0;  // this r-clique's place in the subset order
+#pragma unroll
+  for (int q = 0; q < N; q++)
+    if (cb.mask[q] == rmask) self = q;
   bool alive = active;
-  uint32_t owner = p;
+  bool other_owner = false;
   bool live[N];
 #pragma unroll
   for (int q = 0; q < N; q++) {
@@ -146,13 +153,13 @@ __device__ __forceinline__ void update_func(const PeelArgs &a, const int32_t (&S
     } else if (sl[q].stamp < a.t) {
       alive = false;  // S was destroyed in an earlier round
     } else if (sl[q].stamp == a.t) {
-      owner = (uint32_t)pos[q] < owner ? (uint32_t)pos[q] : owner;
+      other_owner = other_owner || q < self;  // peeled with R and first in order
     } else {
       live[q] = true;
     }
   }
   if (active) ls.disc++;
-  const bool mine = alive && owner == p;
+  const bool mine = alive && !other_owner;
 #pragma unroll
   for (int q = 0; q < N; q++) {
     bool want_append = false, want_low = false;
@@ -315,8 +322,10 @@ __global__ void k_clear_alive(GraphView g, TableView T, FastView fx,
       const int64_t arc = lower_pos(g.col, g.up[Rv[1]], g.rp[Rv[1] + 1], Rv[2]);
       const int64_t lb = (int64_t)fx.lptr[arc], le = (int64_t)fx.lptr[arc + 1];
       const int64_t q = lower_pos(fx.lval, lb, le, Rv[0]);
-      if (q < le && fx.lval[q] == Rv[0])
+      if (q < le && fx.lval[q] == Rv[0]) {
         atomicAnd((unsigned long long *)&fx.alive_apex[q >> 6], ~(1ull << (q & 63)));
+        atomicAnd((unsigned long long *)&fx.front_apex[q >> 6], ~(1ull << (q & 63)));
+      }
     }
     const int64_t o = g.up[Rv[0]];
     const int d = (int)(g.rp[Rv[0] + 1] - o);
@@ -328,7 +337,59 @@ __global__ void k_clear_alive(GraphView g, TableView T, FastView fx,
     unsigned long long *rows = (unsigned long long *)(fx.alive + fx.bm_off[Rv[0]]);
     atomicAnd(&rows[i * wd + (j >> 6)], ~(1ull << (j & 63)));
     atomicAnd(&rows[j * wd + (i >> 6)], ~(1ull << (i & 63)));
+    unsigned long long *fr = (unsigned long long *)(fx.front + fx.bm_off[Rv[0]]);
+    atomicAnd(&fr[i * wd + (j >> 6)], ~(1ull << (j & 63)));
+    atomicAnd(&fr[j * wd + (i >> 6)], ~(1ull << (i & 63)));
   }
+}
+
+// r = 3: mark the triangles of the frontier in the frontier bitmaps (the
+// same positions k_clear_alive clears after the round), so the expand pass
+// can tell which s-cliques another member of the frontier owns.
+__global__ void k_mark_front(GraphView g, TableView T, FastView fx,
+                             const RoundCtl *__restrict__ rc) {
+  if (rc_idle(rc)) return;
+  const uint32_t *__restrict__ F = rc->F;
+  const uint32_t nF = rc->nF;
+  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < nF;
+       it += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t p = F[it];
+    int32_t Rv[3];
+    Rv[0] = T.v1[p];
+    decode_key<3>(T.slots[p].key, T.bits, Rv);
+    {
+      const int64_t arc = lower_pos(g.col, g.up[Rv[1]], g.rp[Rv[1] + 1], Rv[2]);
+      const int64_t lb = (int64_t)fx.lptr[arc], le = (int64_t)fx.lptr[arc + 1];
+      const int64_t q = lower_pos(fx.lval, lb, le, Rv[0]);
+      if (q < le && fx.lval[q] == Rv[0])
+        atomicOr((unsigned long long *)&fx.front_apex[q >> 6], 1ull << (q & 63));
+    }
+    const int64_t o = g.up[Rv[0]];
+    const int d = (int)(g.rp[Rv[0] + 1] - o);
+    if (d > 512) continue;
+    const int64_t i = lower_pos(g.col, o, o + d, Rv[1]) - o;
+    const int64_t j = lower_pos(g.col, o, o + d, Rv[2]) - o;
+    if (i >= d || j >= d) continue;
+    const int wd = (d + 63) >> 6;
+    unsigned long long *fr = (unsigned long long *)(fx.front + fx.bm_off[Rv[0]]);
+    atomicOr(&fr[i * wd + (j >> 6)], 1ull << (j & 63));
+    atomicOr(&fr[j * wd + (i >> 6)], 1ull << (i & 63));
+  }
+}
+
+// Bits of word w of a bitmap row at local positions < l.
+__device__ __forceinline__ uint64_t below_mask(int64_t l, int w) {
+  const int64_t lo = (int64_t)w * 64;
+  if (l >= lo + 64) return ~0ull;
+  if (l <= lo) return 0ull;
+  return (1ull << (l - lo)) - 1ull;
+}
+
+// r = 3, x > v1: candidates whose s-clique another frontier triangle owns,
+// i.e. {v1, v2, x} peeled now with v3 > x, or {v1, v3, x} with v2 > x.
+__device__ __forceinline__ uint64_t owned_elsewhere(const uint64_t *__restrict__ fr, int64_t l2,
+                                                    int64_t l3, int wd, int w) {
+  return (fr[l2 * wd + w] & below_mask(l3, w)) | (fr[l3 * wd + w] & below_mask(l2, w));
 }
 
 // count(R) = |I(R)|, computed per r-clique without atomics.
@@ -533,6 +594,8 @@ __global__ __launch_bounds__(256) void k_expand_bound(PeelArgs base, RoundCtl *r
             uint64_t x = ~0ull;
 #pragma unroll
             for (int i = 1; i < R; i++) x &= rows[(e[i] - o) * wd + w];
+            if constexpr (R == 3)
+              x &= ~owned_elsewhere(fx.front + fx.bm_off[Rv[0]], e[1] - o, e[2] - o, wd, w);
             total1 += (uint64_t)__popcll(x);
           }
         } else {
@@ -602,6 +665,8 @@ __global__ __launch_bounds__(256) void k_expand(PeelArgs base, RoundCtl *rc, Fas
         cw = ~0ull;
 #pragma unroll
         for (int i = 1; i < R; i++) cw &= rows[(e[i] - o) * wd + lane];
+        if constexpr (R == 3)
+          cw &= ~owned_elsewhere(fx.front + fx.bm_off[v1], e[1] - o, e[2] - o, wd, lane);
       }
       const uint32_t incl = wave_incl_scan((uint32_t)__popcll(cw));
       total1 = __shfl(incl, kWave - 1);
@@ -675,7 +740,9 @@ __global__ __launch_bounds__(256) void k_expand(PeelArgs base, RoundCtl *rc, Fas
             const int64_t at = lower_pos(fx.lval, (int64_t)ob, (int64_t)oe, x);
             q2 = at < (int64_t)oe && fx.lval[at] == x ? at : -1;
           }
-          in = q2 >= 0 && apex_alive(fx.alive_apex, q1) && apex_alive(fx.alive_apex, (uint64_t)q2);
+          // both triangles still alive, and neither peeled now (it would own S)
+          in = q2 >= 0 && apex_alive(fx.alive_apex, q1) && apex_alive(fx.alive_apex, (uint64_t)q2) &&
+               !apex_alive(fx.front_apex, q1) && !apex_alive(fx.front_apex, (uint64_t)q2);
         } else {
 #pragma unroll
           for (int i = 1; i < R; i++)
@@ -1381,6 +1448,8 @@ void launch_walker(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, hipEvent_t
 template <int R>
 void launch_fast(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, dim3 ga, hipEvent_t e0,
                  hipEvent_t e1) {
+  if (R == 3)
+    hipLaunchKernelGGL(k_mark_front, gf, dim3(256), 0, E.st, E.gv, E.T, E.fxv, E.rc.get());
   hipLaunchKernelGGL(k_expand_bound<R>, gf, dim3(256), 0, E.st, base, E.rc.get(), E.fxv, E.loc,
                      E.off.get(), E.len.get(), E.fv.get());
   hipLaunchKernelGGL(k_expand<R>, gw, dim3(256), 0, E.st, base, E.rc.get(), E.fxv, E.loc,
