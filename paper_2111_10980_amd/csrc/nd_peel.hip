@@ -59,6 +59,8 @@ struct LaneStats {
 };
 
 constexpr int kAppendCap = 512;  // LDS entries per wave for next-frontier appends
+constexpr int kApexShift = 18;   // r = 3 loc word: 1 + apex-entry position in bits 18..61
+constexpr uint64_t kApexMask = (1ull << 44) - 1;
 using Appender = WaveAppender<kAppendCap>;
 
 // Round kernels run only while rounds remain and the host has not been asked
@@ -307,73 +309,48 @@ __device__ __forceinline__ int64_t lower_pos(const int32_t *__restrict__ a, int6
 // r = 3 liveness bitmaps.  A triangle's bits in its root's alive bitmap are
 // cleared after the round that peels it, so the AND of two alive rows lists
 // only candidates whose two triangles through v1 were not peeled earlier.
-__global__ void k_clear_alive(GraphView g, TableView T, FastView fx,
-                              const RoundCtl *__restrict__ rc) {
+// r = 3, after the round: the triangles of the frontier are gone, so their
+// bits leave the alive bitmaps, the apex alive bits and the frontier marks.
+// With mark = true (before the round's bound pass) their frontier bits are
+// set instead: the expand pass can then tell which s-cliques another member
+// of the frontier owns.  Positions come from the slot's loc word.
+template <bool kMark>
+__global__ void k_front_bits(GraphView g, TableView T, FastView fx,
+                             const uint64_t *__restrict__ loc, const RoundCtl *__restrict__ rc) {
   if (rc_idle(rc)) return;
   const uint32_t *__restrict__ F = rc->F;
   const uint32_t nF = rc->nF;
   for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < nF;
        it += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t p = F[it];
-    int32_t Rv[3];
-    Rv[0] = T.v1[p];
-    decode_key<3>(T.slots[p].key, T.bits, Rv);
-    {  // the triangle's apex entry: Rv[0] in the list of the arc (Rv[1], Rv[2])
-      const int64_t arc = lower_pos(g.col, g.up[Rv[1]], g.rp[Rv[1] + 1], Rv[2]);
-      const int64_t lb = (int64_t)fx.lptr[arc], le = (int64_t)fx.lptr[arc + 1];
-      const int64_t q = lower_pos(fx.lval, lb, le, Rv[0]);
-      if (q < le && fx.lval[q] == Rv[0]) {
-        atomicAnd((unsigned long long *)&fx.alive_apex[q >> 6], ~(1ull << (q & 63)));
-        atomicAnd((unsigned long long *)&fx.front_apex[q >> 6], ~(1ull << (q & 63)));
+    const uint64_t lc = loc[p];
+    const uint64_t ap = (lc >> kApexShift) & kApexMask;
+    if (ap) {
+      const uint64_t q = ap - 1, bit = 1ull << (q & 63);
+      if (kMark) {
+        atomicOr((unsigned long long *)&fx.front_apex[q >> 6], bit);
+      } else {
+        atomicAnd((unsigned long long *)&fx.alive_apex[q >> 6], ~bit);
+        atomicAnd((unsigned long long *)&fx.front_apex[q >> 6], ~bit);
       }
     }
-    const int64_t o = g.up[Rv[0]];
-    const int d = (int)(g.rp[Rv[0] + 1] - o);
-    if (d > 512) continue;
-    const int64_t i = lower_pos(g.col, o, o + d, Rv[1]) - o;
-    const int64_t j = lower_pos(g.col, o, o + d, Rv[2]) - o;
-    if (i >= d || j >= d) continue;
+    if (!(lc >> 63)) continue;  // root without a bitmap
+    const int32_t v1 = T.v1[p];
+    const int d = (int)(g.rp[v1 + 1] - g.up[v1]);
     const int wd = (d + 63) >> 6;
-    unsigned long long *rows = (unsigned long long *)(fx.alive + fx.bm_off[Rv[0]]);
-    atomicAnd(&rows[i * wd + (j >> 6)], ~(1ull << (j & 63)));
-    atomicAnd(&rows[j * wd + (i >> 6)], ~(1ull << (i & 63)));
-    unsigned long long *fr = (unsigned long long *)(fx.front + fx.bm_off[Rv[0]]);
-    atomicAnd(&fr[i * wd + (j >> 6)], ~(1ull << (j & 63)));
-    atomicAnd(&fr[j * wd + (i >> 6)], ~(1ull << (i & 63)));
-  }
-}
-
-// r = 3: mark the triangles of the frontier in the frontier bitmaps (the
-// same positions k_clear_alive clears after the round), so the expand pass
-// can tell which s-cliques another member of the frontier owns.
-__global__ void k_mark_front(GraphView g, TableView T, FastView fx,
-                             const RoundCtl *__restrict__ rc) {
-  if (rc_idle(rc)) return;
-  const uint32_t *__restrict__ F = rc->F;
-  const uint32_t nF = rc->nF;
-  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < nF;
-       it += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t p = F[it];
-    int32_t Rv[3];
-    Rv[0] = T.v1[p];
-    decode_key<3>(T.slots[p].key, T.bits, Rv);
-    {
-      const int64_t arc = lower_pos(g.col, g.up[Rv[1]], g.rp[Rv[1] + 1], Rv[2]);
-      const int64_t lb = (int64_t)fx.lptr[arc], le = (int64_t)fx.lptr[arc + 1];
-      const int64_t q = lower_pos(fx.lval, lb, le, Rv[0]);
-      if (q < le && fx.lval[q] == Rv[0])
-        atomicOr((unsigned long long *)&fx.front_apex[q >> 6], 1ull << (q & 63));
+    const int64_t i = (int64_t)(lc & 511u), j = (int64_t)((lc >> 9) & 511u);
+    const uint64_t bi = 1ull << (i & 63), bj = 1ull << (j & 63);
+    unsigned long long *fr = (unsigned long long *)(fx.front + fx.bm_off[v1]);
+    if (kMark) {
+      atomicOr(&fr[i * wd + (j >> 6)], bj);
+      atomicOr(&fr[j * wd + (i >> 6)], bi);
+    } else {
+      unsigned long long *al = (unsigned long long *)(fx.alive + fx.bm_off[v1]);
+      atomicAnd(&al[i * wd + (j >> 6)], ~bj);
+      atomicAnd(&al[j * wd + (i >> 6)], ~bi);
+      atomicAnd(&fr[i * wd + (j >> 6)], ~bj);
+      atomicAnd(&fr[j * wd + (i >> 6)], ~bi);
     }
-    const int64_t o = g.up[Rv[0]];
-    const int d = (int)(g.rp[Rv[0] + 1] - o);
-    if (d > 512) continue;
-    const int64_t i = lower_pos(g.col, o, o + d, Rv[1]) - o;
-    const int64_t j = lower_pos(g.col, o, o + d, Rv[2]) - o;
-    if (i >= d || j >= d) continue;
-    const int wd = (d + 63) >> 6;
-    unsigned long long *fr = (unsigned long long *)(fx.front + fx.bm_off[Rv[0]]);
-    atomicOr(&fr[i * wd + (j >> 6)], 1ull << (j & 63));
-    atomicOr(&fr[j * wd + (i >> 6)], 1ull << (i & 63));
   }
 }
 
@@ -886,9 +863,13 @@ __global__ __launch_bounds__(256) void k_count_wave(PeelArgs a, FastView fx,
 }
 
 // Local indices of v2..vr in N+(v1) for every occupied slot of a bitmap
-// root (9 bits each, bit 63 marks them valid).
+// root (9 bits each, bit 63 marks them valid).  For r = 3 bits 18..61 also
+// hold 1 + the position of the triangle's apex entry (v1 in the list of the
+// arc (v2, v3)), 0 if it has none.
+
 template <int R>
-__global__ void k_make_loc(GraphView g, TableView T, uint64_t n_slots, uint64_t *loc) {
+__global__ void k_make_loc(GraphView g, TableView T, FastView fx, uint64_t n_slots,
+                           uint64_t *loc) {
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < (int64_t)n_slots;
        p += (int64_t)gridDim.x * blockDim.x) {
     const Slot sl = T.slots[p];
@@ -915,6 +896,12 @@ __global__ void k_make_loc(GraphView g, TableView T, uint64_t n_slots, uint64_t 
           for (int i = 1; i < R; i++) v |= (uint64_t)(at[i - 1] - o) << (9 * (i - 1));
         }
       }
+      if constexpr (R == 3) {
+        const int64_t arc = lower_pos(g.col, g.up[Rv[1]], g.rp[Rv[1] + 1], Rv[2]);
+        const int64_t lb = (int64_t)fx.lptr[arc], le = (int64_t)fx.lptr[arc + 1];
+        const int64_t q = lower_pos(fx.lval, lb, le, Rv[0]);
+        if (q < le && fx.lval[q] == Rv[0]) v |= (((uint64_t)q + 1) & kApexMask) << kApexShift;
+      }
     }
     loc[p] = v;
   }
@@ -922,12 +909,14 @@ __global__ void k_make_loc(GraphView g, TableView T, uint64_t n_slots, uint64_t 
 
 // ---------------------------------------------------------- round control
 // One round is queued as
-//   k_adv_min<false>, k_adv_min<true>, k_adv_partition, k_adv_finish
+//   k_adv_min<false>, k_adv_min<true>, k_adv_partition
 //       level advance; they act only when the round starts with an empty
 //       frontier (B.next_bucket of Algorithm 2);
-//   k_round_begin            one thread: the round's lists and counters;
+//   k_round_begin            one thread: finishes an advance, then the
+//                            round's lists and counters;
+//   [k_front_bits<true>]     r = 3 frontier marks;
 //   the update passes of the path (the first one stamps A_t with t);
-//   [k_clear_alive]          r = 3 liveness bitmaps;
+//   [k_front_bits<false>]    r = 3 liveness bitmaps and marks;
 //   k_round_end              one thread: trace, finished += |A_t|, next frontier.
 // Every kernel returns at once once the peel has finished or halted, so the
 // host may queue rounds past the last one and read the state only now and
@@ -975,7 +964,7 @@ __global__ __launch_bounds__(kPartThreads) void k_adv_partition(RoundCtl *rc,
   if (rc_idle(rc) || rc->nF != 0) return;
   const bool win = rc->nW != 0 && rc->mw != kNone;
   const uint32_t mn = win ? rc->mw : rc->mh;
-  if (mn == kNone) return;  // k_adv_finish reports it
+  if (mn == kNone) return;  // k_round_begin reports it
   const uint32_t k = rc->k > mn ? rc->k : mn;
   const uint32_t kw = win ? 0xFFFFFFFEu : k + kWindowLevels;
   const uint32_t *__restrict__ L = win ? rc->bufW[rc->selW] : rc->bufH[rc->selH];
@@ -1036,35 +1025,35 @@ __global__ __launch_bounds__(kPartThreads) void k_adv_partition(RoundCtl *rc,
   }
 }
 
-// One thread: k <- max(k, minimum), new list sizes, swap the list buffers.
-__global__ void k_adv_finish(RoundCtl *rc) {
-  if (rc_idle(rc) || rc->nF != 0) return;
-  const bool win = rc->nW != 0 && rc->mw != kNone;
-  const uint32_t mn = win ? rc->mw : rc->mh;
-  if (mn == kNone || rc->cF == 0) {  // no live r-clique left, or an empty bucket
-    rc->err |= kErrBucket;
-    rc->halt = 3;
-    return;
-  }
-  rc->k = rc->k > mn ? rc->k : mn;
-  if (win) {
-    rc->selW ^= 1u;
-  } else {
-    rc->kw = rc->k + kWindowLevels;
-    rc->nH = rc->cH;
-    rc->selH ^= 1u;
-  }
-  rc->nW = rc->cW;
-  rc->nF = rc->cF;
-  rc->advances++;
-  rc->mw = kNone;
-  rc->mh = kNone;
-  rc->cF = rc->cW = rc->cH = 0;
-}
-
+// One thread.  After a level advance (the round started with an empty
+// frontier): k <- max(k, minimum), new list sizes, swap the list buffers.
+// Then the round's lists and counters.
 __global__ void k_round_begin(RoundCtl *rc, Counters *dc) {
   if (rc_idle(rc)) return;
-  if (rc->t >= rc->trace_cap) {  // the host grows the round trace
+  if (rc->nF == 0) {  // finish the advance first: a rerun must not partition again
+    const bool win = rc->nW != 0 && rc->mw != kNone;
+    const uint32_t mn = win ? rc->mw : rc->mh;
+    if (mn == kNone || rc->cF == 0) {  // no live r-clique left, or an empty bucket
+      rc->err |= kErrBucket;
+      rc->halt = 3;
+      return;
+    }
+    rc->k = rc->k > mn ? rc->k : mn;
+    if (win) {
+      rc->selW ^= 1u;
+    } else {
+      rc->kw = rc->k + kWindowLevels;
+      rc->nH = rc->cH;
+      rc->selH ^= 1u;
+    }
+    rc->nW = rc->cW;
+    rc->nF = rc->cF;
+    rc->advances++;
+    rc->mw = kNone;
+    rc->mh = kNone;
+    rc->cF = rc->cW = rc->cH = 0;
+  }
+  if (rc->t >= rc->trace_cap) {  // the host grows the round trace, then reruns
     rc->halt = 2;
     return;
   }
@@ -1449,7 +1438,8 @@ template <int R>
 void launch_fast(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, dim3 ga, hipEvent_t e0,
                  hipEvent_t e1) {
   if (R == 3)
-    hipLaunchKernelGGL(k_mark_front, gf, dim3(256), 0, E.st, E.gv, E.T, E.fxv, E.rc.get());
+    hipLaunchKernelGGL(k_front_bits<true>, gf, dim3(256), 0, E.st, E.gv, E.T, E.fxv, E.loc,
+                       E.rc.get());
   hipLaunchKernelGGL(k_expand_bound<R>, gf, dim3(256), 0, E.st, base, E.rc.get(), E.fxv, E.loc,
                      E.off.get(), E.len.get(), E.fv.get());
   hipLaunchKernelGGL(k_expand<R>, gw, dim3(256), 0, E.st, base, E.rc.get(), E.fxv, E.loc,
@@ -1459,7 +1449,8 @@ void launch_fast(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, dim3 ga, hip
                      E.fv.get());
   if (e1) hipEventRecord(e1, E.st);
   if (R == 3)
-    hipLaunchKernelGGL(k_clear_alive, gf, dim3(256), 0, E.st, E.gv, E.T, E.fxv, E.rc.get());
+    hipLaunchKernelGGL(k_front_bits<false>, gf, dim3(256), 0, E.st, E.gv, E.T, E.fxv, E.loc,
+                       E.rc.get());
 }
 
 template <int R, int S>
@@ -1492,7 +1483,8 @@ void enqueue_round(Engine &E, const RoundCtl &m, bool exact, hipEvent_t e0, hipE
   const hipStream_t st = E.st;
   RoundCtl *rc = E.rc.get();
   if (!exact || m.nF == 0) {
-    const uint64_t cap_b = exact ? 8192 : 1024;
+    // queued behind other rounds these act only now and then: small grids
+    const uint64_t cap_b = exact ? 8192 : 256;
     hipLaunchKernelGGL(k_adv_min<false>, blocks_for(m.nW, 256 * 8, 1, cap_b), dim3(256), 0, st, rc,
                        E.T.slots);
     hipLaunchKernelGGL(k_adv_min<true>, blocks_for(m.nH, 256 * 8, 1, cap_b), dim3(256), 0, st, rc,
@@ -1500,7 +1492,6 @@ void enqueue_round(Engine &E, const RoundCtl &m, bool exact, hipEvent_t e0, hipE
     hipLaunchKernelGGL(k_adv_partition,
                        blocks_for(m.nW > m.nH ? m.nW : m.nH, kPartThreads * kPartItems, 1, cap_b),
                        dim3(kPartThreads), 0, st, rc, E.T.slots);
-    hipLaunchKernelGGL(k_adv_finish, dim3(1), dim3(1), 0, st, rc);
   }
   if (e_adv) hipEventRecord(e_adv, st);
   hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, st, rc, E.dc);
@@ -1777,12 +1768,13 @@ void build_slot_loc(const OrientedGraph &g, int r, const TableView &T, uint64_t 
   if (!n_slots) return;
   dim3 grid((unsigned)grid_for(n_slots, 256)), blk(256);
   const GraphView gv = g.view();
+  const FastView fv = fx->view();
   switch (r) {
-    case 2: hipLaunchKernelGGL(k_make_loc<2>, grid, blk, 0, st, gv, T, n_slots, fx->loc.get()); break;
-    case 3: hipLaunchKernelGGL(k_make_loc<3>, grid, blk, 0, st, gv, T, n_slots, fx->loc.get()); break;
-    case 4: hipLaunchKernelGGL(k_make_loc<4>, grid, blk, 0, st, gv, T, n_slots, fx->loc.get()); break;
-    case 5: hipLaunchKernelGGL(k_make_loc<5>, grid, blk, 0, st, gv, T, n_slots, fx->loc.get()); break;
-    case 6: hipLaunchKernelGGL(k_make_loc<6>, grid, blk, 0, st, gv, T, n_slots, fx->loc.get()); break;
+    case 2: hipLaunchKernelGGL(k_make_loc<2>, grid, blk, 0, st, gv, T, fv, n_slots, fx->loc.get()); break;
+    case 3: hipLaunchKernelGGL(k_make_loc<3>, grid, blk, 0, st, gv, T, fv, n_slots, fx->loc.get()); break;
+    case 4: hipLaunchKernelGGL(k_make_loc<4>, grid, blk, 0, st, gv, T, fv, n_slots, fx->loc.get()); break;
+    case 5: hipLaunchKernelGGL(k_make_loc<5>, grid, blk, 0, st, gv, T, fv, n_slots, fx->loc.get()); break;
+    case 6: hipLaunchKernelGGL(k_make_loc<6>, grid, blk, 0, st, gv, T, fv, n_slots, fx->loc.get()); break;
     default: break;
   }
 }
