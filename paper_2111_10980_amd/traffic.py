@@ -7,7 +7,8 @@ plain copy kernel ``k_copy`` of the roofline probes, which moves a known
 number of bytes (1 GiB read + 1 GiB written per dispatch), so the figure is in
 true bytes whatever the counter's unit convention.
 
-The result is written as JSON together with a hash of the HIP sources, so a
+The result is written as JSON together with a hash of the HIP sources that
+define the peel kernels (the peel module and the headers it includes), so a
 reader can tell whether the numbers still describe the current kernels.
 
 Usage:
@@ -26,14 +27,16 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 1 << 30  # k_copy: bytes read (and written) per dispatch
 
 
+KERNEL_SOURCES = ("nd_peel.hip", "nd_internal.h", "nd_host.h")
+
+
 def source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
