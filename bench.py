@@ -30,6 +30,7 @@ SLOT_BYTES = 16                # one r-clique table slot {key, count, stamp}
 
 BATCH_WORKLOAD = "batch4096_34"
 SERVE_WORKLOAD = "serve_rmat"
+SWEEP_WORKLOAD = "rmat_density_sweep"
 
 WORKLOADS = {
     # name: (generator, r, s, description)
@@ -67,7 +68,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat18_34",
-                    choices=sorted(WORKLOADS) + [BATCH_WORKLOAD, SERVE_WORKLOAD])
+                    choices=sorted(WORKLOADS) + [BATCH_WORKLOAD, SERVE_WORKLOAD, SWEEP_WORKLOAD])
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--rates", default="5,10,20,40",
                     help="serving: Poisson arrival rates (jobs/s) to sweep")
@@ -93,6 +94,8 @@ def main():
         return bench_batch(args)
     if args.workload == SERVE_WORKLOAD:
         return bench_serve(args)
+    if args.workload == SWEEP_WORKLOAD:
+        return bench_sweep(args)
     gen, r, s, desc = WORKLOADS[args.workload]
     t0 = time.perf_counter()
     g = getattr(inputs, gen)() if args.seed is None else getattr(inputs, gen)(args.seed)
@@ -269,6 +272,55 @@ def bench_batch(args):
                    "sum_n": int(sum(g.n for g in gs)), "sum_m": int(sum(g.m for g in gs)),
                    "n_r": st["n_r"], "n_s": st["n_s"], "rounds": st["rounds"],
                    "phase_ms": st["ms"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_sweep(args):
+    """The paper's rMAT density sweep (a=.5, b=c=.1, d=.3): scale 16, edge
+    factor 4..32, for (2,3), (3,4) and (4,5); one timed decomposition per
+    point after a warm-up, s-clique peel updates/s per point."""
+    import torch
+    import paper_2111_10980_amd as nd
+    from paper_2111_10980_amd import inputs
+    torch.cuda.set_device(0)
+    points = []
+    tot_ns, tot_s = 0, 0.0
+    for ef in inputs.DENSITY_SWEEP_EF:
+        g = inputs.rmat_paper(inputs.DENSITY_SWEEP_SCALE, ef, 5000 + ef)
+        rp, col = nd.to_device(g, "cuda:0")
+        for r, s in inputs.DENSITY_SWEEP_RS:
+            for _ in range(args.warmup):
+                nd.decompose(rp, col, r, s)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                d = nd.decompose(rp, col, r, s)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / max(1, args.steps)
+            st = d.stats
+            tot_ns += st["n_s"]
+            tot_s += dt
+            points.append({"edge_factor": ef, "m": g.m, "r": r, "s": s, "n_r": st["n_r"],
+                           "n_s": st["n_s"], "rounds": st["rounds"], "max_kappa": st["max_kappa"],
+                           "ms": dt * 1000.0, "s_cliques_per_s": st["n_s"] / dt})
+            log(f"[bench] ef {ef:2d} ({r},{s}): m={g.m} n_r={st['n_r']} n_s={st['n_s']} "
+                f"rounds={st['rounds']} {dt * 1000:.1f} ms")
+    out = {
+        "metric": "s-clique peel updates/sec",
+        "value": tot_ns / tot_s,
+        "unit": "s-cliques/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": tot_s * 1000.0,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": SWEEP_WORKLOAD, "scale": inputs.DENSITY_SWEEP_SCALE,
+                   "abcd": [0.5, 0.1, 0.1, 0.3], "points": points},
     }
     print(json.dumps(out), flush=True)
 

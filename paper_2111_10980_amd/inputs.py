@@ -244,6 +244,18 @@ def er_2000(seed: int = 1) -> CSR:
     return erdos_renyi(2000, 10000, seed)
 
 
+def rmat_paper(scale: int, edge_factor: int, seed: int) -> CSR:
+    """rMAT with the paper's own parameters (a, b, c, d) = (.5, .1, .1, .3)
+    (Section 5.1), used for its density sweep over edge factors."""
+    return rmat(scale, edge_factor, seed, a=0.5, b=0.1, c=0.1, d=0.3)
+
+
+# the density sweep: scale 16, edge factor 4..32, seed 5000 + edge factor
+DENSITY_SWEEP_SCALE = 16
+DENSITY_SWEEP_EF = (4, 8, 16, 32)
+DENSITY_SWEEP_RS = ((2, 3), (3, 4), (4, 5))
+
+
 def rmat18(seed: int = 18) -> CSR:
     """rMAT scale 18, edge factor 16, (a,b,c,d) = (.57,.19,.19,.05); the (3,4)
     single-graph workload."""

@@ -144,6 +144,14 @@ def test_rmat_flattened_update(r, s):
     check_against_oracle(g, r, s)
 
 
+@pytest.mark.parametrize("ef", [2, 4, 8, 16])
+@pytest.mark.parametrize("r,s", [(2, 3), (3, 4), (4, 5)])
+def test_paper_rmat_density_sweep_small(ef, r, s):
+    """The paper's own rMAT parameters (a=.5, b=c=.1, d=.3) over a density
+    sweep, at a size the oracle finishes quickly."""
+    check_against_oracle(inputs.rmat_paper(9, ef, 5000 + ef), r, s)
+
+
 @pytest.mark.parametrize("r,s", [(3, 4), (4, 5), (2, 4)])
 def test_chung_lu_small(r, s):
     g = inputs.chung_lu_planted(3000, 8.0, 2.1, 4, 8, 16, 77)
