@@ -151,9 +151,18 @@ def main():
     launches = max(1, launches)
     achieved = nbytes / (t_ms / 1000.0) / 1e9 if t_ms > 0 else 0.0
     n_launch = max(1, launches)
-    # measured device ceilings; k_copy inside also calibrates the HBM counters
-    ceil = nd.nd_roofline_measure(st["table_slots"] * SLOT_BYTES, st["n_r"] * 4)
+    # measured device ceilings over buffers the size of the r-clique table
+    # (probes and decrements both land in its slots); k_copy inside also
+    # calibrates the HBM counters
+    table_bytes = st["table_slots"] * SLOT_BYTES
+    ceil = nd.nd_roofline_measure(table_bytes, table_bytes)
     log(f"[bench] ceilings: {ceil}")
+    # random-access model of the peel's update pass: every discovered s-clique
+    # probes its C(s,r)-1 other slots; every decrement is a returning atomic
+    probes = st["discoveries"] * (c - 1)
+    model_ms = 1000.0 * (probes / (ceil["gather16_gops"] * 1e9) +
+                         st["decrements"] / (ceil["atomic_ret_gops"] * 1e9))
+    peel_step_ms = peel_ms / len(runs)
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"traffic_{kern.split('<')[0]}_{args.workload}.json")
     if os.path.exists(tfile):
@@ -168,7 +177,11 @@ def main():
                 "algorithmic_bytes_per_launch": nbytes // n_launch,
                 "count_kernel_ms_per_step": round(cnt_ms / len(runs), 3),
                 "peel_kernel_ms_per_step": round(peel_ms / len(runs), 3),
-                "measured_ceilings": {k: round(v, 3) for k, v in ceil.items()}}
+                "measured_ceilings": {k: round(v, 3) for k, v in ceil.items()},
+                "random_access_model": {
+                    "probes": probes, "atomics": st["decrements"],
+                    "model_ms": round(model_ms, 2),
+                    "frac": round(model_ms / peel_step_ms, 4) if peel_step_ms > 0 else None}}
 
     base = None
     if not args.no_cpu_baseline:
