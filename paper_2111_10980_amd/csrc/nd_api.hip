@@ -356,12 +356,18 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
     if (p->budget && graph_bytes > p->budget) fail(ND_ENOMEM, "graph exceeds the HBM budget");
     orient_relabel(n, gin->nnz, gin->row_ptr, gin->col, p->opt.orient, &p->g, st);
     tm.mark(2, st);
-    // r-clique table: count per first vertex, capacities, prefix sum
+    // r-clique table: count per first vertex, capacities, prefix sum.  For
+    // (3,4)-type plans the triangles of bitmap roots are placed by rank
+    // (ordered within a root), so the bitmaps are built first.
+    const bool ranked = p->fast && r == 3;
+    if (ranked) build_fast_index(p->g, &p->fx, p->ctr.get(), st);
     DevBuf<uint32_t> cnt(n > 0 ? (size_t)n : 1);
     count_rcliques(p->g, r, cnt.get(), st);
     p->seg.reset((size_t)n + 1);
     fill_u64(p->seg.get() + n, 0, 1, st);
-    if (n > 0)
+    if (ranked)
+      ranked_caps(p->g, &p->fx, cnt.get(), p->opt.load_factor, p->seg.get(), st);
+    else if (n > 0)
       hipLaunchKernelGGL(k_caps, dim3((unsigned)grid_for(n, 256)), dim3(256), 0, st, n, r,
                          p->opt.load_factor, cnt.get(), p->seg.get());
     scan_exclusive_u64(p->seg.get(), p->seg.get(), (int64_t)n + 1, st);
@@ -380,13 +386,18 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
     p->v1.reset(p->n_slots ? p->n_slots : 1);
     fill_slots(p->slots.get(), (int64_t)p->n_slots, st);
     fill_u32(&p->ctr.get()->err, 0, 1, st);
-    insert_rcliques(p->g, r, p->table(), p->ctr.get(), st);
+    if (ranked) {
+      ranked_insert(p->g, p->fx, p->table(), st);
+      insert_rcliques_heavy3(p->g, p->table(), p->ctr.get(), st);
+    } else {
+      insert_rcliques(p->g, r, p->table(), p->ctr.get(), st);
+    }
     p->occ.reset(p->n_r ? p->n_r : 1);
     occupied_list(p->slots.get(), p->n_slots, p->occ.get(), st);
     uint32_t err = read_dev(&p->ctr.get()->err, st);
     if (err) fail(ND_EHIP, "r-clique table build failed (flags %u)", err);
     if (p->fast) {
-      build_fast_index(p->g, &p->fx, p->ctr.get(), st);
+      if (!ranked) build_fast_index(p->g, &p->fx, p->ctr.get(), st);
       build_slot_loc(p->g, r, p->table(), p->n_slots, &p->fx, st);
       p->held += p->fx.bm_words * 8 + p->fx.n_tri * 4 + (uint64_t)(gin->nnz + 1) * 8 +
                  p->n_slots * 8;

@@ -455,6 +455,17 @@ void insert_rcliques(const OrientedGraph &g, int r, const TableView &T, Counters
   }
 }
 
+void insert_rcliques_heavy3(const OrientedGraph &g, const TableView &T, Counters *dctr,
+                            hipStream_t st) {
+  if (g.n == 0) return;
+  Bins b;
+  bin_roots(g, 2, dctr, &b, st);
+  if (b.size[4])
+    hipLaunchKernelGGL((k_list_heavy<3, InsertOp<3>>),
+                       dim3(b.size[4] < 262144u ? b.size[4] : 262144u), dim3(kWave), 0, st,
+                       g.view(), b.list(4), b.size[4], InsertOp<3>{T, dctr});
+}
+
 void list_apex_keys(const OrientedGraph &g, uint64_t *cursor, uint64_t *keys, int xbits,
                     Counters *dctr, hipStream_t st) {
   if (g.n == 0) return;

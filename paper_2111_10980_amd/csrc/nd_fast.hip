@@ -118,6 +118,119 @@ int bits_for(uint64_t maxval) {
 
 }  // namespace
 
+// ---- ranked triangle table (r = 3)
+
+namespace {
+
+// bits of word w of a row that lie strictly above local position i
+__device__ __forceinline__ uint64_t above_mask(int i, int w) {
+  const int lo = w * 64;
+  if (i < lo) return ~0ull;
+  if (i >= lo + 63) return 0ull;
+  return ~((1ull << (i - lo + 1)) - 1ull);
+}
+
+// One wave per bitmap root: triangles per row above the diagonal, prefix
+// summed over the root's rows into rowpre (indexed by out-arc position).
+__global__ __launch_bounds__(256) void k_rank_rows(GraphView g, const uint64_t *__restrict__ bm_off,
+                                                   const uint64_t *__restrict__ bm,
+                                                   uint32_t *rowpre) {
+  const int wpb = blockDim.x / kWave;
+  const int lane = lane_id();
+  for (int64_t v = (int64_t)blockIdx.x * wpb + threadIdx.x / kWave; v < g.n;
+       v += (int64_t)gridDim.x * wpb) {
+    const int64_t o = g.up[v];
+    const int d = (int)(g.rp[v + 1] - o);
+    if (d < 1 || d > 512) continue;
+    const int wd = (d + 63) >> 6;
+    const uint64_t *rows = bm + bm_off[v];
+    uint32_t carry = 0;
+    for (int b0 = 0; b0 < d; b0 += kWave) {
+      const int i = b0 + lane;
+      uint32_t c = 0;
+      if (i < d)
+        for (int w = 0; w < wd; w++) c += (uint32_t)__popcll(rows[i * wd + w] & above_mask(i, w));
+      const uint32_t incl = wave_incl_scan(c);
+      if (i < d) rowpre[o + i] = carry + incl - c;
+      carry += __shfl(incl, kWave - 1);
+    }
+  }
+}
+
+// bitmap roots: exactly their triangle count; others: hashed capacity
+__global__ void k_caps_ranked(GraphView g, float lf, const uint32_t *__restrict__ cnt,
+                              uint64_t *cap) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t d = g.rp[v + 1] - g.up[v];
+    const uint64_t c = cnt[v];
+    uint64_t k = 0;
+    if (c != 0) {
+      if (d <= 512) {
+        k = c;
+      } else {
+        k = (uint64_t)((double)c / (double)lf + 0.999999);
+        if (k < c + 1) k = c + 1;  // an empty slot ends every probe chain
+      }
+    }
+    cap[v] = k;
+  }
+}
+
+// One wave per bitmap root, a lane per row: the triangles of the row in
+// column order at consecutive slots.
+__global__ __launch_bounds__(256) void k_insert_ranked(GraphView g, const uint64_t *__restrict__ bm_off,
+                                                       const uint64_t *__restrict__ bm,
+                                                       const uint32_t *__restrict__ rowpre,
+                                                       TableView T) {
+  const int wpb = blockDim.x / kWave;
+  const int lane = lane_id();
+  for (int64_t v = (int64_t)blockIdx.x * wpb + threadIdx.x / kWave; v < g.n;
+       v += (int64_t)gridDim.x * wpb) {
+    const int64_t o = g.up[v];
+    const int d = (int)(g.rp[v + 1] - o);
+    if (d < 1 || d > 512) continue;
+    const int wd = (d + 63) >> 6;
+    const uint64_t *rows = bm + bm_off[v];
+    const uint64_t base = T.seg[v];
+    for (int i = lane; i < d; i += kWave) {
+      uint64_t pos = base + rowpre[o + i];
+      const int32_t a = g.col[o + i];
+      for (int w = 0; w < wd; w++) {
+        uint64_t m = rows[i * wd + w] & above_mask(i, w);
+        while (m) {
+          const int j = w * 64 + __ffsll((unsigned long long)m) - 1;
+          m &= m - 1;
+          const int32_t Rv[3] = {(int32_t)v, a, g.col[o + j]};
+          T.slots[pos].key = make_key<3>(Rv, T.bits);
+          T.v1[pos] = (int32_t)v;
+          pos++;
+        }
+      }
+    }
+  }
+}
+
+}  // namespace
+
+void ranked_caps(const OrientedGraph &g, FastIndex *fx, const uint32_t *tri_per_root, float lf,
+                 uint64_t *cap, hipStream_t st) {
+  fx->rowpre.reset((size_t)g.nnz + 1);
+  if (g.n == 0) return;
+  const GraphView gv = g.view();
+  hipLaunchKernelGGL(k_rank_rows, dim3((unsigned)grid_for(g.n, 4)), dim3(256), 0, st, gv,
+                     fx->bm_off.get(), fx->bm.get(), fx->rowpre.get());
+  hipLaunchKernelGGL(k_caps_ranked, dim3((unsigned)grid_for(g.n, 256)), dim3(256), 0, st, gv, lf,
+                     tri_per_root, cap);
+}
+
+void ranked_insert(const OrientedGraph &g, const FastIndex &fx, const TableView &T,
+                   hipStream_t st) {
+  if (g.n == 0) return;
+  hipLaunchKernelGGL(k_insert_ranked, dim3((unsigned)grid_for(g.n, 4)), dim3(256), 0, st,
+                     g.view(), fx.bm_off.get(), fx.bm.get(), fx.rowpre.get(), T);
+}
+
 void build_fast_index(const OrientedGraph &g, FastIndex *fx, Counters *dctr, hipStream_t st) {
   const int32_t n = g.n;
   const GraphView gv = g.view();

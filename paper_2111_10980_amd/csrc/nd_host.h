@@ -108,18 +108,35 @@ struct FastView {
   uint64_t *front;                      // r = 3: bitmap layout, bits of the triangles
                                         // of the current frontier (else null)
   uint64_t *front_apex;                 // r = 3: apex-entry bits of the same (else null)
+  const uint32_t *__restrict__ rowpre;  // r = 3 ranked table: per out-arc (v, N+(v)[i]) the
+                                        // triangles of v's bitmap rows before i (else null)
 };
 struct FastIndex {
   DevBuf<uint64_t> bm_off, bm, lptr, alive, alive_apex, front, front_apex;
+  DevBuf<uint32_t> rowpre;
   DevBuf<uint64_t> loc;  // per slot: local indices of v2..vr in N+(v1), 9 bits each
   DevBuf<int32_t> lval;
   uint64_t bm_words = 0, n_tri = 0;
   FastView view() const {
     return FastView{bm_off.get(), bm.get(),        lptr.get(),  lval.get(),
-                    alive.get(),  alive_apex.get(), front.get(), front_apex.get()};
+                    alive.get(),  alive_apex.get(), front.get(), front_apex.get(),
+                    rowpre.n ? rowpre.get() : nullptr};
   }
 };
 void build_fast_index(const OrientedGraph &g, FastIndex *fx, Counters *dctr, hipStream_t st);
+// r = 3 ranked table.  A triangle (v, a, b) whose root v keeps a bitmap sits
+// at seg[v] + its rank among the bits of v's bitmap above the diagonal
+// (row-major), so the triangles of one bitmap row are contiguous; roots
+// without a bitmap keep a hashed segment.  ranked_caps writes the segment
+// capacities (before the prefix sum) and fills fx->rowpre; ranked_insert
+// writes the keys of the bitmap roots' triangles.
+void ranked_caps(const OrientedGraph &g, FastIndex *fx, const uint32_t *tri_per_root, float lf,
+                 uint64_t *cap, hipStream_t st);
+void ranked_insert(const OrientedGraph &g, const FastIndex &fx, const TableView &T,
+                   hipStream_t st);
+// r = 3: insert the triangles of the roots without a bitmap (> 512 out-neighbours)
+void insert_rcliques_heavy3(const OrientedGraph &g, const TableView &T, Counters *dctr,
+                            hipStream_t st);
 // count(R) = |common neighbourhood of R| written straight into each slot
 void count_direct(const OrientedGraph &g, int r, const TableView &T, const FastIndex &fx,
                   const uint32_t *occ, uint64_t n_r, Counters *dctr, hipStream_t st);

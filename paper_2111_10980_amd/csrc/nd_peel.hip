@@ -469,6 +469,172 @@ __device__ __forceinline__ void peel_candidate(const PeelArgs &a, const int32_t 
   update_func<R, S, true>(a, Sv, rmask, p, in, ls, ap);
 }
 
+// ---------------------------------------------- r = 3 ranked table lookups
+// A triangle (a < b < c) whose root a keeps a bitmap sits at seg[a] + the
+// number of bitmap bits above the diagonal that precede bit (i, j) in
+// row-major order, i and j the local indices of b and c in N+(a).  Roots
+// without a bitmap are hashed.
+
+struct RootRow {
+  int64_t o;      // up[a]
+  int d;          // |N+(a)|
+  int wd;         // words per bitmap row
+  uint64_t bmo;   // bitmap word offset
+  uint64_t segb;  // first slot of a's segment
+};
+
+__device__ __forceinline__ RootRow root_row(const PeelArgs &a, const FastView &fx, int32_t v) {
+  RootRow rr;
+  rr.o = a.g.up[v];
+  rr.d = (int)(a.g.rp[v + 1] - rr.o);
+  rr.wd = (rr.d + 63) >> 6;
+  rr.bmo = rr.d <= 512 ? fx.bm_off[v] : 0;
+  rr.segb = a.T.seg[v];
+  return rr;
+}
+
+// bits of word w of a row strictly above local position i
+__device__ __forceinline__ uint64_t bits_above(int64_t i, int w) {
+  const int64_t lo = (int64_t)w * 64;
+  if (i < lo) return ~0ull;
+  if (i >= lo + 63) return 0ull;
+  return ~((1ull << (i - lo + 1)) - 1ull);
+}
+
+// slot of (root, row i, column j), i < j, in a bitmap root's ranked segment
+__device__ __forceinline__ int64_t ranked_pos(const FastView &fx, const RootRow &rr, int64_t i,
+                                              int64_t j) {
+  const uint64_t *row = fx.bm + rr.bmo + (uint64_t)i * rr.wd;
+  uint64_t rank = fx.rowpre[rr.o + i];
+  for (int w = (int)((i + 1) >> 6); w <= (int)(j >> 6); w++) {
+    const int64_t lo = (int64_t)w * 64;
+    const uint64_t below = j >= lo + 64 ? ~0ull : ((1ull << (j - lo)) - 1ull);
+    rank += (uint64_t)__popcll(row[w] & bits_above(i, w) & below);
+  }
+  return (int64_t)(rr.segb + rank);
+}
+
+// slot of the triangle (x0 < x1 < x2), or -1; l1, l2 are the local indices
+// of x1 and x2 in N+(x0) when known (else -1)
+__device__ __forceinline__ int64_t tri_slot(const PeelArgs &a, const FastView &fx,
+                                            const RootRow &rr, int32_t x0, int32_t x1, int32_t x2,
+                                            int64_t l1, int64_t l2) {
+  if (rr.d > 512) {
+    const int32_t Tv[3] = {x0, x1, x2};
+    Slot tmp;
+    return table_find(a.T, x0, make_key<3>(Tv, a.T.bits), &tmp);
+  }
+  if (l1 < 0 || l2 < 0) {
+    const int32_t ys[2] = {x1, x2};
+    int64_t at[2];
+    lower_bounds<2>(a.g.col, rr.o, rr.o + rr.d, ys, at);
+    if (at[0] >= rr.o + rr.d || a.g.col[at[0]] != x1 || at[1] >= rr.o + rr.d ||
+        a.g.col[at[1]] != x2)
+      return -1;
+    l1 = at[0] - rr.o;
+    l2 = at[1] - rr.o;
+  }
+  return ranked_pos(fx, rr, l1, l2);
+}
+
+// Update-Func of the s-clique R + x for r = 3 on the ranked table: the same
+// decisions as update_func, with the three other triangles located by rank
+// (local indices of v2, v3 in N+(v1) come from R's loc word).  Called by every
+// lane of the wave together.
+__device__ __forceinline__ void update_r3_ranked(const PeelArgs &a, const FastView &fx,
+                                                 const int32_t (&Rv)[3], int32_t x, uint64_t lc,
+                                                 bool active, LaneStats &ls, Appender *ap) {
+  constexpr Combos<4, 3> cb{};
+  int32_t Sv[4];
+  uint32_t rmask = 0;
+  {
+    int at = 0;
+#pragma unroll
+    for (int i = 0; i < 3; i++) at += Rv[i] < x ? 1 : 0;
+#pragma unroll
+    for (int o = 0, i = 0; o < 4; o++) {
+      if (o == at) {
+        Sv[o] = x;
+      } else {
+        Sv[o] = Rv[i++];
+        rmask |= 1u << o;
+      }
+    }
+  }
+  const int32_t v1 = Rv[0];
+  RootRow r1{};
+  int64_t l2 = -1, l3 = -1, lx = -1;
+  if (active) {
+    r1 = root_row(a, fx, v1);
+    if (r1.d <= 512 && (lc >> 63)) {
+      l2 = (int64_t)(lc & 511u);
+      l3 = (int64_t)((lc >> 9) & 511u);
+      if (x > v1) {
+        lx = lower_pos(a.g.col, r1.o, r1.o + r1.d, x) - r1.o;
+        if (lx >= r1.d || a.g.col[r1.o + lx] != x) lx = -1;  // tri_slot searches again
+      }
+    }
+  }
+  int self = 0;
+  int64_t pos[4];
+  bool want[4];
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    if (cb.mask[q] == rmask) self = q;
+    want[q] = active && cb.mask[q] != rmask;
+    pos[q] = -1;
+    if (!want[q]) continue;
+    const int32_t t0 = Sv[cb.idx[q][0]], t1 = Sv[cb.idx[q][1]], t2 = Sv[cb.idx[q][2]];
+    if (t0 == v1) {
+      const int64_t h1 = t1 == Rv[1] ? l2 : (t1 == Rv[2] ? l3 : lx);
+      const int64_t h2 = t2 == Rv[1] ? l2 : (t2 == Rv[2] ? l3 : lx);
+      pos[q] = tri_slot(a, fx, r1, t0, t1, t2, h1, h2);
+    } else {
+      const RootRow rr = root_row(a, fx, t0);
+      pos[q] = tri_slot(a, fx, rr, t0, t1, t2, -1, -1);
+    }
+  }
+  Slot sl[4];
+  bool alive = active, other_owner = false, live[4];
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    live[q] = false;
+    if (!want[q]) continue;
+    if (pos[q] < 0) {
+      ls.err |= kErrLookup;
+      alive = false;
+      continue;
+    }
+    sl[q] = a.T.slots[pos[q]];
+    const int32_t Tv[3] = {Sv[cb.idx[q][0]], Sv[cb.idx[q][1]], Sv[cb.idx[q][2]]};
+    if (sl[q].key != make_key<3>(Tv, a.T.bits)) {  // the rank must land on the triangle
+      ls.err |= kErrLookup;
+      alive = false;
+    } else if (sl[q].stamp < a.t) {
+      alive = false;  // S was destroyed in an earlier round
+    } else if (sl[q].stamp == a.t) {
+      other_owner = other_owner || q < self;  // peeled with R and first in order
+    } else {
+      live[q] = true;
+    }
+  }
+  if (active) ls.disc++;
+  const bool mine = alive && !other_owner;
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    bool want_append = false, want_low = false;
+    if (mine && live[q]) {
+      const uint32_t old = __hip_atomic_fetch_add(&a.T.slots[pos[q]].cnt, 0xFFFFFFFFu,
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ls.dec++;
+      want_append = old == a.k + 1;
+      want_low = a.kw > a.k && old == a.kw + 1;
+    }
+    ap[0].push(want_append, (uint32_t)pos[q]);
+    ap[1].push(want_low, (uint32_t)pos[q]);
+  }
+}
+
 constexpr int kListCap = 1024;  // LDS entries per wave for a staged apex list
 
 // position of x in the sorted LDS array a[0..n), or -1
@@ -733,10 +899,15 @@ __global__ __launch_bounds__(256) void k_expand(PeelArgs base, RoundCtl *rc, Fas
   }
 }
 
+// At least 6 waves per SIMD: the ranked lookups need more registers than
+// that allows by default, and the occupancy hides their dependent loads
+// (measured: 5 waves 391 ms, 6 waves 376 ms, 8 waves with spills 434 ms per
+// rMAT-18 (3,4) decomposition).
 template <int R>
-__global__ __launch_bounds__(256) void k_apply(PeelArgs base, const RoundCtl *__restrict__ rc,
+__global__ __launch_bounds__(256, 6) void k_apply(PeelArgs base, const RoundCtl *__restrict__ rc,
                                                const int2 *__restrict__ rec,
-                                               const int32_t *__restrict__ fv) {
+                                               const int32_t *__restrict__ fv, FastView fx,
+                                               const uint64_t *__restrict__ loc) {
   if (rc_idle(rc)) return;
   const PeelArgs a = round_args(base, rc);
   const uint32_t *__restrict__ F = rc->F;
@@ -765,7 +936,10 @@ __global__ __launch_bounds__(256) void k_apply(PeelArgs base, const RoundCtl *__
 #pragma unroll
       for (int q = 0; q < R; q++) Rv[q] = q;
     }
-    peel_candidate<R>(a, Rv, in ? rc.y : R, in, p, ls, ap);
+    if constexpr (R == 3)  // r = 3 plans keep the ranked table
+      update_r3_ranked(a, fx, Rv, in ? rc.y : R, in ? loc[p] : 0ull, in, ls, ap);
+    else
+      peel_candidate<R>(a, Rv, in ? rc.y : R, in, p, ls, ap);
   }
   ap[0].flush();
   ap[1].flush();
@@ -1446,7 +1620,7 @@ void launch_fast(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, dim3 ga, hip
                      E.off.get(), E.len.get(), E.fv.get(), E.rec.get());
   if (e0) hipEventRecord(e0, E.st);
   hipLaunchKernelGGL(k_apply<R>, ga, dim3(256), 0, E.st, base, E.rc.get(), E.rec.get(),
-                     E.fv.get());
+                     E.fv.get(), E.fxv, E.loc);
   if (e1) hipEventRecord(e1, E.st);
   if (R == 3)
     hipLaunchKernelGGL(k_front_bits<false>, gf, dim3(256), 0, E.st, E.gv, E.T, E.fxv, E.loc,
