@@ -702,12 +702,28 @@ __device__ __forceinline__ bool front_positions(const PeelArgs &a, uint64_t lc,
   return found;
 }
 
+// What the expand pass needs of a peeled r-clique, written by the bound pass
+// so that expand starts from one load instead of re-deriving it.
+struct ExpandDesc {
+  uint64_t o;      // up[v1]: N+(v1) = col[o, o + d)
+  uint64_t bmo;    // word offset of v1's bitmap (d <= 512)
+  uint64_t lb;     // first entry of the driving apex list
+  uint64_t ob;     // r = 3: first entry of the other apex list
+  uint32_t d;      // |N+(v1)|
+  uint32_t len2;   // driving list length
+  uint32_t olen;   // r = 3: other list length
+  uint32_t drv;    // 1..r-1: the member whose arc (v1, v_drv) drives
+  uint32_t l[5];   // local indices of v2..vr in N+(v1)
+  uint32_t pad;
+};
+
 // Also stamps A_t with t (the apply pass of the same round reads the stamps)
 // and allocates each r-clique's record range with one atomic per block.
 template <int R>
 __global__ __launch_bounds__(256) void k_expand_bound(PeelArgs base, RoundCtl *rc, FastView fx,
                                                       const uint64_t *__restrict__ loc,
-                                                      uint64_t *off, uint32_t *len, int32_t *fv) {
+                                                      uint64_t *off, uint32_t *len, int32_t *fv,
+                                                      ExpandDesc *desc) {
   if (rc_idle(rc)) return;
   const PeelArgs a = round_args(base, rc);
   const uint32_t *__restrict__ F = rc->F;
@@ -744,13 +760,35 @@ __global__ __launch_bounds__(256) void k_expand_bound(PeelArgs base, RoundCtl *r
         } else {
           total1 = (uint64_t)d;
         }
+        int drv = 1;
         uint64_t len2 = fx.lptr[e[1] + 1] - fx.lptr[e[1]];
 #pragma unroll
         for (int i = 2; i < R; i++) {
           const uint64_t len = fx.lptr[e[i] + 1] - fx.lptr[e[i]];
-          len2 = len < len2 ? len : len2;
+          if (len < len2) {
+            len2 = len;
+            drv = i;
+          }
         }
         bound = total1 + len2;
+        ExpandDesc ds;
+        ds.o = (uint64_t)o;
+        ds.bmo = d <= 512 ? fx.bm_off[Rv[0]] : 0;
+        ds.lb = fx.lptr[e[drv]];
+        ds.d = (uint32_t)d;
+        ds.len2 = (uint32_t)len2;
+        ds.drv = (uint32_t)drv;
+        ds.ob = 0;
+        ds.olen = 0;
+        if constexpr (R == 3) {
+          const int other = drv == 1 ? 2 : 1;
+          ds.ob = fx.lptr[e[other]];
+          ds.olen = (uint32_t)(fx.lptr[e[other] + 1] - ds.ob);
+        }
+#pragma unroll
+        for (int i = 0; i < 5; i++) ds.l[i] = i + 1 < R ? (uint32_t)(e[i + 1] - o) : 0u;
+        ds.pad = 0;
+        desc[f] = ds;
       } else {
         atomicOr(&a.ctr->err, kErrLookup);
       }
@@ -766,7 +804,7 @@ __global__ __launch_bounds__(256) void k_expand_bound(PeelArgs base, RoundCtl *r
 
 template <int R>
 __global__ __launch_bounds__(256) void k_expand(PeelArgs base, RoundCtl *rc, FastView fx,
-                                                const uint64_t *__restrict__ loc,
+                                                const ExpandDesc *__restrict__ desc,
                                                 const uint64_t *__restrict__ off,
                                                 const uint32_t *__restrict__ len,
                                                 const int32_t *__restrict__ fv, int2 *rec) {
@@ -789,27 +827,24 @@ __global__ __launch_bounds__(256) void k_expand(PeelArgs base, RoundCtl *rc, Fas
     const uint64_t b = off[f];
     const uint64_t total = len[f];
     if (total == 0) continue;
-    const uint32_t p = F[f];
-    int32_t Rv[R];
-#pragma unroll
-    for (int i = 0; i < R; i++) Rv[i] = fv[f * R + i];
-    const int32_t v1 = Rv[0];
-    const int64_t o = a.g.up[v1];
-    const int d = (int)(a.g.rp[v1 + 1] - o);
+    const ExpandDesc ds = desc[f];
+    const int64_t o = (int64_t)ds.o;
+    const int d = (int)ds.d;
     int64_t e[R];
-    front_positions<R>(a, loc[p], Rv, o, d, e);  // found: the bound pass checked it
+#pragma unroll
+    for (int i = 1; i < R; i++) e[i] = o + (int64_t)ds.l[i - 1];
     const bool has_bm = d <= 512;
     uint32_t total1, iw[8];
     uint64_t cw = 0;
     if (has_bm) {
       const int wd = (d + 63) >> 6;
-      const uint64_t *rows = (R == 3 ? fx.alive : fx.bm) + fx.bm_off[v1];
+      const uint64_t *rows = (R == 3 ? fx.alive : fx.bm) + ds.bmo;
       if (lane < wd) {
         cw = ~0ull;
 #pragma unroll
         for (int i = 1; i < R; i++) cw &= rows[(e[i] - o) * wd + lane];
         if constexpr (R == 3)
-          cw &= ~owned_elsewhere(fx.front + fx.bm_off[v1], e[1] - o, e[2] - o, wd, lane);
+          cw &= ~owned_elsewhere(fx.front + ds.bmo, e[1] - o, e[2] - o, wd, lane);
       }
       const uint32_t incl = wave_incl_scan((uint32_t)__popcll(cw));
       total1 = __shfl(incl, kWave - 1);
@@ -820,23 +855,14 @@ __global__ __launch_bounds__(256) void k_expand(PeelArgs base, RoundCtl *rc, Fas
 #pragma unroll
       for (int q = 0; q < 8; q++) iw[q] = 0;
     }
-    int drv = 1;
-    uint64_t len2 = fx.lptr[e[1] + 1] - fx.lptr[e[1]];
-#pragma unroll
-    for (int i = 2; i < R; i++) {
-      const uint64_t len = fx.lptr[e[i] + 1] - fx.lptr[e[i]];
-      if (len < len2) {
-        len2 = len;
-        drv = i;
-      }
-    }
-    const uint64_t lb = fx.lptr[e[drv]];
+    const int drv = (int)ds.drv;
+    const uint64_t len2 = ds.len2;
+    const uint64_t lb = ds.lb;
     int staged_len = -1;
     uint64_t ob = 0, oe = 0;
     if constexpr (R == 3) {
-      const int other = drv == 1 ? 2 : 1;
-      ob = fx.lptr[e[other]];
-      oe = fx.lptr[e[other] + 1];
+      ob = ds.ob;
+      oe = ds.ob + ds.olen;
       if (len2 > 0 && oe - ob <= (uint64_t)kListCap) {
         staged_len = (int)(oe - ob);
         for (int i = lane; i < staged_len; i += kWave) lbuf[wv][i] = fx.lval[ob + i];
@@ -867,7 +893,7 @@ __global__ __launch_bounds__(256) void k_expand(PeelArgs base, RoundCtl *rc, Fas
         } else {
           x = a.g.col[o + (int64_t)k];
 #pragma unroll
-          for (int i = 1; i < R; i++) in = in && adjacent(a.g, x, Rv[i]);
+          for (int i = 1; i < R; i++) in = in && adjacent(a.g, x, fv[f * R + i]);
         }
       } else if (in) {
         const uint64_t q1 = lb + (k - total1);
@@ -1588,6 +1614,7 @@ struct Engine {
   DevBuf<uint32_t> len;    // per frontier entry: records / flags
   DevBuf<int32_t> fv;      // per frontier entry: its r vertices
   DevBuf<int32_t> drv;     // per frontier entry: driver (s >= r+2)
+  DevBuf<ExpandDesc> desc; // per frontier entry: expand descriptor (s = r+1)
   DevBuf<int2> rec;        // candidate records (s = r+1) or member records (s >= r+2)
   DevBuf<uint8_t> flag;    // s >= r+2: membership flags
   DevBuf<uint32_t> owner;  // s >= r+2: frontier index of each candidate
@@ -1615,8 +1642,8 @@ void launch_fast(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, dim3 ga, hip
     hipLaunchKernelGGL(k_front_bits<true>, gf, dim3(256), 0, E.st, E.gv, E.T, E.fxv, E.loc,
                        E.rc.get());
   hipLaunchKernelGGL(k_expand_bound<R>, gf, dim3(256), 0, E.st, base, E.rc.get(), E.fxv, E.loc,
-                     E.off.get(), E.len.get(), E.fv.get());
-  hipLaunchKernelGGL(k_expand<R>, gw, dim3(256), 0, E.st, base, E.rc.get(), E.fxv, E.loc,
+                     E.off.get(), E.len.get(), E.fv.get(), E.desc.get());
+  hipLaunchKernelGGL(k_expand<R>, gw, dim3(256), 0, E.st, base, E.rc.get(), E.fxv, E.desc.get(),
                      E.off.get(), E.len.get(), E.fv.get(), E.rec.get());
   if (e0) hipEventRecord(e0, E.st);
   hipLaunchKernelGGL(k_apply<R>, ga, dim3(256), 0, E.st, base, E.rc.get(), E.rec.get(),
@@ -1774,6 +1801,7 @@ uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableVie
   E.len.reset(n_r);
   E.fv.reset(n_r * (uint64_t)r);
   if (path == 2) E.drv.reset(n_r);
+  if (path == 1) E.desc.reset(n_r);
   // initial capacities; ND_PEEL_CAP / ND_PEEL_TRACE_CAP override them (small
   // values exercise the grow-and-rerun path)
   uint64_t cap0 = n_r > (1u << 20) ? n_r : (1u << 20);
