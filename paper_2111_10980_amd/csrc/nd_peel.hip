@@ -524,7 +524,7 @@ __device__ __forceinline__ int64_t tri_slot(const PeelArgs &a, const FastView &f
     Slot tmp;
     return table_find(a.T, x0, make_key<3>(Tv, a.T.bits), &tmp);
   }
-  if (l1 < 0 || l2 < 0) {
+  if (l1 < 0 && l2 < 0) {
     const int32_t ys[2] = {x1, x2};
     int64_t at[2];
     lower_bounds<2>(a.g.col, rr.o, rr.o + rr.d, ys, at);
@@ -533,6 +533,11 @@ __device__ __forceinline__ int64_t tri_slot(const PeelArgs &a, const FastView &f
       return -1;
     l1 = at[0] - rr.o;
     l2 = at[1] - rr.o;
+  } else if (l1 < 0 || l2 < 0) {  // one of them known
+    const int32_t y = l1 < 0 ? x1 : x2;
+    const int64_t at = lower_pos(a.g.col, rr.o, rr.o + rr.d, y);
+    if (at >= rr.o + rr.d || a.g.col[at] != y) return -1;
+    (l1 < 0 ? l1 : l2) = at - rr.o;
   }
   return ranked_pos(fx, rr, l1, l2);
 }
@@ -541,9 +546,12 @@ __device__ __forceinline__ int64_t tri_slot(const PeelArgs &a, const FastView &f
 // decisions as update_func, with the three other triangles located by rank
 // (local indices of v2, v3 in N+(v1) come from R's loc word).  Called by every
 // lane of the wave together.
+// lxh: local index of x in N+(v1) when the expand pass had it (else 0xFFFF);
+// l23: local index of v3 in N+(v2) (else 0xFFFFFFFF).
 __device__ __forceinline__ void update_r3_ranked(const PeelArgs &a, const FastView &fx,
                                                  const int32_t (&Rv)[3], int32_t x, uint64_t lc,
-                                                 bool active, LaneStats &ls, Appender *ap) {
+                                                 uint32_t lxh, uint32_t l23, bool active,
+                                                 LaneStats &ls, Appender *ap) {
   constexpr Combos<4, 3> cb{};
   int32_t Sv[4];
   uint32_t rmask = 0;
@@ -570,8 +578,12 @@ __device__ __forceinline__ void update_r3_ranked(const PeelArgs &a, const FastVi
       l2 = (int64_t)(lc & 511u);
       l3 = (int64_t)((lc >> 9) & 511u);
       if (x > v1) {
-        lx = lower_pos(a.g.col, r1.o, r1.o + r1.d, x) - r1.o;
-        if (lx >= r1.d || a.g.col[r1.o + lx] != x) lx = -1;  // tri_slot searches again
+        if (lxh != 0xFFFFu) {
+          lx = (int64_t)lxh;
+        } else {
+          lx = lower_pos(a.g.col, r1.o, r1.o + r1.d, x) - r1.o;
+          if (lx >= r1.d || a.g.col[r1.o + lx] != x) lx = -1;  // tri_slot searches again
+        }
       }
     }
   }
@@ -591,7 +603,10 @@ __device__ __forceinline__ void update_r3_ranked(const PeelArgs &a, const FastVi
       pos[q] = tri_slot(a, fx, r1, t0, t1, t2, h1, h2);
     } else {
       const RootRow rr = root_row(a, fx, t0);
-      pos[q] = tri_slot(a, fx, rr, t0, t1, t2, -1, -1);
+      // (v2, v3, x) rooted at v2: v3's local index in N+(v2) is known
+      const int64_t h1 = (t0 == Rv[1] && t1 == Rv[2] && l23 != 0xFFFFFFFFu) ? (int64_t)l23 : -1;
+      const int64_t h2 = (t0 == Rv[1] && t2 == Rv[2] && l23 != 0xFFFFFFFFu) ? (int64_t)l23 : -1;
+      pos[q] = tri_slot(a, fx, rr, t0, t1, t2, h1, h2);
     }
   }
   Slot sl[4];
@@ -723,7 +738,7 @@ template <int R>
 __global__ __launch_bounds__(256) void k_expand_bound(PeelArgs base, RoundCtl *rc, FastView fx,
                                                       const uint64_t *__restrict__ loc,
                                                       uint64_t *off, uint32_t *len, int32_t *fv,
-                                                      ExpandDesc *desc) {
+                                                      ExpandDesc *desc, uint32_t *f23) {
   if (rc_idle(rc)) return;
   const PeelArgs a = round_args(base, rc);
   const uint32_t *__restrict__ F = rc->F;
@@ -789,6 +804,16 @@ __global__ __launch_bounds__(256) void k_expand_bound(PeelArgs base, RoundCtl *r
         for (int i = 0; i < 5; i++) ds.l[i] = i + 1 < R ? (uint32_t)(e[i + 1] - o) : 0u;
         ds.pad = 0;
         desc[f] = ds;
+        if constexpr (R == 3) {  // v3's place in N+(v2), for the triangles (v2, v3, x)
+          const int64_t o2 = a.g.up[Rv[1]];
+          const int64_t d2 = a.g.rp[Rv[1] + 1] - o2;
+          uint32_t l = 0xFFFFFFFFu;
+          if (d2 <= 512) {
+            const int64_t at = lower_pos(a.g.col, o2, o2 + d2, Rv[2]);
+            if (at < o2 + d2 && a.g.col[at] == Rv[2]) l = (uint32_t)(at - o2);
+          }
+          f23[f] = l;
+        }
       } else {
         atomicOr(&a.ctr->err, kErrLookup);
       }
@@ -807,7 +832,8 @@ __global__ __launch_bounds__(256) void k_expand(PeelArgs base, RoundCtl *rc, Fas
                                                 const ExpandDesc *__restrict__ desc,
                                                 const uint64_t *__restrict__ off,
                                                 const uint32_t *__restrict__ len,
-                                                const int32_t *__restrict__ fv, int2 *rec) {
+                                                const int32_t *__restrict__ fv, int2 *rec,
+                                                uint16_t *rloc) {
   if (rc_idle(rc)) return;
   if (rc->total > rc->cap) {  // records do not fit: the host grows the buffer, reruns the round
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -885,11 +911,13 @@ __global__ __launch_bounds__(256) void k_expand(PeelArgs base, RoundCtl *rc, Fas
         }
       }
       const uint64_t wordw = __shfl(cw, w);
+      uint32_t lxw = 0xFFFFu;  // local index of x in N+(v1), bitmap part only
       if (in && k < total1) {
         if (has_bm) {
           uint64_t m = wordw;
           for (uint32_t q = 0; q < kk - before; q++) m &= m - 1;
-          x = a.g.col[o + w * 64 + (__ffsll((unsigned long long)m) - 1)];
+          lxw = (uint32_t)(w * 64 + (__ffsll((unsigned long long)m) - 1));
+          x = a.g.col[o + lxw];
         } else {
           x = a.g.col[o + (int64_t)k];
 #pragma unroll
@@ -919,7 +947,10 @@ __global__ __launch_bounds__(256) void k_expand(PeelArgs base, RoundCtl *rc, Fas
               in = in && sorted_contains(fx.lval, fx.lptr[e[i]], fx.lptr[e[i] + 1], x);
         }
       }
-      if (k < total) rec[b + k] = make_int2((int)f, in ? x : -1);
+      if (k < total) {
+        rec[b + k] = make_int2((int)f, in ? x : -1);
+        if constexpr (R == 3) rloc[b + k] = (uint16_t)lxw;
+      }
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -933,7 +964,9 @@ template <int R>
 __global__ __launch_bounds__(256, 6) void k_apply(PeelArgs base, const RoundCtl *__restrict__ rc,
                                                const int2 *__restrict__ rec,
                                                const int32_t *__restrict__ fv, FastView fx,
-                                               const uint64_t *__restrict__ loc) {
+                                               const uint64_t *__restrict__ loc,
+                                               const uint16_t *__restrict__ rloc,
+                                               const uint32_t *__restrict__ f23) {
   if (rc_idle(rc)) return;
   const PeelArgs a = round_args(base, rc);
   const uint32_t *__restrict__ F = rc->F;
@@ -963,7 +996,8 @@ __global__ __launch_bounds__(256, 6) void k_apply(PeelArgs base, const RoundCtl 
       for (int q = 0; q < R; q++) Rv[q] = q;
     }
     if constexpr (R == 3)  // r = 3 plans keep the ranked table
-      update_r3_ranked(a, fx, Rv, in ? rc.y : R, in ? loc[p] : 0ull, in, ls, ap);
+      update_r3_ranked(a, fx, Rv, in ? rc.y : R, in ? loc[p] : 0ull, in ? rloc[i] : 0xFFFFu,
+                       in ? f23[rc.x] : 0xFFFFFFFFu, in, ls, ap);
     else
       peel_candidate<R>(a, Rv, in ? rc.y : R, in, p, ls, ap);
   }
@@ -1615,6 +1649,8 @@ struct Engine {
   DevBuf<int32_t> fv;      // per frontier entry: its r vertices
   DevBuf<int32_t> drv;     // per frontier entry: driver (s >= r+2)
   DevBuf<ExpandDesc> desc; // per frontier entry: expand descriptor (s = r+1)
+  DevBuf<uint32_t> f23;    // r = 3: per frontier entry, v3's local index in N+(v2)
+  DevBuf<uint16_t> rloc;   // r = 3: per record, x's local index in N+(v1) (or 0xFFFF)
   DevBuf<int2> rec;        // candidate records (s = r+1) or member records (s >= r+2)
   DevBuf<uint8_t> flag;    // s >= r+2: membership flags
   DevBuf<uint32_t> owner;  // s >= r+2: frontier index of each candidate
@@ -1642,12 +1678,12 @@ void launch_fast(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, dim3 ga, hip
     hipLaunchKernelGGL(k_front_bits<true>, gf, dim3(256), 0, E.st, E.gv, E.T, E.fxv, E.loc,
                        E.rc.get());
   hipLaunchKernelGGL(k_expand_bound<R>, gf, dim3(256), 0, E.st, base, E.rc.get(), E.fxv, E.loc,
-                     E.off.get(), E.len.get(), E.fv.get(), E.desc.get());
+                     E.off.get(), E.len.get(), E.fv.get(), E.desc.get(), E.f23.get());
   hipLaunchKernelGGL(k_expand<R>, gw, dim3(256), 0, E.st, base, E.rc.get(), E.fxv, E.desc.get(),
-                     E.off.get(), E.len.get(), E.fv.get(), E.rec.get());
+                     E.off.get(), E.len.get(), E.fv.get(), E.rec.get(), E.rloc.get());
   if (e0) hipEventRecord(e0, E.st);
   hipLaunchKernelGGL(k_apply<R>, ga, dim3(256), 0, E.st, base, E.rc.get(), E.rec.get(),
-                     E.fv.get(), E.fxv, E.loc);
+                     E.fv.get(), E.fxv, E.loc, E.rloc.get(), E.f23.get());
   if (e1) hipEventRecord(e1, E.st);
   if (R == 3)
     hipLaunchKernelGGL(k_front_bits<false>, gf, dim3(256), 0, E.st, E.gv, E.T, E.fxv, E.loc,
@@ -1746,6 +1782,7 @@ void set_field(RoundCtl *rc, size_t offset, T value, hipStream_t st) {
 
 void alloc_records(Engine &E, uint64_t cap) {
   E.rec.reset(cap);
+  E.rloc.reset(E.path == 1 && E.r == 3 ? cap : 1);
   if (E.path == 2) {
     E.flag.reset(cap);
     E.owner.reset(cap);
@@ -1801,7 +1838,10 @@ uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableVie
   E.len.reset(n_r);
   E.fv.reset(n_r * (uint64_t)r);
   if (path == 2) E.drv.reset(n_r);
-  if (path == 1) E.desc.reset(n_r);
+  if (path == 1) {
+    E.desc.reset(n_r);
+    E.f23.reset(r == 3 ? n_r : 1);
+  }
   // initial capacities; ND_PEEL_CAP / ND_PEEL_TRACE_CAP override them (small
   // values exercise the grow-and-rerun path)
   uint64_t cap0 = n_r > (1u << 20) ? n_r : (1u << 20);
@@ -1873,6 +1913,7 @@ uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableVie
       uint64_t want = m.need + m.need / 4;
       if (want < 2 * E.cap) want = 2 * E.cap;
       E.rec.release();
+      E.rloc.release();
       E.flag.release();
       E.owner.release();
       E.mbeg.release();
