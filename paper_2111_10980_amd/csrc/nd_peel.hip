@@ -956,25 +956,21 @@ __global__ __launch_bounds__(256) void k_expand(PeelArgs base, RoundCtl *rc, Fas
   }
 }
 
-// At least 6 waves per SIMD: the ranked lookups need more registers than
-// that allows by default, and the occupancy hides their dependent loads
-// (measured: 5 waves 391 ms, 6 waves 376 ms, 8 waves with spills 434 ms per
-// rMAT-18 (3,4) decomposition).
 template <int R>
-__global__ __launch_bounds__(256, 6) void k_apply(PeelArgs base, const RoundCtl *__restrict__ rc,
+__device__ __forceinline__ void apply_body(const PeelArgs &base, const RoundCtl *__restrict__ rc,
                                                const int2 *__restrict__ rec,
                                                const int32_t *__restrict__ fv, FastView fx,
                                                const uint64_t *__restrict__ loc,
                                                const uint16_t *__restrict__ rloc,
-                                               const uint32_t *__restrict__ f23) {
-  if (rc_idle(rc)) return;
+                                               const uint32_t *__restrict__ f23,
+                                               uint32_t (*abuf_mem)[2][kAppendCap]) {
   const PeelArgs a = round_args(base, rc);
   const uint32_t *__restrict__ F = rc->F;
   const uint64_t total = rc->total;
   const int wv = threadIdx.x / kWave;
   const int lane = lane_id();
   LaneStats ls;
-  __shared__ uint32_t abuf[256 / kWave][2][kAppendCap];
+  uint32_t(*abuf)[2][kAppendCap] = abuf_mem;
   Appender ap[2] = {{abuf[wv][0], 0u, a.Fnext, &a.ctr->next_size},
                     {abuf[wv][1], 0u, a.Low, &a.ctr->low_size}};
   // wave-uniform trip count: every lane reaches every append
@@ -1006,6 +1002,34 @@ __global__ __launch_bounds__(256, 6) void k_apply(PeelArgs base, const RoundCtl 
   stat_add(a.stats, kStatDec, ls.dec);
   stat_add(a.stats, kStatDisc, ls.disc);
   if (ls.err) atomicOr(&a.ctr->err, ls.err);
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_apply(PeelArgs base, const RoundCtl *__restrict__ rc,
+                                               const int2 *__restrict__ rec,
+                                               const int32_t *__restrict__ fv, FastView fx,
+                                               const uint64_t *__restrict__ loc,
+                                               const uint16_t *__restrict__ rloc,
+                                               const uint32_t *__restrict__ f23) {
+  if (rc_idle(rc)) return;
+  __shared__ uint32_t abuf[256 / kWave][2][kAppendCap];
+  apply_body<R>(base, rc, rec, fv, fx, loc, rloc, f23, abuf);
+}
+
+// r = 3: at least 6 waves per SIMD.  The ranked lookups need more registers
+// than that allows by default, and the occupancy hides their dependent loads
+// (measured: 5 waves 391 ms, 6 waves 376 ms, 8 waves with spills 434 ms per
+// rMAT-18 (3,4) decomposition).  Other r keep the default (their larger
+// subset arrays would spill).
+__global__ __launch_bounds__(256, 6) void k_apply3(PeelArgs base, const RoundCtl *__restrict__ rc,
+                                                   const int2 *__restrict__ rec,
+                                                   const int32_t *__restrict__ fv, FastView fx,
+                                                   const uint64_t *__restrict__ loc,
+                                                   const uint16_t *__restrict__ rloc,
+                                                   const uint32_t *__restrict__ f23) {
+  if (rc_idle(rc)) return;
+  __shared__ uint32_t abuf[256 / kWave][2][kAppendCap];
+  apply_body<3>(base, rc, rec, fv, fx, loc, rloc, f23, abuf);
 }
 
 // Direct count, one wave per r-clique (r >= 3): the part x > v1 is a
@@ -1682,8 +1706,12 @@ void launch_fast(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, dim3 ga, hip
   hipLaunchKernelGGL(k_expand<R>, gw, dim3(256), 0, E.st, base, E.rc.get(), E.fxv, E.desc.get(),
                      E.off.get(), E.len.get(), E.fv.get(), E.rec.get(), E.rloc.get());
   if (e0) hipEventRecord(e0, E.st);
-  hipLaunchKernelGGL(k_apply<R>, ga, dim3(256), 0, E.st, base, E.rc.get(), E.rec.get(),
-                     E.fv.get(), E.fxv, E.loc, E.rloc.get(), E.f23.get());
+  if constexpr (R == 3)
+    hipLaunchKernelGGL(k_apply3, ga, dim3(256), 0, E.st, base, E.rc.get(), E.rec.get(),
+                       E.fv.get(), E.fxv, E.loc, E.rloc.get(), E.f23.get());
+  else
+    hipLaunchKernelGGL(k_apply<R>, ga, dim3(256), 0, E.st, base, E.rc.get(), E.rec.get(),
+                       E.fv.get(), E.fxv, E.loc, E.rloc.get(), E.f23.get());
   if (e1) hipEventRecord(e1, E.st);
   if (R == 3)
     hipLaunchKernelGGL(k_front_bits<false>, gf, dim3(256), 0, E.st, E.gv, E.T, E.fxv, E.loc,
