@@ -8,6 +8,10 @@
 //                        vertex v occupies slots [seg[v], seg[v+1]);
 //                        slots[] 16-byte {key, cnt, stamp}; v1[] int32 per
 //                        slot.  The slot position is the r-clique's index.
+//                        Segments are hashed (open addressing), except for
+//                        r = 3 plans of the s = r+1 path, where a root with
+//                        an adjacency bitmap keeps its triangles in the rank
+//                        order of the bitmap's bits (exactly full).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -326,12 +330,9 @@ struct Counters {
   uint64_t decrements;
   uint64_t discoveries;
   uint32_t err;          // kErr* bits
-  uint32_t next_size;    // size of the next frontier
-  uint32_t live_min;     // minimum live count (k-advance)
-  uint32_t live_size;    // size of the compacted live list
+  uint32_t next_size;    // appends to the next frontier in this round
   uint32_t class_size[8];
-  uint32_t low_size;     // size of the level-window list
-  uint32_t high_size;    // size of the list above the window
+  uint32_t low_size;     // size of the level-window list (appends continue after it)
 };
 
 
