@@ -301,3 +301,32 @@ def test_round_queue_depth(depth, monkeypatch):
     the device round state."""
     monkeypatch.setenv("ND_PEEL_DEPTH", depth)
     check_against_oracle(inputs.rmat(10, 8, 55), 2, 4)
+
+
+def _random_case(seed):
+    rng = np.random.default_rng(seed)
+    kind = int(rng.integers(0, 5))
+    sd = int(rng.integers(0, 2**31))
+    if kind == 0:
+        n = int(rng.integers(2, 120))
+        g = inputs.erdos_renyi(n, int(rng.integers(0, min(n * (n - 1) // 2, 6 * n) + 1)), sd)
+    elif kind == 1:
+        g = inputs.planted_er(int(rng.integers(20, 200)), float(rng.uniform(1, 10)),
+                              int(rng.integers(1, 5)), 4, 14, sd)
+    elif kind == 2:
+        g = inputs.rmat(int(rng.integers(4, 10)), int(rng.integers(2, 17)), sd)
+    elif kind == 3:
+        g = inputs.rmat_paper(int(rng.integers(4, 10)), int(rng.integers(2, 17)), sd)
+    else:
+        g = inputs.disjoint_union([inputs.complete_graph(int(k))
+                                   for k in rng.integers(1, 12, size=int(rng.integers(1, 6)))])
+    r = int(rng.integers(1, 6))
+    s = r + int(rng.integers(1, min(3, 7 - r) + 1))
+    return g, r, s
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_random_graphs_and_rs(seed):
+    """Seeded random graphs of every generator and random (r, s), s <= r+3."""
+    g, r, s = _random_case(9000 + seed)
+    check_against_oracle(g, r, s)
