@@ -515,6 +515,8 @@ nd_status nd_run(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *cou
     const uint32_t perr =
         peel_all(p->g, r, s, path, p->table(), p->fast ? &p->fx : nullptr, p->occ.get(), p->n_r,
                  dc, p->stats.get(), timing, st, tm.ev[2], &kround, &pr);
+    if (perr & kErrRuntime) fail(ND_EHIP, "HIP error in the peel loop: %s",
+                                 hipGetErrorString(hipGetLastError()));
     if (perr) fail(ND_EHIP, "peel failed (flags %u)", perr);
     p->round_sizes = pr.sizes;
     p->round_k = pr.levels;

@@ -53,6 +53,7 @@ enum : uint32_t {
   kErrOverflow = 4u,
   kErrTable = 8u,
   kErrBucket = 16u,  // a level advance found no live r-clique, or an empty bucket
+  kErrRuntime = 32u, // host side: a HIP call of the peel loop failed
 };
 
 // ----------------------------------------------------------------- helpers

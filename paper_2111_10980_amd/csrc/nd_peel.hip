@@ -1922,7 +1922,7 @@ uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableVie
     first = false;
     hipMemcpyAsync(mirror, E.rc.get(), sizeof(RoundCtl), hipMemcpyDeviceToHost, st);
     if (hipStreamSynchronize(st) != hipSuccess) {
-      status = kErrOverflow;  // reported by the caller's launch check
+      status = kErrRuntime;
       break;
     }
     const RoundCtl prev = m;
