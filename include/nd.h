@@ -38,7 +38,8 @@ typedef enum {
   ND_EINVAL = 1,     /* bad argument: r < 1, s <= r, s > ND_MAX_S, null pointer, ... */
   ND_EGRAPH = 2,     /* CSR is not simple/symmetric/sorted, or ids out of range */
   ND_EKEYWIDTH = 3,  /* (r-1) * ceil(log2 n) > 63: an r-clique key does not fit 64 bits */
-  ND_EOVERFLOW = 4,  /* an s-clique count exceeds UINT32_MAX, or a size exceeds 2^32 slots */
+  ND_EOVERFLOW = 4,  /* an s-clique count exceeds UINT32_MAX, the table exceeds 2^32-1 slots,
+                        or the graph has more than 2^31-1 r-cliques */
   ND_ENOMEM = 5,     /* device memory budget exceeded or allocation failed */
   ND_EHIP = 6,       /* a HIP runtime call failed */
   ND_ESTATE = 7      /* entry point called in the wrong order */

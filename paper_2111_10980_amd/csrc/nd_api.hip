@@ -377,6 +377,9 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
     p->n_r = read_dev((uint64_t *)&p->ctr.get()->n_s, st);
     if (p->n_slots >= (1ull << 32) - 1)
       fail(ND_EOVERFLOW, "table needs %llu slots (limit 2^32-1)", (unsigned long long)p->n_slots);
+    // round records carry the frontier position as a signed 32-bit index
+    if (p->n_r > 0x7FFFFFFFull)
+      fail(ND_EOVERFLOW, "%llu r-cliques (limit 2^31-1)", (unsigned long long)p->n_r);
     uint64_t table_bytes = p->n_slots * (sizeof(Slot) + 4) + p->n_r * 4 * 5;
     p->held = graph_bytes + table_bytes + (uint64_t)(n + 1) * 8;
     if (p->budget && p->held > p->budget)
