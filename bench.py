@@ -158,10 +158,11 @@ def main():
     ceil = nd.nd_roofline_measure(table_bytes, table_bytes)
     log(f"[bench] ceilings: {ceil}")
     # random-access model of the peel's update pass: every discovered s-clique
-    # probes its C(s,r)-1 other slots; every decrement is a returning atomic
+    # probes its C(s,r)-1 other slots; every decrement of a count still above
+    # the level is a returning atomic
     probes = st["discoveries"] * (c - 1)
     model_ms = 1000.0 * (probes / (ceil["gather16_gops"] * 1e9) +
-                         st["decrements"] / (ceil["atomic_ret_gops"] * 1e9))
+                         st["atomics"] / (ceil["atomic_ret_gops"] * 1e9))
     peel_step_ms = peel_ms / len(runs)
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"traffic_{kern.split('<')[0]}_{args.workload}.json")
@@ -179,7 +180,7 @@ def main():
                 "peel_kernel_ms_per_step": round(peel_ms / len(runs), 3),
                 "measured_ceilings": {k: round(v, 3) for k, v in ceil.items()},
                 "random_access_model": {
-                    "probes": probes, "atomics": st["decrements"],
+                    "probes": probes, "atomics": st["atomics"],
                     "model_ms": round(model_ms, 2),
                     "frac": round(model_ms / peel_step_ms, 4) if peel_step_ms > 0 else None}}
 
@@ -206,7 +207,7 @@ def main():
                    "m": g.m, "n_r": st["n_r"], "n_s": n_s, "rounds": st["rounds"],
                    "max_kappa": st["max_kappa"], "orientation": ["degree", "core"][args.orient],
                    "max_out_degree": st["max_out_degree"], "decrements": st["decrements"],
-                   "discoveries": st["discoveries"], "k_advances": st["k_advances"],
+                   "atomics": st["atomics"], "discoveries": st["discoveries"], "k_advances": st["k_advances"],
                    "table_slots": st["table_slots"], "phase_ms": st["ms"]},
         "roofline": roofline,
         "cpu_baseline": base,

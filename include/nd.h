@@ -84,6 +84,9 @@ typedef struct {
   float peel_kernel_ms;  /* with options.timing: summed time of the peel-round kernels */
   uint32_t count_launches;
   uint32_t peel_launches;
+  uint64_t atomics;      /* returning atomic decrements issued: a decrement of a count that
+                            is already at or below the level (Algorithm 2 clamps it to k)
+                            is counted in decrements but needs no memory operation */
 } nd_stats;
 
 typedef struct nd_plan_s *nd_plan; /* opaque, library-owned */

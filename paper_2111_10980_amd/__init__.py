@@ -50,7 +50,7 @@ class nd_stats(ctypes.Structure):
                 ("max_kappa", ctypes.c_uint32), ("max_out_degree", ctypes.c_uint32),
                 ("ms", ctypes.c_float * 8), ("count_kernel_ms", ctypes.c_float),
                 ("peel_kernel_ms", ctypes.c_float), ("count_launches", ctypes.c_uint32),
-                ("peel_launches", ctypes.c_uint32)]
+                ("peel_launches", ctypes.c_uint32), ("atomics", ctypes.c_uint64)]
 
 
 def _load():

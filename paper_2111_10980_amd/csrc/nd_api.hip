@@ -545,6 +545,7 @@ nd_status nd_run(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *cou
       stats->k_advances = p->k_advances;
       stats->decrements = hc.decrements;
       stats->discoveries = hc.discoveries;
+      stats->atomics = hc.atomics;
       stats->table_slots = p->n_slots;
       stats->max_kappa = p->round_k.empty() ? 0 : p->round_k.back();
       stats->max_out_degree = p->g.max_out;

@@ -476,15 +476,16 @@ void list_apex_keys(const OrientedGraph &g, uint64_t *cursor, uint64_t *keys, in
 
 __global__ __launch_bounds__(256) void k_stats_collect(const unsigned long long *__restrict__ stats,
                                                        Counters *dctr) {
-  // one block: thread i sums column i's lines for the three statistics
-  uint64_t acc[3] = {0, 0, 0};
+  // one block: thread i sums column i's lines for the four statistics
+  uint64_t acc[4] = {0, 0, 0, 0};
   for (int line = threadIdx.x; line < kStatLines; line += blockDim.x)
-    for (int w = 0; w < 3; w++) acc[w] += stats[line * kStatStride + w];
-  for (int w = 0; w < 3; w++) {
+    for (int w = 0; w < 4; w++) acc[w] += stats[line * kStatStride + w];
+  for (int w = 0; w < 4; w++) {
     const uint64_t t = wave_sum_u64(acc[w]);
     if (lane_id() == 0 && t) {
       unsigned long long *dst = (unsigned long long *)(w == kStatDec    ? &dctr->decrements
                                                        : w == kStatDisc ? &dctr->discoveries
+                                                       : w == kStatAtom ? &dctr->atomics
                                                                         : &dctr->n_s);
       atomicAdd(dst, (unsigned long long)t);
     }

@@ -330,6 +330,7 @@ struct Counters {
   uint64_t n_s;          // s-cliques listed by the count phase
   uint64_t decrements;
   uint64_t discoveries;
+  uint64_t atomics;      // returning atomic decrements issued (subset of decrements)
   uint32_t err;          // kErr* bits
   uint32_t next_size;    // appends to the next frontier in this round
   uint32_t class_size[8];
@@ -377,7 +378,7 @@ struct RoundCtl {
 // channel across all XCDs.
 constexpr int kStatLines = 1024;
 constexpr int kStatStride = 16;  // u64 per line
-enum : int { kStatDec = 0, kStatDisc = 1, kStatNs = 2 };
+enum : int { kStatDec = 0, kStatDisc = 1, kStatNs = 2, kStatAtom = 3 };
 
 __device__ __forceinline__ void stat_add(unsigned long long *stats, int which, uint64_t v) {
   const uint64_t t = wave_sum_u64(v);

@@ -54,7 +54,7 @@ struct PeelArgs {
 };
 
 struct LaneStats {
-  uint64_t dec = 0, disc = 0;
+  uint64_t dec = 0, disc = 0, atom = 0;
   uint32_t err = 0;
 };
 
@@ -166,11 +166,16 @@ __device__ __forceinline__ void update_func(const PeelArgs &a, const int32_t (&S
   for (int q = 0; q < N; q++) {
     bool want_append = false, want_low = false;
     if (mine && live[q]) {
-      uint32_t old = __hip_atomic_fetch_add(&a.T.slots[pos[q]].cnt, 0xFFFFFFFFu, __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT);
       ls.dec++;
-      want_append = old == a.k + 1;              // reaches this round's level
-      want_low = a.kw > a.k && old == a.kw + 1;  // enters the level window
+      // a count read at or below the level has crossed k+1 (and the window
+      // level) already: its decrement changes nothing after the clamp to k
+      if (sl[q].cnt > a.k) {
+        uint32_t old = __hip_atomic_fetch_add(&a.T.slots[pos[q]].cnt, 0xFFFFFFFFu,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ls.atom++;
+        want_append = old == a.k + 1;              // reaches this round's level
+        want_low = a.kw > a.k && old == a.kw + 1;  // enters the level window
+      }
     }
     if constexpr (kConvergent) {
       ap[0].push(want_append, (uint32_t)pos[q]);
@@ -287,6 +292,7 @@ __global__ __launch_bounds__(256) void k_peel(PeelArgs base, const RoundCtl *__r
   ap[1].flush();
   stat_add(a.stats, kStatDec, ls.dec);
   stat_add(a.stats, kStatDisc, ls.disc);
+  stat_add(a.stats, kStatAtom, ls.atom);
   if (ls.err) atomicOr(&a.ctr->err, ls.err);
 }
 
@@ -639,11 +645,14 @@ __device__ __forceinline__ void update_r3_ranked(const PeelArgs &a, const FastVi
   for (int q = 0; q < 4; q++) {
     bool want_append = false, want_low = false;
     if (mine && live[q]) {
-      const uint32_t old = __hip_atomic_fetch_add(&a.T.slots[pos[q]].cnt, 0xFFFFFFFFu,
-                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       ls.dec++;
-      want_append = old == a.k + 1;
-      want_low = a.kw > a.k && old == a.kw + 1;
+      if (sl[q].cnt > a.k) {  // else crossed already: see update_func
+        const uint32_t old = __hip_atomic_fetch_add(&a.T.slots[pos[q]].cnt, 0xFFFFFFFFu,
+                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ls.atom++;
+        want_append = old == a.k + 1;
+        want_low = a.kw > a.k && old == a.kw + 1;
+      }
     }
     ap[0].push(want_append, (uint32_t)pos[q]);
     ap[1].push(want_low, (uint32_t)pos[q]);
@@ -1001,6 +1010,7 @@ __device__ __forceinline__ void apply_body(const PeelArgs &base, const RoundCtl 
   ap[1].flush();
   stat_add(a.stats, kStatDec, ls.dec);
   stat_add(a.stats, kStatDisc, ls.disc);
+  stat_add(a.stats, kStatAtom, ls.atom);
   if (ls.err) atomicOr(&a.ctr->err, ls.err);
 }
 
@@ -1646,6 +1656,7 @@ __global__ __launch_bounds__(256) void k_gen_apply(PeelArgs base, RoundCtl *rc,
   ap[1].flush();
   stat_add(a.stats, kStatDec, ls.dec);
   stat_add(a.stats, kStatDisc, ls.disc);
+  stat_add(a.stats, kStatAtom, ls.atom);
   if (ls.err) atomicOr(&a.ctr->err, ls.err);
 }
 

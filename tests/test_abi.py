@@ -46,8 +46,39 @@ def test_struct_layouts():
     import paper_2111_10980_amd as nd
     assert ctypes.sizeof(nd.nd_csr) == 32
     assert ctypes.sizeof(nd.nd_options) == 16
-    # 7 u64 + 2 u32 + 8 floats + 2 floats + 2 u32
-    assert ctypes.sizeof(nd.nd_stats) == 7 * 8 + 2 * 4 + 8 * 4 + 2 * 4 + 2 * 4
+    # 7 u64 + 2 u32 + 8 floats + 2 floats + 2 u32 + 1 u64
+    assert ctypes.sizeof(nd.nd_stats) == 7 * 8 + 2 * 4 + 8 * 4 + 2 * 4 + 2 * 4 + 8
+
+
+def test_struct_layouts_match_c(tmp_path):
+    """Every field offset and struct size of the ctypes mirrors equals what a
+    C compiler makes of include/nd.h."""
+    import shutil
+    import subprocess
+    import paper_2111_10980_amd as nd
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"nd_csr": nd.nd_csr, "nd_options": nd.nd_options, "nd_stats": nd.nd_stats,
+               "nd_roofline": nd.nd_roofline}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "nd.h"',
+             '#include "nd_roofline.h"', "int main(void) {"]
+    for sname, cls in structs.items():
+        lines.append(f'  printf("{sname} %zu\\n", sizeof({sname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{sname}.{fname} %zu\\n", offsetof({sname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                  text=True).stdout.splitlines())
+    for sname, cls in structs.items():
+        assert int(got[sname]) == ctypes.sizeof(cls), sname
+        for fname, _ in cls._fields_:
+            assert int(got[f"{sname}.{fname}"]) == getattr(cls, fname).offset, (sname, fname)
 
 
 def test_binding_names_match_header():
