@@ -236,12 +236,17 @@ __device__ __forceinline__ void wave_append(bool want, uint32_t val, uint32_t *b
 // single atomic when fewer than 64 free entries remain, so a round with
 // A appended r-cliques costs about A / (kCap - 64) global atomics instead of
 // one per appending wave call (same-address atomics serialise across XCDs).
-template <int kCap>
+struct NoFlushHook {
+  __device__ __forceinline__ void operator()(uint32_t) const {}
+};
+
+template <int kCap, class Hook = NoFlushHook>
 struct WaveAppender {
   uint32_t *buf;   // LDS, kCap entries, private to this wave
   uint32_t count;  // wave-uniform
   uint32_t *out;
   uint32_t *counter;
+  Hook hook;       // called once per value as it is written out
 
   __device__ __forceinline__ void flush() {
     if (count == 0) return;
@@ -250,7 +255,11 @@ struct WaveAppender {
     uint32_t base = 0;
     if (lane_id() == 0) base = atomicAdd(counter, count);
     base = __shfl(base, 0);
-    for (uint32_t i = (uint32_t)lane_id(); i < count; i += kWave) out[base + i] = buf[i];
+    for (uint32_t i = (uint32_t)lane_id(); i < count; i += kWave) {
+      const uint32_t v = buf[i];
+      out[base + i] = v;
+      hook(v);
+    }
     __builtin_amdgcn_wave_barrier();
     count = 0;
   }
@@ -370,6 +379,8 @@ struct RoundCtl {
   uint32_t cF, cW, cH;     // partition output sizes (advance)
   uint32_t advances;
   uint32_t trace_cap;
+  uint32_t arrive;         // blocks of the running kernel that have finished (its last
+                           // block runs the round's bookkeeping and resets it to 0)
 };
 
 // Statistics accumulated by many waves go to kStatLines counter lines (one

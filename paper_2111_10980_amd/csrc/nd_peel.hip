@@ -79,6 +79,92 @@ __device__ __forceinline__ PeelArgs round_args(PeelArgs a, const RoundCtl *rc) {
   return a;
 }
 
+// Called by every thread of the block once its work is done; true in thread
+// 0 of the block that finishes last in the grid, which then resets the
+// counter for the next kernel.  What that block reads of the other blocks'
+// work must have been written with device-scope atomics (which complete
+// before the barrier) and be read back with atomic loads.
+__device__ __forceinline__ bool block_arrive_last(uint32_t *arrive) {
+  __syncthreads();
+  if (threadIdx.x != 0) return false;
+  const uint32_t prev =
+      __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (prev != gridDim.x - 1) return false;
+  __hip_atomic_store(arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return true;
+}
+
+__device__ __forceinline__ uint32_t load_agent(const uint32_t *p) {
+  return __hip_atomic_load(const_cast<uint32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Start of a round (one thread).  If the round starts with an empty frontier
+// the level advance is finished first: k <- max(k, minimum), new list sizes,
+// swapped list buffers.  A window list that holds only peeled r-cliques is
+// dropped instead and the round stays empty (the next one scans the high
+// list).  Then the round's lists and counters.
+__device__ void round_begin_body(RoundCtl *rc, Counters *dc) {
+  if (rc->nF == 0) {  // finish the advance first: a rerun must not partition again
+    const bool win = rc->nW != 0;
+    const uint32_t mn = win ? rc->mw : rc->mh;
+    const uint32_t cF = load_agent(&rc->cF), cW = load_agent(&rc->cW), cH = load_agent(&rc->cH);
+    if (win && mn == kNone) {
+      rc->nW = 0;
+    } else if (mn == kNone || cF == 0) {  // no live r-clique left, or an empty bucket
+      rc->err |= kErrBucket;
+      rc->halt = 3;
+      return;
+    } else {
+      rc->k = rc->k > mn ? rc->k : mn;
+      if (win) {
+        rc->selW ^= 1u;
+      } else {
+        rc->kw = rc->k + kWindowLevels;
+        rc->nH = cH;
+        rc->selH ^= 1u;
+      }
+      rc->nW = cW;
+      rc->nF = cF;
+      rc->advances++;
+    }
+    rc->mw = kNone;
+    rc->mh = kNone;
+    rc->cF = rc->cW = rc->cH = 0;
+  }
+  if (rc->t >= rc->trace_cap) {  // the host grows the round trace, then reruns
+    rc->halt = 2;
+    return;
+  }
+  const uint32_t sF = rc->selF;
+  rc->F = rc->bufF[sF];
+  rc->Fnext = rc->bufF[sF ^ 1u];
+  rc->Low = rc->bufW[rc->selW];
+  rc->total = 0;
+  rc->total2 = 0;
+  rc->total3 = 0;
+  dc->next_size = 0;
+  dc->low_size = rc->nW;  // window appends continue after the live entries
+}
+
+// End of a round (one thread): trace, finished += |A_t|, next frontier.  An
+// empty round (one that only dropped the window list) is not counted.
+__device__ void round_end_body(RoundCtl *rc, const Counters *dc) {
+  if (rc->nF == 0) return;
+  rc->trace_size[rc->t] = rc->nF;
+  rc->trace_k[rc->t] = rc->k;
+  rc->finished += rc->nF;
+  rc->t++;
+  rc->nF = load_agent(&dc->next_size);
+  rc->nW = load_agent(&dc->low_size);
+  rc->selF ^= 1u;
+  if (rc->finished > rc->n_r) {
+    rc->err |= kErrBucket;
+    rc->halt = 3;
+  } else if (rc->finished == rc->n_r) {
+    rc->done = 1;
+  }
+}
+
 __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
   const int lane = lane_id();
 #pragma unroll
@@ -315,49 +401,90 @@ __device__ __forceinline__ int64_t lower_pos(const int32_t *__restrict__ a, int6
 // r = 3 liveness bitmaps.  A triangle's bits in its root's alive bitmap are
 // cleared after the round that peels it, so the AND of two alive rows lists
 // only candidates whose two triangles through v1 were not peeled earlier.
-// r = 3, after the round: the triangles of the frontier are gone, so their
-// bits leave the alive bitmaps, the apex alive bits and the frontier marks.
-// With mark = true (before the round's bound pass) their frontier bits are
-// set instead: the expand pass can then tell which s-cliques another member
-// of the frontier owns.  Positions come from the slot's loc word.
+// A triangle's frontier bits are set when it joins a frontier (the level
+// advance that selects it, or the update pass whose decrement brings its
+// count to the level): the next round's bound and expand passes can then
+// tell which s-cliques another member of the frontier owns.  When its round
+// ends (kMark = false) its bits leave the alive bitmaps, the apex alive bits
+// and the frontier marks.  Positions come from the slot's loc word; bits of
+// different triangles may share a word, hence the atomics.
 template <bool kMark>
-__global__ void k_front_bits(GraphView g, TableView T, FastView fx,
-                             const uint64_t *__restrict__ loc, const RoundCtl *__restrict__ rc) {
-  if (rc_idle(rc)) return;
-  const uint32_t *__restrict__ F = rc->F;
-  const uint32_t nF = rc->nF;
-  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < nF;
-       it += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t p = F[it];
-    const uint64_t lc = loc[p];
-    const uint64_t ap = (lc >> kApexShift) & kApexMask;
-    if (ap) {
-      const uint64_t q = ap - 1, bit = 1ull << (q & 63);
-      if (kMark) {
-        atomicOr((unsigned long long *)&fx.front_apex[q >> 6], bit);
-      } else {
-        atomicAnd((unsigned long long *)&fx.alive_apex[q >> 6], ~bit);
-        atomicAnd((unsigned long long *)&fx.front_apex[q >> 6], ~bit);
-      }
-    }
-    if (!(lc >> 63)) continue;  // root without a bitmap
-    const int32_t v1 = T.v1[p];
-    const int d = (int)(g.rp[v1 + 1] - g.up[v1]);
-    const int wd = (d + 63) >> 6;
-    const int64_t i = (int64_t)(lc & 511u), j = (int64_t)((lc >> 9) & 511u);
-    const uint64_t bi = 1ull << (i & 63), bj = 1ull << (j & 63);
-    unsigned long long *fr = (unsigned long long *)(fx.front + fx.bm_off[v1]);
+__device__ __forceinline__ void front_bits_one(const GraphView &g,
+                                               const int32_t *__restrict__ v1s,
+                                               const FastView &fx,
+                                               const uint64_t *__restrict__ loc, uint32_t p) {
+  const uint64_t lc = loc[p];
+  const uint64_t ap = (lc >> kApexShift) & kApexMask;
+  if (ap) {
+    const uint64_t q = ap - 1, bit = 1ull << (q & 63);
     if (kMark) {
-      atomicOr(&fr[i * wd + (j >> 6)], bj);
-      atomicOr(&fr[j * wd + (i >> 6)], bi);
+      atomicOr((unsigned long long *)&fx.front_apex[q >> 6], bit);
     } else {
-      unsigned long long *al = (unsigned long long *)(fx.alive + fx.bm_off[v1]);
-      atomicAnd(&al[i * wd + (j >> 6)], ~bj);
-      atomicAnd(&al[j * wd + (i >> 6)], ~bi);
-      atomicAnd(&fr[i * wd + (j >> 6)], ~bj);
-      atomicAnd(&fr[j * wd + (i >> 6)], ~bi);
+      atomicAnd((unsigned long long *)&fx.alive_apex[q >> 6], ~bit);
+      atomicAnd((unsigned long long *)&fx.front_apex[q >> 6], ~bit);
     }
   }
+  if (!(lc >> 63)) return;  // root without a bitmap
+  const int32_t v1 = v1s[p];
+  const int d = (int)(g.rp[v1 + 1] - g.up[v1]);
+  const int wd = (d + 63) >> 6;
+  const int64_t i = (int64_t)(lc & 511u), j = (int64_t)((lc >> 9) & 511u);
+  const uint64_t bi = 1ull << (i & 63), bj = 1ull << (j & 63);
+  unsigned long long *fr = (unsigned long long *)(fx.front + fx.bm_off[v1]);
+  if (kMark) {
+    atomicOr(&fr[i * wd + (j >> 6)], bj);
+    atomicOr(&fr[j * wd + (i >> 6)], bi);
+  } else {
+    unsigned long long *al = (unsigned long long *)(fx.alive + fx.bm_off[v1]);
+    atomicAnd(&al[i * wd + (j >> 6)], ~bj);
+    atomicAnd(&al[j * wd + (i >> 6)], ~bi);
+    atomicAnd(&fr[i * wd + (j >> 6)], ~bj);
+    atomicAnd(&fr[j * wd + (i >> 6)], ~bi);
+  }
+}
+
+// Flush hook of the r = 3 update pass: an r-clique appended to the next
+// frontier gets its frontier marks as it is written out (the marking half
+// of front_bits_one, with only the pointers it needs).
+struct FrontMark {
+  const int64_t *rp, *up;
+  const int32_t *v1;
+  const uint64_t *bm_off, *loc;
+  uint64_t *front, *front_apex;
+  __device__ __forceinline__ void operator()(uint32_t p) const {
+    GraphView g{};
+    g.rp = rp;
+    g.up = up;
+    FastView fx{};
+    fx.bm_off = bm_off;
+    fx.front = front;
+    fx.front_apex = front_apex;
+    front_bits_one<true>(g, v1, fx, loc, p);
+  }
+};
+using FrontAppender = WaveAppender<kAppendCap, FrontMark>;
+
+// Position of the (n+1)-th set bit of m, n < popcount(m): a halving search
+// on popcounts, the same six steps in every lane.
+__device__ __forceinline__ uint32_t select_bit(uint64_t m, uint32_t n) {
+  uint32_t pos = 0;
+  uint32_t lo = (uint32_t)m;
+  uint32_t c = (uint32_t)__popc(lo);
+  if (n >= c) {
+    n -= c;
+    lo = (uint32_t)(m >> 32);
+    pos = 32;
+  }
+#pragma unroll
+  for (int w = 16; w >= 2; w >>= 1) {
+    c = (uint32_t)__popc(lo & ((1u << w) - 1u));
+    if (n >= c) {
+      n -= c;
+      lo >>= w;
+      pos += (uint32_t)w;
+    }
+  }
+  return pos + (n >= (lo & 1u) ? 1u : 0u);
 }
 
 // Bits of word w of a bitmap row at local positions < l.
@@ -557,7 +684,8 @@ __device__ __forceinline__ int64_t tri_slot(const PeelArgs &a, const FastView &f
 __device__ __forceinline__ void update_r3_ranked(const PeelArgs &a, const FastView &fx,
                                                  const int32_t (&Rv)[3], int32_t x, uint64_t lc,
                                                  uint32_t lxh, uint32_t l23, bool active,
-                                                 LaneStats &ls, Appender *ap) {
+                                                 LaneStats &ls, FrontAppender &apf,
+                                                 Appender &apl) {
   constexpr Combos<4, 3> cb{};
   int32_t Sv[4];
   uint32_t rmask = 0;
@@ -654,8 +782,8 @@ __device__ __forceinline__ void update_r3_ranked(const PeelArgs &a, const FastVi
         want_low = a.kw > a.k && old == a.kw + 1;
       }
     }
-    ap[0].push(want_append, (uint32_t)pos[q]);
-    ap[1].push(want_low, (uint32_t)pos[q]);
+    apf.push(want_append, (uint32_t)pos[q]);
+    apl.push(want_low, (uint32_t)pos[q]);
   }
 }
 
@@ -923,9 +1051,7 @@ __global__ __launch_bounds__(256) void k_expand(PeelArgs base, RoundCtl *rc, Fas
       uint32_t lxw = 0xFFFFu;  // local index of x in N+(v1), bitmap part only
       if (in && k < total1) {
         if (has_bm) {
-          uint64_t m = wordw;
-          for (uint32_t q = 0; q < kk - before; q++) m &= m - 1;
-          lxw = (uint32_t)(w * 64 + (__ffsll((unsigned long long)m) - 1));
+          lxw = (uint32_t)w * 64u + select_bit(wordw, kk - before);
           x = a.g.col[o + lxw];
         } else {
           x = a.g.col[o + (int64_t)k];
@@ -980,34 +1106,48 @@ __device__ __forceinline__ void apply_body(const PeelArgs &base, const RoundCtl 
   const int lane = lane_id();
   LaneStats ls;
   uint32_t(*abuf)[2][kAppendCap] = abuf_mem;
-  Appender ap[2] = {{abuf[wv][0], 0u, a.Fnext, &a.ctr->next_size},
-                    {abuf[wv][1], 0u, a.Low, &a.ctr->low_size}};
   // wave-uniform trip count: every lane reaches every append
-  for (uint64_t base = ((uint64_t)blockIdx.x * blockDim.x) + (uint64_t)wv * kWave; base < total;
-       base += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t i = base + lane;
-    bool in = i < total;
-    int2 rc = make_int2(0, -1);
-    if (in) rc = rec[i];
-    in = in && rc.y >= 0;
-    int32_t Rv[R];
-    uint32_t p = 0;
-    if (in) {
-      p = F[rc.x];
+  auto each_record = [&](auto &&update) {
+    for (uint64_t b0 = ((uint64_t)blockIdx.x * blockDim.x) + (uint64_t)wv * kWave; b0 < total;
+         b0 += (uint64_t)gridDim.x * blockDim.x) {
+      const uint64_t i = b0 + lane;
+      bool in = i < total;
+      int2 rc = make_int2(0, -1);
+      if (in) rc = rec[i];
+      in = in && rc.y >= 0;
+      int32_t Rv[R];
+      uint32_t p = 0;
+      if (in) {
+        p = F[rc.x];
 #pragma unroll
-      for (int q = 0; q < R; q++) Rv[q] = fv[(int64_t)rc.x * R + q];
-    } else {
+        for (int q = 0; q < R; q++) Rv[q] = fv[(int64_t)rc.x * R + q];
+      } else {
 #pragma unroll
-      for (int q = 0; q < R; q++) Rv[q] = q;
+        for (int q = 0; q < R; q++) Rv[q] = q;
+      }
+      update(Rv, in, rc, p, i);
     }
-    if constexpr (R == 3)  // r = 3 plans keep the ranked table
+  };
+  if constexpr (R == 3) {  // r = 3 plans keep the ranked table and the frontier marks
+    FrontAppender apf{abuf[wv][0], 0u, a.Fnext, &a.ctr->next_size,
+                      FrontMark{a.g.rp, a.g.up, a.T.v1, fx.bm_off, loc, fx.front,
+                                fx.front_apex}};
+    Appender apl{abuf[wv][1], 0u, a.Low, &a.ctr->low_size};
+    each_record([&](const int32_t(&Rv)[R], bool in, int2 rc, uint32_t p, uint64_t i) {
       update_r3_ranked(a, fx, Rv, in ? rc.y : R, in ? loc[p] : 0ull, in ? rloc[i] : 0xFFFFu,
-                       in ? f23[rc.x] : 0xFFFFFFFFu, in, ls, ap);
-    else
+                       in ? f23[rc.x] : 0xFFFFFFFFu, in, ls, apf, apl);
+    });
+    apf.flush();
+    apl.flush();
+  } else {
+    Appender ap[2] = {{abuf[wv][0], 0u, a.Fnext, &a.ctr->next_size},
+                      {abuf[wv][1], 0u, a.Low, &a.ctr->low_size}};
+    each_record([&](const int32_t(&Rv)[R], bool in, int2 rc, uint32_t p, uint64_t) {
       peel_candidate<R>(a, Rv, in ? rc.y : R, in, p, ls, ap);
+    });
+    ap[0].flush();
+    ap[1].flush();
   }
-  ap[0].flush();
-  ap[1].flush();
   stat_add(a.stats, kStatDec, ls.dec);
   stat_add(a.stats, kStatDisc, ls.disc);
   stat_add(a.stats, kStatAtom, ls.atom);
@@ -1031,7 +1171,10 @@ __global__ __launch_bounds__(256) void k_apply(PeelArgs base, const RoundCtl *__
 // (measured: 5 waves 391 ms, 6 waves 376 ms, 8 waves with spills 434 ms per
 // rMAT-18 (3,4) decomposition).  Other r keep the default (their larger
 // subset arrays would spill).
-__global__ __launch_bounds__(256, 6) void k_apply3(PeelArgs base, const RoundCtl *__restrict__ rc,
+// It also ends the round: the frontier's triangles leave the liveness
+// bitmaps and frontier marks (no pass of the round reads them after expand),
+// and the block that finishes last does the round's bookkeeping.
+__global__ __launch_bounds__(256, 6) void k_apply3(PeelArgs base, RoundCtl *rc,
                                                    const int2 *__restrict__ rec,
                                                    const int32_t *__restrict__ fv, FastView fx,
                                                    const uint64_t *__restrict__ loc,
@@ -1040,6 +1183,12 @@ __global__ __launch_bounds__(256, 6) void k_apply3(PeelArgs base, const RoundCtl
   if (rc_idle(rc)) return;
   __shared__ uint32_t abuf[256 / kWave][2][kAppendCap];
   apply_body<3>(base, rc, rec, fv, fx, loc, rloc, f23, abuf);
+  const uint32_t *__restrict__ F = rc->F;
+  const uint32_t nF = rc->nF;
+  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < nF;
+       it += (int64_t)gridDim.x * blockDim.x)
+    front_bits_one<false>(base.g, base.T.v1, fx, loc, F[it]);
+  if (block_arrive_last(&rc->arrive)) round_end_body(rc, base.ctr);
 }
 
 // Direct count, one wave per r-clique (r >= 3): the part x > v1 is a
@@ -1177,15 +1326,16 @@ __global__ void k_make_loc(GraphView g, TableView T, FastView fx, uint64_t n_slo
 
 // ---------------------------------------------------------- round control
 // One round is queued as
-//   k_adv_min<false>, k_adv_min<true>, k_adv_partition
+//   k_adv_min, k_adv_partition
 //       level advance; they act only when the round starts with an empty
-//       frontier (B.next_bucket of Algorithm 2);
-//   k_round_begin            one thread: finishes an advance, then the
-//                            round's lists and counters;
-//   [k_front_bits<true>]     r = 3 frontier marks;
+//       frontier (B.next_bucket of Algorithm 2).  The partition's last block
+//       finishes the advance and sets up the round (round_begin_body); when
+//       the host knows the frontier is not empty it queues k_round_begin
+//       alone instead;
 //   the update passes of the path (the first one stamps A_t with t);
-//   [k_front_bits<false>]    r = 3 liveness bitmaps and marks;
-//   k_round_end              one thread: trace, finished += |A_t|, next frontier.
+//   k_round_end              one thread: trace, finished += |A_t|, next
+//                            frontier (for r = 3 on the s = r+1 path the
+//                            update pass's last block does this).
 // Every kernel returns at once once the peel has finished or halted, so the
 // host may queue rounds past the last one and read the state only now and
 // then.
@@ -1199,14 +1349,13 @@ __global__ void k_stamp(const RoundCtl *__restrict__ rc, Slot *slots) {
     slots[F[i]].stamp = t;
 }
 
-// Minimum count over the live entries of the window list (kHigh = false),
-// or of the high list once the window holds no live entry.
-template <bool kHigh>
+// Minimum count over the live entries of the window list, or of the high
+// list when the window list is empty.
 __global__ __launch_bounds__(256) void k_adv_min(RoundCtl *rc, const Slot *__restrict__ slots) {
   if (rc_idle(rc) || rc->nF != 0) return;
-  if (kHigh ? (rc->nW != 0 && rc->mw != kNone) : rc->nW == 0) return;
-  const uint32_t *__restrict__ L = kHigh ? rc->bufH[rc->selH] : rc->bufW[rc->selW];
-  const uint32_t nL = kHigh ? rc->nH : rc->nW;
+  const bool win = rc->nW != 0;
+  const uint32_t *__restrict__ L = win ? rc->bufW[rc->selW] : rc->bufH[rc->selH];
+  const uint32_t nL = win ? rc->nW : rc->nH;
   uint32_t m = kNone;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nL;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -1214,7 +1363,7 @@ __global__ __launch_bounds__(256) void k_adv_min(RoundCtl *rc, const Slot *__res
     if (s.stamp == kLive && s.cnt < m) m = s.cnt;
   }
   m = wave_min_u32(m);
-  if (lane_id() == 0 && m != kNone) atomicMin(kHigh ? &rc->mh : &rc->mw, m);
+  if (lane_id() == 0 && m != kNone) atomicMin(win ? &rc->mw : &rc->mh, m);
 }
 
 // Three-way partition of the list the advance works on, by count c:
@@ -1223,16 +1372,18 @@ __global__ __launch_bounds__(256) void k_adv_min(RoundCtl *rc, const Slot *__res
 // window list is compacted into its other buffer; when a new window is
 // opened the high list is split.  Each block compacts a tile of 256 x 16
 // entries with one atomic per output per tile (a single global counter per
-// wave would serialise in L2).
+// wave would serialise in L2).  With mark (r = 3 on the s = r+1 path) the
+// new frontier's triangles get their frontier marks.  Runs in every round:
+// the last block to finish sets the round up.
 constexpr int kPartThreads = 256;
 constexpr int kPartItems = 16;
 
-__global__ __launch_bounds__(kPartThreads) void k_adv_partition(RoundCtl *rc,
-                                                                const Slot *__restrict__ slots) {
-  if (rc_idle(rc) || rc->nF != 0) return;
-  const bool win = rc->nW != 0 && rc->mw != kNone;
-  const uint32_t mn = win ? rc->mw : rc->mh;
-  if (mn == kNone) return;  // k_round_begin reports it
+__device__ __forceinline__ void partition_body(RoundCtl *rc, const Slot *__restrict__ slots,
+                                               bool win, uint32_t mn, bool mark,
+                                               const GraphView &g,
+                                               const int32_t *__restrict__ v1s,
+                                               const FastView &fx,
+                                               const uint64_t *__restrict__ loc) {
   const uint32_t k = rc->k > mn ? rc->k : mn;
   const uint32_t kw = win ? 0xFFFFFFFEu : k + kWindowLevels;
   const uint32_t *__restrict__ L = win ? rc->bufW[rc->selW] : rc->bufH[rc->selH];
@@ -1285,7 +1436,10 @@ __global__ __launch_bounds__(kPartThreads) void k_adv_partition(RoundCtl *rc,
     for (int q = 0; q < 3; q++) at[q] = base[q] + wsum[q][w] + incl[q] - cnt[q];
 #pragma unroll
     for (int j = 0; j < kPartItems; j++) {
-      if (m[0] >> j & 1u) F[at[0]++] = p[j];
+      if (m[0] >> j & 1u) {
+        F[at[0]++] = p[j];
+        if (mark) front_bits_one<true>(g, v1s, fx, loc, p[j]);
+      }
       if (m[1] >> j & 1u) Lo[at[1]++] = p[j];
       if (m[2] >> j & 1u) Hi[at[2]++] = p[j];
     }
@@ -1293,64 +1447,24 @@ __global__ __launch_bounds__(kPartThreads) void k_adv_partition(RoundCtl *rc,
   }
 }
 
-// One thread.  After a level advance (the round started with an empty
-// frontier): k <- max(k, minimum), new list sizes, swap the list buffers.
-// Then the round's lists and counters.
+__global__ __launch_bounds__(kPartThreads) void k_adv_partition(
+    RoundCtl *rc, const Slot *__restrict__ slots, Counters *dc, bool mark, GraphView g,
+    const int32_t *__restrict__ v1s, FastView fx, const uint64_t *__restrict__ loc) {
+  if (rc_idle(rc)) return;
+  const bool win = rc->nW != 0;
+  const uint32_t mn = win ? rc->mw : rc->mh;
+  if (rc->nF == 0 && mn != kNone) partition_body(rc, slots, win, mn, mark, g, v1s, fx, loc);
+  if (block_arrive_last(&rc->arrive)) round_begin_body(rc, dc);
+}
+
 __global__ void k_round_begin(RoundCtl *rc, Counters *dc) {
   if (rc_idle(rc)) return;
-  if (rc->nF == 0) {  // finish the advance first: a rerun must not partition again
-    const bool win = rc->nW != 0 && rc->mw != kNone;
-    const uint32_t mn = win ? rc->mw : rc->mh;
-    if (mn == kNone || rc->cF == 0) {  // no live r-clique left, or an empty bucket
-      rc->err |= kErrBucket;
-      rc->halt = 3;
-      return;
-    }
-    rc->k = rc->k > mn ? rc->k : mn;
-    if (win) {
-      rc->selW ^= 1u;
-    } else {
-      rc->kw = rc->k + kWindowLevels;
-      rc->nH = rc->cH;
-      rc->selH ^= 1u;
-    }
-    rc->nW = rc->cW;
-    rc->nF = rc->cF;
-    rc->advances++;
-    rc->mw = kNone;
-    rc->mh = kNone;
-    rc->cF = rc->cW = rc->cH = 0;
-  }
-  if (rc->t >= rc->trace_cap) {  // the host grows the round trace, then reruns
-    rc->halt = 2;
-    return;
-  }
-  const uint32_t sF = rc->selF;
-  rc->F = rc->bufF[sF];
-  rc->Fnext = rc->bufF[sF ^ 1u];
-  rc->Low = rc->bufW[rc->selW];
-  rc->total = 0;
-  rc->total2 = 0;
-  rc->total3 = 0;
-  dc->next_size = 0;
-  dc->low_size = rc->nW;  // window appends continue after the live entries
+  round_begin_body(rc, dc);
 }
 
 __global__ void k_round_end(RoundCtl *rc, const Counters *dc) {
   if (rc_idle(rc)) return;
-  rc->trace_size[rc->t] = rc->nF;
-  rc->trace_k[rc->t] = rc->k;
-  rc->finished += rc->nF;
-  rc->t++;
-  rc->nF = dc->next_size;
-  rc->nW = dc->low_size;
-  rc->selF ^= 1u;
-  if (rc->finished > rc->n_r) {
-    rc->err |= kErrBucket;
-    rc->halt = 3;
-  } else if (rc->finished == rc->n_r) {
-    rc->done = 1;
-  }
+  round_end_body(rc, dc);
 }
 
 __global__ void k_occ_flags(const Slot *__restrict__ slots, uint64_t n, uint32_t *flags) {
@@ -1709,9 +1823,6 @@ void launch_walker(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, hipEvent_t
 template <int R>
 void launch_fast(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, dim3 ga, hipEvent_t e0,
                  hipEvent_t e1) {
-  if (R == 3)
-    hipLaunchKernelGGL(k_front_bits<true>, gf, dim3(256), 0, E.st, E.gv, E.T, E.fxv, E.loc,
-                       E.rc.get());
   hipLaunchKernelGGL(k_expand_bound<R>, gf, dim3(256), 0, E.st, base, E.rc.get(), E.fxv, E.loc,
                      E.off.get(), E.len.get(), E.fv.get(), E.desc.get(), E.f23.get());
   hipLaunchKernelGGL(k_expand<R>, gw, dim3(256), 0, E.st, base, E.rc.get(), E.fxv, E.desc.get(),
@@ -1724,9 +1835,6 @@ void launch_fast(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, dim3 ga, hip
     hipLaunchKernelGGL(k_apply<R>, ga, dim3(256), 0, E.st, base, E.rc.get(), E.rec.get(),
                        E.fv.get(), E.fxv, E.loc, E.rloc.get(), E.f23.get());
   if (e1) hipEventRecord(e1, E.st);
-  if (R == 3)
-    hipLaunchKernelGGL(k_front_bits<false>, gf, dim3(256), 0, E.st, E.gv, E.T, E.fxv, E.loc,
-                       E.rc.get());
 }
 
 template <int R, int S>
@@ -1758,19 +1866,22 @@ void enqueue_round(Engine &E, const RoundCtl &m, bool exact, hipEvent_t e0, hipE
                    hipEvent_t e_adv) {
   const hipStream_t st = E.st;
   RoundCtl *rc = E.rc.get();
+  // r = 3 on the s = r+1 path: frontier marks at selection, round end in
+  // the update pass
+  const bool r3 = E.path == 1 && E.r == 3;
   if (!exact || m.nF == 0) {
     // queued behind other rounds these act only now and then: small grids
     const uint64_t cap_b = exact ? 8192 : 256;
-    hipLaunchKernelGGL(k_adv_min<false>, blocks_for(m.nW, 256 * 8, 1, cap_b), dim3(256), 0, st, rc,
+    const uint64_t nl = m.nW != 0 ? m.nW : m.nH;
+    hipLaunchKernelGGL(k_adv_min, blocks_for(nl, 256 * 8, 1, cap_b), dim3(256), 0, st, rc,
                        E.T.slots);
-    hipLaunchKernelGGL(k_adv_min<true>, blocks_for(m.nH, 256 * 8, 1, cap_b), dim3(256), 0, st, rc,
-                       E.T.slots);
-    hipLaunchKernelGGL(k_adv_partition,
-                       blocks_for(m.nW > m.nH ? m.nW : m.nH, kPartThreads * kPartItems, 1, cap_b),
-                       dim3(kPartThreads), 0, st, rc, E.T.slots);
+    hipLaunchKernelGGL(k_adv_partition, blocks_for(nl, kPartThreads * kPartItems, 1, cap_b),
+                       dim3(kPartThreads), 0, st, rc, E.T.slots, E.dc, r3, E.gv, E.T.v1, E.fxv,
+                       E.loc);
+  } else {
+    hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, st, rc, E.dc);
   }
   if (e_adv) hipEventRecord(e_adv, st);
-  hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, st, rc, E.dc);
   // Grids: sized to the frontier when it is known (nothing in flight and no
   // level advance), otherwise wide enough to fill the chip, so that a large
   // round queued behind small ones never runs on a small grid.
@@ -1810,7 +1921,7 @@ void enqueue_round(Engine &E, const RoundCtl &m, bool exact, hipEvent_t e0, hipE
       default: break;
     }
   }
-  hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, st, rc, E.dc);
+  if (!r3) hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, st, rc, E.dc);
 }
 
 template <class T>
