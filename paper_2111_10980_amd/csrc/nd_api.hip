@@ -360,9 +360,11 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
     // (3,4)-type plans the triangles of bitmap roots are placed by rank
     // (ordered within a root), so the bitmaps are built first.
     const bool ranked = p->fast && r == 3;
-    if (ranked) build_fast_index(p->g, &p->fx, p->ctr.get(), st);
     DevBuf<uint32_t> cnt(n > 0 ? (size_t)n : 1);
-    count_rcliques(p->g, r, cnt.get(), st);
+    if (ranked)  // the index counts the triangles per root on the way
+      build_fast_index(p->g, &p->fx, p->ctr.get(), st, cnt.get());
+    else
+      count_rcliques(p->g, r, cnt.get(), st);
     p->seg.reset((size_t)n + 1);
     fill_u64(p->seg.get() + n, 0, 1, st);
     if (ranked)

@@ -96,11 +96,27 @@ __global__ void k_bitmap_classes(GraphView g, uint32_t *lists, int32_t n, uint32
   }
 }
 
+// Apex-list lengths.  The keys are sorted, so the lanes of a wave mostly
+// share an arc: each run of equal arcs is added by its last lane with one
+// atomic.
 __global__ void k_arc_hist(const uint64_t *__restrict__ keys, uint64_t nk, int xbits,
                            unsigned long long *cnt) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)nk;
-       i += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&cnt[keys[i] >> xbits], 1ull);
+  const int lane = lane_id();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1));
+       b < (int64_t)nk; b += stride) {  // wave-uniform
+    const int64_t i = b + lane;
+    const bool in = i < (int64_t)nk;
+    const uint64_t a = in ? keys[i] >> xbits : ~0ull;
+    const uint64_t an = __shfl_down(a, 1);
+    const bool last = in && (lane == kWave - 1 || an != a);
+    const uint64_t m = __ballot(last);
+    if (last) {
+      const uint64_t below = m & lanes_below();
+      const int prev = below ? 63 - __clzll((long long)below) : -1;
+      atomicAdd(&cnt[a], (unsigned long long)(lane - prev));
+    }
+  }
 }
 
 __global__ void k_apex_values(const uint64_t *__restrict__ keys, uint64_t nk, uint64_t xmask,
@@ -231,7 +247,8 @@ void ranked_insert(const OrientedGraph &g, const FastIndex &fx, const TableView 
                      g.view(), fx.bm_off.get(), fx.bm.get(), fx.rowpre.get(), T);
 }
 
-void build_fast_index(const OrientedGraph &g, FastIndex *fx, Counters *dctr, hipStream_t st) {
+void build_fast_index(const OrientedGraph &g, FastIndex *fx, Counters *dctr, hipStream_t st,
+                      uint32_t *tri_per_root) {
   const int32_t n = g.n;
   const GraphView gv = g.view();
   fx->bm_off.reset((size_t)n + 1);
@@ -276,10 +293,15 @@ void build_fast_index(const OrientedGraph &g, FastIndex *fx, Counters *dctr, hip
                          lists.get() + 3 * (int64_t)n, sz[3], fx->bm_off.get(), fx->bm.get());
   }
   // ---- apex lists
-  DevBuf<uint32_t> tri((size_t)n);
-  count_rcliques(g, 3, tri.get(), st);
+  DevBuf<uint32_t> own_tri;
+  uint32_t *tri = tri_per_root;
+  if (!tri) {
+    own_tri.reset((size_t)n);
+    tri = own_tri.get();
+  }
+  count_rcliques(g, 3, tri, st);
   DevBuf<uint64_t> cur((size_t)n + 1);
-  widen_u32_to_u64(tri.get(), cur.get(), n, st);
+  widen_u32_to_u64(tri, cur.get(), n, st);
   fill_u64(cur.get() + n, 0, 1, st);
   scan_exclusive_u64(cur.get(), cur.get(), (int64_t)n + 1, st);
   hipMemcpyAsync(&fx->n_tri, cur.get() + n, 8, hipMemcpyDeviceToHost, st);
@@ -291,7 +313,9 @@ void build_fast_index(const OrientedGraph &g, FastIndex *fx, Counters *dctr, hip
     const int eb = bits_for((uint64_t)g.nnz);
     DevBuf<uint64_t> keys(T);
     list_apex_keys(g, cur.get(), keys.get(), xb, dctr, st);
-    radix_sort(keys.get(), nullptr, (int64_t)T, xb + eb, st);
+    // the keys arrive grouped by x in ascending order, so a stable sort on
+    // the arc bits alone leaves each list sorted by x
+    radix_sort(keys.get(), nullptr, (int64_t)T, xb + eb, st, xb);
     DevBuf<uint64_t> cnt((size_t)g.nnz + 1);
     fill_u64(cnt.get(), 0, g.nnz + 1, st);
     hipLaunchKernelGGL(k_arc_hist, dim3((unsigned)grid_for(T, 256)), dim3(256), 0, st, keys.get(),

@@ -57,8 +57,9 @@ void widen_u32_to_u64(const uint32_t *a, uint64_t *b, int64_t n, hipStream_t st)
 // exclusive prefix sum, in place allowed; n elements
 void scan_exclusive_u64(const uint64_t *in, uint64_t *out, int64_t n, hipStream_t st);
 void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t st);
-// stable LSD radix sort of keys (low `bits` bits significant), optional values
-void radix_sort(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t st);
+// stable LSD radix sort of keys by bits [lo_bit, bits), optional values
+void radix_sort(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t st,
+                int lo_bit = 0);
 // sum of a u32 array into *out (device u64, accumulated)
 void sum_u32(const uint32_t *p, int64_t n, uint64_t *out, hipStream_t st);
 uint32_t max_u32_host(const uint32_t *p, int64_t n, hipStream_t st);
@@ -123,7 +124,10 @@ struct FastIndex {
                     rowpre.n ? rowpre.get() : nullptr};
   }
 };
-void build_fast_index(const OrientedGraph &g, FastIndex *fx, Counters *dctr, hipStream_t st);
+// tri_per_root (nullable, n entries) receives the triangles rooted at each
+// vertex, which the apex lists are laid out by
+void build_fast_index(const OrientedGraph &g, FastIndex *fx, Counters *dctr, hipStream_t st,
+                      uint32_t *tri_per_root = nullptr);
 // r = 3 ranked table.  A triangle (v, a, b) whose root v keeps a bitmap sits
 // at seg[v] + its rank among the bits of v's bitmap above the diagonal
 // (row-major), so the triangles of one bitmap row are contiguous; roots

@@ -379,8 +379,6 @@ struct RoundCtl {
   uint32_t cF, cW, cH;     // partition output sizes (advance)
   uint32_t advances;
   uint32_t trace_cap;
-  uint32_t arrive;         // blocks of the running kernel that have finished (its last
-                           // block runs the round's bookkeeping and resets it to 0)
 };
 
 // Statistics accumulated by many waves go to kStatLines counter lines (one

@@ -79,25 +79,6 @@ __device__ __forceinline__ PeelArgs round_args(PeelArgs a, const RoundCtl *rc) {
   return a;
 }
 
-// Called by every thread of the block once its work is done; true in thread
-// 0 of the block that finishes last in the grid, which then resets the
-// counter for the next kernel.  What that block reads of the other blocks'
-// work must have been written with device-scope atomics (which complete
-// before the barrier) and be read back with atomic loads.
-__device__ __forceinline__ bool block_arrive_last(uint32_t *arrive) {
-  __syncthreads();
-  if (threadIdx.x != 0) return false;
-  const uint32_t prev =
-      __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (prev != gridDim.x - 1) return false;
-  __hip_atomic_store(arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return true;
-}
-
-__device__ __forceinline__ uint32_t load_agent(const uint32_t *p) {
-  return __hip_atomic_load(const_cast<uint32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Start of a round (one thread).  If the round starts with an empty frontier
 // the level advance is finished first: k <- max(k, minimum), new list sizes,
 // swapped list buffers.  A window list that holds only peeled r-cliques is
@@ -107,7 +88,7 @@ __device__ void round_begin_body(RoundCtl *rc, Counters *dc) {
   if (rc->nF == 0) {  // finish the advance first: a rerun must not partition again
     const bool win = rc->nW != 0;
     const uint32_t mn = win ? rc->mw : rc->mh;
-    const uint32_t cF = load_agent(&rc->cF), cW = load_agent(&rc->cW), cH = load_agent(&rc->cH);
+    const uint32_t cF = rc->cF, cW = rc->cW, cH = rc->cH;
     if (win && mn == kNone) {
       rc->nW = 0;
     } else if (mn == kNone || cF == 0) {  // no live r-clique left, or an empty bucket
@@ -154,8 +135,8 @@ __device__ void round_end_body(RoundCtl *rc, const Counters *dc) {
   rc->trace_k[rc->t] = rc->k;
   rc->finished += rc->nF;
   rc->t++;
-  rc->nF = load_agent(&dc->next_size);
-  rc->nW = load_agent(&dc->low_size);
+  rc->nF = dc->next_size;
+  rc->nW = dc->low_size;
   rc->selF ^= 1u;
   if (rc->finished > rc->n_r) {
     rc->err |= kErrBucket;
@@ -965,7 +946,10 @@ __global__ __launch_bounds__(256) void k_expand_bound(PeelArgs base, RoundCtl *r
 }
 
 template <int R>
-__global__ __launch_bounds__(256) void k_expand(PeelArgs base, RoundCtl *rc, FastView fx,
+// 8 waves per SIMD: the pass is a chain of dependent loads per wave, and the
+// occupancy hides them (measured ~2% of a rMAT-18 (3,4) decomposition over
+// the default 6)
+__global__ __launch_bounds__(256, 8) void k_expand(PeelArgs base, RoundCtl *rc, FastView fx,
                                                 const ExpandDesc *__restrict__ desc,
                                                 const uint64_t *__restrict__ off,
                                                 const uint32_t *__restrict__ len,
@@ -1171,10 +1155,11 @@ __global__ __launch_bounds__(256) void k_apply(PeelArgs base, const RoundCtl *__
 // (measured: 5 waves 391 ms, 6 waves 376 ms, 8 waves with spills 434 ms per
 // rMAT-18 (3,4) decomposition).  Other r keep the default (their larger
 // subset arrays would spill).
-// It also ends the round: the frontier's triangles leave the liveness
-// bitmaps and frontier marks (no pass of the round reads them after expand),
-// and the block that finishes last does the round's bookkeeping.
-__global__ __launch_bounds__(256, 6) void k_apply3(PeelArgs base, RoundCtl *rc,
+// It also retires the frontier: its triangles leave the liveness bitmaps and
+// frontier marks (no pass of the round reads them after expand).  The
+// round's bookkeeping stays in k_round_end: a block-arrival counter over
+// this kernel's thousands of blocks cost more than the launch it saves.
+__global__ __launch_bounds__(256, 6) void k_apply3(PeelArgs base, const RoundCtl *rc,
                                                    const int2 *__restrict__ rec,
                                                    const int32_t *__restrict__ fv, FastView fx,
                                                    const uint64_t *__restrict__ loc,
@@ -1188,7 +1173,6 @@ __global__ __launch_bounds__(256, 6) void k_apply3(PeelArgs base, RoundCtl *rc,
   for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < nF;
        it += (int64_t)gridDim.x * blockDim.x)
     front_bits_one<false>(base.g, base.T.v1, fx, loc, F[it]);
-  if (block_arrive_last(&rc->arrive)) round_end_body(rc, base.ctr);
 }
 
 // Direct count, one wave per r-clique (r >= 3): the part x > v1 is a
@@ -1328,14 +1312,13 @@ __global__ void k_make_loc(GraphView g, TableView T, FastView fx, uint64_t n_slo
 // One round is queued as
 //   k_adv_min, k_adv_partition
 //       level advance; they act only when the round starts with an empty
-//       frontier (B.next_bucket of Algorithm 2).  The partition's last block
-//       finishes the advance and sets up the round (round_begin_body); when
-//       the host knows the frontier is not empty it queues k_round_begin
-//       alone instead;
+//       frontier (B.next_bucket of Algorithm 2);
+//   k_round_begin            one thread: finishes an advance (or drops a
+//                            window list of peeled entries), then the
+//                            round's lists and counters;
 //   the update passes of the path (the first one stamps A_t with t);
 //   k_round_end              one thread: trace, finished += |A_t|, next
-//                            frontier (for r = 3 on the s = r+1 path the
-//                            update pass's last block does this).
+//                            frontier.
 // Every kernel returns at once once the peel has finished or halted, so the
 // host may queue rounds past the last one and read the state only now and
 // then.
@@ -1373,8 +1356,7 @@ __global__ __launch_bounds__(256) void k_adv_min(RoundCtl *rc, const Slot *__res
 // opened the high list is split.  Each block compacts a tile of 256 x 16
 // entries with one atomic per output per tile (a single global counter per
 // wave would serialise in L2).  With mark (r = 3 on the s = r+1 path) the
-// new frontier's triangles get their frontier marks.  Runs in every round:
-// the last block to finish sets the round up.
+// new frontier's triangles get their frontier marks.
 constexpr int kPartThreads = 256;
 constexpr int kPartItems = 16;
 
@@ -1448,13 +1430,13 @@ __device__ __forceinline__ void partition_body(RoundCtl *rc, const Slot *__restr
 }
 
 __global__ __launch_bounds__(kPartThreads) void k_adv_partition(
-    RoundCtl *rc, const Slot *__restrict__ slots, Counters *dc, bool mark, GraphView g,
+    RoundCtl *rc, const Slot *__restrict__ slots, bool mark, GraphView g,
     const int32_t *__restrict__ v1s, FastView fx, const uint64_t *__restrict__ loc) {
-  if (rc_idle(rc)) return;
+  if (rc_idle(rc) || rc->nF != 0) return;
   const bool win = rc->nW != 0;
   const uint32_t mn = win ? rc->mw : rc->mh;
-  if (rc->nF == 0 && mn != kNone) partition_body(rc, slots, win, mn, mark, g, v1s, fx, loc);
-  if (block_arrive_last(&rc->arrive)) round_begin_body(rc, dc);
+  if (mn == kNone) return;  // round_begin_body drops the window or reports the error
+  partition_body(rc, slots, win, mn, mark, g, v1s, fx, loc);
 }
 
 __global__ void k_round_begin(RoundCtl *rc, Counters *dc) {
@@ -1866,8 +1848,7 @@ void enqueue_round(Engine &E, const RoundCtl &m, bool exact, hipEvent_t e0, hipE
                    hipEvent_t e_adv) {
   const hipStream_t st = E.st;
   RoundCtl *rc = E.rc.get();
-  // r = 3 on the s = r+1 path: frontier marks at selection, round end in
-  // the update pass
+  // r = 3 on the s = r+1 path: frontier marks at selection
   const bool r3 = E.path == 1 && E.r == 3;
   if (!exact || m.nF == 0) {
     // queued behind other rounds these act only now and then: small grids
@@ -1876,12 +1857,10 @@ void enqueue_round(Engine &E, const RoundCtl &m, bool exact, hipEvent_t e0, hipE
     hipLaunchKernelGGL(k_adv_min, blocks_for(nl, 256 * 8, 1, cap_b), dim3(256), 0, st, rc,
                        E.T.slots);
     hipLaunchKernelGGL(k_adv_partition, blocks_for(nl, kPartThreads * kPartItems, 1, cap_b),
-                       dim3(kPartThreads), 0, st, rc, E.T.slots, E.dc, r3, E.gv, E.T.v1, E.fxv,
-                       E.loc);
-  } else {
-    hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, st, rc, E.dc);
+                       dim3(kPartThreads), 0, st, rc, E.T.slots, r3, E.gv, E.T.v1, E.fxv, E.loc);
   }
   if (e_adv) hipEventRecord(e_adv, st);
+  hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, st, rc, E.dc);
   // Grids: sized to the frontier when it is known (nothing in flight and no
   // level advance), otherwise wide enough to fill the chip, so that a large
   // round queued behind small ones never runs on a small grid.
@@ -1921,7 +1900,7 @@ void enqueue_round(Engine &E, const RoundCtl &m, bool exact, hipEvent_t e0, hipE
       default: break;
     }
   }
-  if (!r3) hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, st, rc, E.dc);
+  hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, st, rc, E.dc);
 }
 
 template <class T>

@@ -263,9 +263,10 @@ void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_
   scan_impl<uint32_t>(in, out, n, st);
 }
 
-void radix_sort(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t st) {
-  if (n <= 1 || bits <= 0) return;
-  int passes = (bits + 7) / 8;
+void radix_sort(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t st,
+                int lo_bit) {
+  if (n <= 1 || bits <= lo_bit) return;
+  int passes = (bits - lo_bit + 7) / 8;
   int64_t nb = (n + kSortTile - 1) / kSortTile;
   DevBuf<uint64_t> k2((size_t)n);
   DevBuf<uint32_t> v2(vals ? (size_t)n : 0);
@@ -273,7 +274,7 @@ void radix_sort(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t
   uint64_t *ks = keys, *kd = k2.get();
   uint32_t *vs = vals, *vd = v2.get();
   for (int p = 0; p < passes; p++) {
-    int shift = 8 * p;
+    int shift = lo_bit + 8 * p;
     hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(kWave), 0, st, ks, n, shift,
                        hist.get(), nb);
     scan_exclusive_u32(hist.get(), hist.get(), 256 * nb, st);
