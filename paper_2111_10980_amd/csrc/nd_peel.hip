@@ -53,8 +53,8 @@ struct PeelArgs {
   uint32_t *Low;              // r-cliques whose count fell to kw (window list)
 };
 
-struct LaneStats {
-  uint64_t dec = 0, disc = 0, atom = 0;
+struct LaneStats {  // per lane and launch: far below 2^32
+  uint32_t dec = 0, disc = 0, atom = 0;
   uint32_t err = 0;
 };
 
@@ -211,10 +211,15 @@ __device__ __forceinline__ void update_func(const PeelArgs &a, const int32_t (&S
     if (cb.mask[q] == rmask) self = q;
   bool alive = active;
   bool other_owner = false;
-  bool live[N];
+  // hot: live (not peeled) and its count read above the level.  A count read
+  // at or below the level has crossed k+1 (and the window level) already:
+  // its decrement changes nothing after the clamp to k and needs no atomic,
+  // but it is still one of the decrements Algorithm 2 applies (n_live).
+  bool hot[N];
+  uint32_t n_live = 0;
 #pragma unroll
   for (int q = 0; q < N; q++) {
-    live[q] = false;
+    hot[q] = false;
     if (!want[q]) continue;
     if (pos[q] < 0) {
       ls.err |= kErrLookup;
@@ -224,25 +229,22 @@ __device__ __forceinline__ void update_func(const PeelArgs &a, const int32_t (&S
     } else if (sl[q].stamp == a.t) {
       other_owner = other_owner || q < self;  // peeled with R and first in order
     } else {
-      live[q] = true;
+      n_live++;
+      hot[q] = sl[q].cnt > a.k;
     }
   }
   if (active) ls.disc++;
   const bool mine = alive && !other_owner;
+  if (mine) ls.dec += n_live;
 #pragma unroll
   for (int q = 0; q < N; q++) {
     bool want_append = false, want_low = false;
-    if (mine && live[q]) {
-      ls.dec++;
-      // a count read at or below the level has crossed k+1 (and the window
-      // level) already: its decrement changes nothing after the clamp to k
-      if (sl[q].cnt > a.k) {
-        uint32_t old = __hip_atomic_fetch_add(&a.T.slots[pos[q]].cnt, 0xFFFFFFFFu,
-                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ls.atom++;
-        want_append = old == a.k + 1;              // reaches this round's level
-        want_low = a.kw > a.k && old == a.kw + 1;  // enters the level window
-      }
+    if (mine && hot[q]) {
+      uint32_t old = __hip_atomic_fetch_add(&a.T.slots[pos[q]].cnt, 0xFFFFFFFFu, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+      ls.atom++;
+      want_append = old == a.k + 1;              // reaches this round's level
+      want_low = a.kw > a.k && old == a.kw + 1;  // enters the level window
     }
     if constexpr (kConvergent) {
       ap[0].push(want_append, (uint32_t)pos[q]);
@@ -725,10 +727,11 @@ __device__ __forceinline__ void update_r3_ranked(const PeelArgs &a, const FastVi
     }
   }
   Slot sl[4];
-  bool alive = active, other_owner = false, live[4];
+  bool alive = active, other_owner = false, hot[4];  // as in update_func
+  uint32_t n_live = 0;
 #pragma unroll
   for (int q = 0; q < 4; q++) {
-    live[q] = false;
+    hot[q] = false;
     if (!want[q]) continue;
     if (pos[q] < 0) {
       ls.err |= kErrLookup;
@@ -745,23 +748,22 @@ __device__ __forceinline__ void update_r3_ranked(const PeelArgs &a, const FastVi
     } else if (sl[q].stamp == a.t) {
       other_owner = other_owner || q < self;  // peeled with R and first in order
     } else {
-      live[q] = true;
+      n_live++;
+      hot[q] = sl[q].cnt > a.k;
     }
   }
   if (active) ls.disc++;
   const bool mine = alive && !other_owner;
+  if (mine) ls.dec += n_live;
 #pragma unroll
   for (int q = 0; q < 4; q++) {
     bool want_append = false, want_low = false;
-    if (mine && live[q]) {
-      ls.dec++;
-      if (sl[q].cnt > a.k) {  // else crossed already: see update_func
-        const uint32_t old = __hip_atomic_fetch_add(&a.T.slots[pos[q]].cnt, 0xFFFFFFFFu,
-                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ls.atom++;
-        want_append = old == a.k + 1;
-        want_low = a.kw > a.k && old == a.kw + 1;
-      }
+    if (mine && hot[q]) {
+      const uint32_t old = __hip_atomic_fetch_add(&a.T.slots[pos[q]].cnt, 0xFFFFFFFFu,
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ls.atom++;
+      want_append = old == a.k + 1;
+      want_low = a.kw > a.k && old == a.kw + 1;
     }
     apf.push(want_append, (uint32_t)pos[q]);
     apl.push(want_low, (uint32_t)pos[q]);
@@ -1138,8 +1140,12 @@ __device__ __forceinline__ void apply_body(const PeelArgs &base, const RoundCtl 
   if (ls.err) atomicOr(&a.ctr->err, ls.err);
 }
 
+// r = 4: at least 4 waves per SIMD (128 registers, a few spilled; without
+// the bound the compiler takes 133 and 3 waves, ~60 ms slower per Chung-Lu
+// 1M (4,5) decomposition).  r = 5, 6 keep the default (the bound spills
+// their larger subset arrays).
 template <int R>
-__global__ __launch_bounds__(256) void k_apply(PeelArgs base, const RoundCtl *__restrict__ rc,
+__global__ __launch_bounds__(256, R == 4 ? 4 : 1) void k_apply(PeelArgs base, const RoundCtl *__restrict__ rc,
                                                const int2 *__restrict__ rec,
                                                const int32_t *__restrict__ fv, FastView fx,
                                                const uint64_t *__restrict__ loc,
