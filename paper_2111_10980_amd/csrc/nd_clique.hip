@@ -316,7 +316,14 @@ struct ApexOp {
       if (g.col[mid] < z) lo = mid + 1;
       else hi = mid;
     }
-    unsigned long long at = atomicAdd(&cursor[Sv[0]], 1ull);
+    // the wave lists one root at a time (Sv[0] is wave-uniform): one atomic
+    // per call reserves the active lanes' places, in lane order
+    const uint64_t m = __ballot(1);
+    const int first = __ffsll((unsigned long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane_id() == first) base = atomicAdd(&cursor[Sv[0]], (unsigned long long)__popcll(m));
+    base = __shfl(base, first);
+    const unsigned long long at = base + (unsigned long long)__popcll(m & lanes_below());
     keys[at] = ((uint64_t)lo << xbits) | (uint64_t)(uint32_t)Sv[0];
   }
   __device__ void lane_finish(Lane &) const {}
