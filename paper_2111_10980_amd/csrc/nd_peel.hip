@@ -1269,6 +1269,74 @@ __global__ __launch_bounds__(256) void k_count_wave(PeelArgs a, FastView fx,
   }
 }
 
+// r = 3 direct count with 16-lane groups, four triangles per wave: the
+// bitmap part needs at most 8 lanes (d <= 512) and most apex lists are short,
+// so a whole wave per triangle leaves most lanes idle.  Same steps as
+// k_count_wave; the other apex list is staged in the group's LDS share.
+constexpr int kCountGroup = 16;
+constexpr int kGroupList = kListCap * kCountGroup / kWave;
+
+__global__ __launch_bounds__(256) void k_count_group3(PeelArgs a, FastView fx,
+                                                      const uint64_t *__restrict__ loc,
+                                                      const uint32_t *__restrict__ occ,
+                                                      uint64_t n_r) {
+  constexpr int G = kCountGroup;
+  const int gpb = blockDim.x / G;
+  const int gi = threadIdx.x / G;
+  const int gl = threadIdx.x % G;
+  __shared__ int32_t lbuf[256 / G][kGroupList];
+  for (int64_t it = (int64_t)blockIdx.x * gpb + gi; it < (int64_t)n_r;
+       it += (int64_t)gridDim.x * gpb) {  // group-uniform
+    const uint32_t p = occ[it];
+    const Slot sl = a.T.slots[p];
+    int32_t Rv[3];
+    Rv[0] = a.T.v1[p];
+    decode_key<3>(sl.key, a.T.bits, Rv);
+    const int64_t o = a.g.up[Rv[0]];
+    const int d = (int)(a.g.rp[Rv[0] + 1] - o);
+    int64_t e[3];
+    if (!front_positions<3>(a, loc[p], Rv, o, d, e)) {  // group-uniform
+      if (gl == 0) atomicOr(&a.ctr->err, kErrLookup);
+      continue;
+    }
+    uint32_t c = 0;
+    if (d <= 512) {
+      const int wd = (d + 63) >> 6;
+      const uint64_t *rows = fx.bm + fx.bm_off[Rv[0]];
+      if (gl < wd)
+        c = (uint32_t)__popcll(rows[(e[1] - o) * wd + gl] & rows[(e[2] - o) * wd + gl]);
+    } else {
+      for (int64_t j = o + gl; j < o + d; j += G) {
+        const int32_t y = a.g.col[j];
+        c += adjacent(a.g, y, Rv[1]) && adjacent(a.g, y, Rv[2]) ? 1u : 0u;
+      }
+    }
+    const uint64_t len1 = fx.lptr[e[1] + 1] - fx.lptr[e[1]];
+    const uint64_t lenb = fx.lptr[e[2] + 1] - fx.lptr[e[2]];
+    const int drv = lenb < len1 ? 2 : 1, other = 3 - drv;
+    const uint64_t len2 = drv == 1 ? len1 : lenb;
+    const uint64_t lb = fx.lptr[e[drv]];
+    const uint64_t ob = fx.lptr[e[other]], oe = fx.lptr[e[other] + 1];
+    int staged_len = -1;
+    if (len2 > 0 && oe - ob <= (uint64_t)kGroupList) {
+      staged_len = (int)(oe - ob);
+      for (int i = gl; i < staged_len; i += G) lbuf[gi][i] = fx.lval[ob + i];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+    for (uint64_t j = gl; j < len2; j += G) {
+      const int32_t x = fx.lval[lb + j];
+      const bool in = staged_len >= 0 ? lds_contains(lbuf[gi], staged_len, x)
+                                      : sorted_contains(fx.lval, ob, oe, x);
+      c += in ? 1u : 0u;
+    }
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if (gl == 0) a.T.slots[p].cnt = c;
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 // Local indices of v2..vr in N+(v1) for every occupied slot of a bitmap
 // root (9 bits each, bit 63 marks them valid).  For r = 3 bits 18..61 also
 // hold 1 + the position of the triangle's apex entry (v1 in the list of the
@@ -2132,7 +2200,10 @@ void count_direct(const OrientedGraph &g, int r, const TableView &T, const FastI
   const uint64_t *loc = fx.loc.get();
   dim3 grid((unsigned)grid_for(n_r, 4, 1 << 20)), blk(256);
   switch (r) {
-    case 3: hipLaunchKernelGGL(k_count_wave<3>, grid, blk, 0, st, a, fv, loc, occ, n_r); break;
+    case 3:
+      hipLaunchKernelGGL(k_count_group3, dim3((unsigned)grid_for(n_r, 256 / kCountGroup, 1 << 20)),
+                         blk, 0, st, a, fv, loc, occ, n_r);
+      break;
     case 4: hipLaunchKernelGGL(k_count_wave<4>, grid, blk, 0, st, a, fv, loc, occ, n_r); break;
     case 5: hipLaunchKernelGGL(k_count_wave<5>, grid, blk, 0, st, a, fv, loc, occ, n_r); break;
     case 6: hipLaunchKernelGGL(k_count_wave<6>, grid, blk, 0, st, a, fv, loc, occ, n_r); break;
