@@ -1269,11 +1269,14 @@ __global__ __launch_bounds__(256) void k_count_wave(PeelArgs a, FastView fx,
   }
 }
 
-// r = 3 direct count with 16-lane groups, four triangles per wave: the
+// r = 3 direct count with 8-lane groups, eight triangles per wave: the
 // bitmap part needs at most 8 lanes (d <= 512) and most apex lists are short,
-// so a whole wave per triangle leaves most lanes idle.  Same steps as
+// so a whole wave per triangle leaves most lanes idle (measured on rMAT-18:
+// 50 ms with a wave, 32 ms with 16 lanes, 30 ms with 8).  Same steps as
 // k_count_wave; the other apex list is staged in the group's LDS share.
-constexpr int kCountGroup = 16;
+// (The expand pass keeps a whole wave per r-clique: its record loop ran
+// slower with 32 or 16 lanes.)
+constexpr int kCountGroup = 8;
 constexpr int kGroupList = kListCap * kCountGroup / kWave;
 
 __global__ __launch_bounds__(256) void k_count_group3(PeelArgs a, FastView fx,
