@@ -140,7 +140,7 @@ def main():
     # peels through k_gen_apply and counts by listing; (1,2) uses k_peel
     if s == r + 1 and r >= 2:
         peel_name = "k_apply3" if r == 3 else f"k_apply<{r}>"
-        count_name = "k_count_direct<2>" if r == 2 else f"k_count_wave<{r}>"
+        count_name = "k_count_direct<2>" if r == 2 else f"k_count_group<{r}>"
     else:
         peel_name = f"k_gen_apply<{r}, {s}>" if s >= r + 2 else f"k_peel<{r}, {s}>"
         count_name = f"k_list_bitmap<{s}, W, CountOp<{r}, {s}>>"

@@ -1181,20 +1181,30 @@ __global__ __launch_bounds__(256, 6) void k_apply3(PeelArgs base, const RoundCtl
     front_bits_one<false>(base.g, base.T.v1, fx, loc, F[it]);
 }
 
-// Direct count, one wave per r-clique (r >= 3): the part x > v1 is a
-// popcount of the AND of v1's bitmap rows; the part x < v1 is the
-// intersection of the apex lists, the shortest one split across the lanes
-// and the other (r = 3) staged in LDS.
+// Direct count, 8 lanes per r-clique (r >= 3), eight r-cliques per wave: the
+// part x > v1 is a popcount of the AND of v1's bitmap rows (at most 8 words,
+// d <= 512); the part x < v1 is the intersection of the apex lists, the
+// shortest one split across the group's lanes and, for r = 3, the other one
+// staged in the group's LDS share.  Most apex lists are short, so a whole
+// wave per r-clique left most lanes idle (measured on rMAT-18 (3,4): 50 ms
+// with a wave, 32 ms with 16 lanes, 30 ms with 8).
+// (The expand pass keeps a whole wave per r-clique: its record loop ran
+// slower with 32 or 16 lanes.)
+constexpr int kCountGroup = 8;
+constexpr int kGroupList = kListCap * kCountGroup / kWave;
+
 template <int R>
-__global__ __launch_bounds__(256) void k_count_wave(PeelArgs a, FastView fx,
-                                                    const uint64_t *__restrict__ loc,
-                                                    const uint32_t *__restrict__ occ, uint64_t n_r) {
-  const int wpb = blockDim.x / kWave;
-  const int wv = threadIdx.x / kWave;
-  const int lane = lane_id();
-  __shared__ int32_t lbuf[256 / kWave][R == 3 ? kListCap : 1];
-  for (int64_t it = (int64_t)blockIdx.x * wpb + wv; it < (int64_t)n_r;
-       it += (int64_t)gridDim.x * wpb) {
+__global__ __launch_bounds__(256) void k_count_group(PeelArgs a, FastView fx,
+                                                     const uint64_t *__restrict__ loc,
+                                                     const uint32_t *__restrict__ occ,
+                                                     uint64_t n_r) {
+  constexpr int G = kCountGroup;
+  const int gpb = blockDim.x / G;
+  const int gi = threadIdx.x / G;
+  const int gl = threadIdx.x % G;
+  __shared__ int32_t lbuf[256 / G][R == 3 ? kGroupList : 1];
+  for (int64_t it = (int64_t)blockIdx.x * gpb + gi; it < (int64_t)n_r;
+       it += (int64_t)gridDim.x * gpb) {  // group-uniform
     const uint32_t p = occ[it];
     const Slot sl = a.T.slots[p];
     int32_t Rv[R];
@@ -1203,22 +1213,22 @@ __global__ __launch_bounds__(256) void k_count_wave(PeelArgs a, FastView fx,
     const int64_t o = a.g.up[Rv[0]];
     const int d = (int)(a.g.rp[Rv[0] + 1] - o);
     int64_t e[R];
-    if (!front_positions<R>(a, loc[p], Rv, o, d, e)) {  // wave-uniform
-      if (lane == 0) atomicOr(&a.ctr->err, kErrLookup);
+    if (!front_positions<R>(a, loc[p], Rv, o, d, e)) {  // group-uniform
+      if (gl == 0) atomicOr(&a.ctr->err, kErrLookup);
       continue;
     }
     uint32_t c = 0;
     if (d <= 512) {
       const int wd = (d + 63) >> 6;
       const uint64_t *rows = fx.bm + fx.bm_off[Rv[0]];
-      if (lane < wd) {
+      if (gl < wd) {
         uint64_t x = ~0ull;
 #pragma unroll
-        for (int i = 1; i < R; i++) x &= rows[(e[i] - o) * wd + lane];
+        for (int i = 1; i < R; i++) x &= rows[(e[i] - o) * wd + gl];
         c = (uint32_t)__popcll(x);
       }
     } else {
-      for (int64_t j = o + lane; j < o + d; j += kWave) {
+      for (int64_t j = o + gl; j < o + d; j += G) {
         const int32_t y = a.g.col[j];
         bool ok = true;
 #pragma unroll
@@ -1240,97 +1250,27 @@ __global__ __launch_bounds__(256) void k_count_wave(PeelArgs a, FastView fx,
     int staged_len = -1;
     uint64_t ob = 0, oe = 0;
     if constexpr (R == 3) {
-      const int other = drv == 1 ? 2 : 1;
+      const int other = 3 - drv;
       ob = fx.lptr[e[other]];
       oe = fx.lptr[e[other] + 1];
-      if (len2 > 0 && oe - ob <= (uint64_t)kListCap) {
+      if (len2 > 0 && oe - ob <= (uint64_t)kGroupList) {
         staged_len = (int)(oe - ob);
-        for (int i = lane; i < staged_len; i += kWave) lbuf[wv][i] = fx.lval[ob + i];
+        for (int i = gl; i < staged_len; i += G) lbuf[gi][i] = fx.lval[ob + i];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
       }
     }
-    for (uint64_t j = lane; j < len2; j += kWave) {
+    for (uint64_t j = gl; j < len2; j += G) {
       const int32_t x = fx.lval[lb + j];
       bool in = true;
       if constexpr (R == 3) {
-        in = staged_len >= 0 ? lds_contains(lbuf[wv], staged_len, x)
+        in = staged_len >= 0 ? lds_contains(lbuf[gi], staged_len, x)
                              : sorted_contains(fx.lval, ob, oe, x);
       } else {
 #pragma unroll
         for (int i = 1; i < R; i++)
           if (i != drv) in = in && sorted_contains(fx.lval, fx.lptr[e[i]], fx.lptr[e[i] + 1], x);
       }
-      c += in ? 1u : 0u;
-    }
-    const uint64_t total = wave_sum_u64(c);
-    if (lane == 0) a.T.slots[p].cnt = (uint32_t)total;
-    __builtin_amdgcn_wave_barrier();
-  }
-}
-
-// r = 3 direct count with 8-lane groups, eight triangles per wave: the
-// bitmap part needs at most 8 lanes (d <= 512) and most apex lists are short,
-// so a whole wave per triangle leaves most lanes idle (measured on rMAT-18:
-// 50 ms with a wave, 32 ms with 16 lanes, 30 ms with 8).  Same steps as
-// k_count_wave; the other apex list is staged in the group's LDS share.
-// (The expand pass keeps a whole wave per r-clique: its record loop ran
-// slower with 32 or 16 lanes.)
-constexpr int kCountGroup = 8;
-constexpr int kGroupList = kListCap * kCountGroup / kWave;
-
-__global__ __launch_bounds__(256) void k_count_group3(PeelArgs a, FastView fx,
-                                                      const uint64_t *__restrict__ loc,
-                                                      const uint32_t *__restrict__ occ,
-                                                      uint64_t n_r) {
-  constexpr int G = kCountGroup;
-  const int gpb = blockDim.x / G;
-  const int gi = threadIdx.x / G;
-  const int gl = threadIdx.x % G;
-  __shared__ int32_t lbuf[256 / G][kGroupList];
-  for (int64_t it = (int64_t)blockIdx.x * gpb + gi; it < (int64_t)n_r;
-       it += (int64_t)gridDim.x * gpb) {  // group-uniform
-    const uint32_t p = occ[it];
-    const Slot sl = a.T.slots[p];
-    int32_t Rv[3];
-    Rv[0] = a.T.v1[p];
-    decode_key<3>(sl.key, a.T.bits, Rv);
-    const int64_t o = a.g.up[Rv[0]];
-    const int d = (int)(a.g.rp[Rv[0] + 1] - o);
-    int64_t e[3];
-    if (!front_positions<3>(a, loc[p], Rv, o, d, e)) {  // group-uniform
-      if (gl == 0) atomicOr(&a.ctr->err, kErrLookup);
-      continue;
-    }
-    uint32_t c = 0;
-    if (d <= 512) {
-      const int wd = (d + 63) >> 6;
-      const uint64_t *rows = fx.bm + fx.bm_off[Rv[0]];
-      if (gl < wd)
-        c = (uint32_t)__popcll(rows[(e[1] - o) * wd + gl] & rows[(e[2] - o) * wd + gl]);
-    } else {
-      for (int64_t j = o + gl; j < o + d; j += G) {
-        const int32_t y = a.g.col[j];
-        c += adjacent(a.g, y, Rv[1]) && adjacent(a.g, y, Rv[2]) ? 1u : 0u;
-      }
-    }
-    const uint64_t len1 = fx.lptr[e[1] + 1] - fx.lptr[e[1]];
-    const uint64_t lenb = fx.lptr[e[2] + 1] - fx.lptr[e[2]];
-    const int drv = lenb < len1 ? 2 : 1, other = 3 - drv;
-    const uint64_t len2 = drv == 1 ? len1 : lenb;
-    const uint64_t lb = fx.lptr[e[drv]];
-    const uint64_t ob = fx.lptr[e[other]], oe = fx.lptr[e[other] + 1];
-    int staged_len = -1;
-    if (len2 > 0 && oe - ob <= (uint64_t)kGroupList) {
-      staged_len = (int)(oe - ob);
-      for (int i = gl; i < staged_len; i += G) lbuf[gi][i] = fx.lval[ob + i];
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-    }
-    for (uint64_t j = gl; j < len2; j += G) {
-      const int32_t x = fx.lval[lb + j];
-      const bool in = staged_len >= 0 ? lds_contains(lbuf[gi], staged_len, x)
-                                      : sorted_contains(fx.lval, ob, oe, x);
       c += in ? 1u : 0u;
     }
 #pragma unroll
@@ -2201,15 +2141,12 @@ void count_direct(const OrientedGraph &g, int r, const TableView &T, const FastI
   }
   PeelArgs a{gv, T, 0u, 0u, nullptr, dctr, nullptr, 0u, nullptr};
   const uint64_t *loc = fx.loc.get();
-  dim3 grid((unsigned)grid_for(n_r, 4, 1 << 20)), blk(256);
+  dim3 gg((unsigned)grid_for(n_r, 256 / kCountGroup, 1 << 20)), blk(256);
   switch (r) {
-    case 3:
-      hipLaunchKernelGGL(k_count_group3, dim3((unsigned)grid_for(n_r, 256 / kCountGroup, 1 << 20)),
-                         blk, 0, st, a, fv, loc, occ, n_r);
-      break;
-    case 4: hipLaunchKernelGGL(k_count_wave<4>, grid, blk, 0, st, a, fv, loc, occ, n_r); break;
-    case 5: hipLaunchKernelGGL(k_count_wave<5>, grid, blk, 0, st, a, fv, loc, occ, n_r); break;
-    case 6: hipLaunchKernelGGL(k_count_wave<6>, grid, blk, 0, st, a, fv, loc, occ, n_r); break;
+    case 3: hipLaunchKernelGGL(k_count_group<3>, gg, blk, 0, st, a, fv, loc, occ, n_r); break;
+    case 4: hipLaunchKernelGGL(k_count_group<4>, gg, blk, 0, st, a, fv, loc, occ, n_r); break;
+    case 5: hipLaunchKernelGGL(k_count_group<5>, gg, blk, 0, st, a, fv, loc, occ, n_r); break;
+    case 6: hipLaunchKernelGGL(k_count_group<6>, gg, blk, 0, st, a, fv, loc, occ, n_r); break;
     default: break;
   }
 }
