@@ -192,6 +192,33 @@ def test_disjoint_cliques():
     check_against_oracle(g, 3, 4)
 
 
+def _tree(arity, depth):
+    """Complete arity-ary tree: internal vertices have degree arity + 1."""
+    u, v, nxt, level = [], [], 1, [0]
+    for _ in range(depth):
+        new = []
+        for p in level:
+            for _ in range(arity):
+                u.append(p)
+                v.append(nxt)
+                new.append(nxt)
+                nxt += 1
+        level = new
+    return inputs.csr_from_edges(nxt, np.array(u), np.array(v))
+
+
+@pytest.mark.parametrize("generic", [False, True])
+def test_window_of_peeled_entries_dropped(generic):
+    """(1,2) on a 9-ary tree beside K_21: the first level advance puts the
+    tree's internal vertices (degree 10) in the level window and K_21
+    (degree 20) above it; all of the tree peels at level 1, so the next
+    advance finds a window list that holds only peeled entries and must drop
+    it (an empty round, not counted) before it reaches the clique's level."""
+    g = inputs.disjoint_union([_tree(9, 3), inputs.complete_graph(21)])
+    d = check_against_oracle(g, 1, 2, generic=generic)
+    assert list(np.unique(d.round_levels)) == [1, 20]
+
+
 def test_empty_and_isolated():
     nd = _nd()
     g = inputs.csr_from_edges(10, [], [])
