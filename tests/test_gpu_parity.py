@@ -55,6 +55,10 @@ def check_against_oracle(g, r, s, **kw):
     np.testing.assert_array_equal(d.round_sizes, ref.round_sizes)
     np.testing.assert_array_equal(d.round_levels.astype(np.uint64), ref.round_k)
     assert d.stats["decrements"] == ref.decrements
+    # a decrement of a count already at the level needs no atomic; the first
+    # decrement of any count in a round always does
+    assert d.stats["atomics"] <= d.stats["decrements"]
+    assert (d.stats["atomics"] > 0) == (d.stats["decrements"] > 0)
     return d
 
 
