@@ -11,9 +11,15 @@ updates and value = n_s / (seconds per step).
 Prints ONE JSON line.  Besides the driver's fields it carries
   roofline      the dominant kernel's algorithmic HBM bytes / its measured
                 time (HIP events on the library's stream over the timed
-                steps) against the MI355X HBM peak;
-  cpu_baseline  the CPU oracle (single thread) timed on a bounded sample of
-                the same graph family (rMAT scale 12, same a..d).
+                steps) against the MI355X HBM peak, plus the access-pattern
+                roofline T_roof = max(stream bytes / copy rate, probes /
+                random-gather rate, atomics / random-atomic rate) with the
+                three ceilings measured in the same run;
+  cpu_baseline  the CPU oracle (single thread) timed in this run on a bounded
+                sample of the same graph family (rMAT scale 12, same a..d),
+                with the host's core count and CPU model; next to it the
+                oracle's stored run on the full input itself (same SHA-256)
+                from tests/golden/, with the host it ran on.
 """
 import argparse
 import json
@@ -48,6 +54,35 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def host_cpu():
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, check=True).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, ValueError, RuntimeError):
+        pass
+    return "unknown"
+
+
+def full_oracle_run(workload, input_sha):
+    """The oracle's stored run on the full input (tests/golden/), if it is
+    the same input."""
+    path = os.path.join(ROOT, "tests", "golden", f"fullsize_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("input_sha256") != input_sha:
+        return None
+    return {"value": rec["n_s"] / rec["oracle_wall_s"], "unit": "s-clique peel updates/s",
+            "cores": rec["oracle_threads"], "kind": "oracle", "wall_s": rec["oracle_wall_s"],
+            "input_sha256": input_sha, "host_cpu": rec["host_cpu"],
+            "host_nproc": rec["host_nproc"],
+            "sample": f"the whole {workload} input (n_s={rec['n_s']}), validation + table + "
+                      f"count + peel, one thread, stored by {rec['script']}"}
+
+
 def cpu_baseline(r, s, scale=12, seed=18):
     """The oracle as it stands, single-threaded, on rMAT scale `scale`."""
     from oracle import oracle
@@ -57,9 +92,10 @@ def cpu_baseline(r, s, scale=12, seed=18):
     res = oracle.decompose(g.n, g.row_ptr, g.col, r, s)
     dt = time.perf_counter() - t0
     return {"value": res.n_s / dt, "unit": "s-clique peel updates/s", "cores": 1,
-            "kind": "oracle",
+            "kind": "oracle", "host_cpu": host_cpu(), "host_nproc": os.cpu_count(),
             "sample": f"rMAT scale {scale} edge factor 16 (same a..d, seed {seed}; n={g.n}, "
-                      f"m={g.m}, n_s={res.n_s}), ({r},{s}), count+peel, {dt:.2f} s"}
+                      f"m={g.m}, n_s={res.n_s}), ({r},{s}), validation + table + count + peel, "
+                      f"{dt:.2f} s"}
 
 
 def main():
@@ -161,8 +197,13 @@ def main():
     # probes its C(s,r)-1 other slots; every decrement of a count still above
     # the level is a returning atomic
     probes = st["discoveries"] * (c - 1)
-    model_ms = 1000.0 * (probes / (ceil["gather16_gops"] * 1e9) +
-                         st["atomics"] / (ceil["atomic_ret_gops"] * 1e9))
+    t_probe = probes / (ceil["gather16_gops"] * 1e9)
+    t_atom = st["atomics"] / (ceil["atomic_ret_gops"] * 1e9)
+    t_stream = (nbytes / n_launch) * (launches / len(runs)) / (ceil["copy_gbs"] * 1e9)
+    # the access-pattern roofline: the slowest of the three ceilings bounds
+    # the pass; the serial figure adds probes and atomics (no overlap)
+    roof_ms = 1000.0 * max(t_stream, t_probe, t_atom)
+    model_ms = 1000.0 * (t_probe + t_atom)
     peel_step_ms = peel_ms / len(runs)
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"traffic_{kern.split('<')[0]}_{args.workload}.json")
@@ -179,16 +220,26 @@ def main():
                 "count_kernel_ms_per_step": round(cnt_ms / len(runs), 3),
                 "peel_kernel_ms_per_step": round(peel_ms / len(runs), 3),
                 "measured_ceilings": {k: round(v, 3) for k, v in ceil.items()},
-                "random_access_model": {
+                "access_roofline": {
+                    "formula": "T_roof = max(stream bytes / copy rate, probes / gather rate, "
+                               "atomics / atomic rate); frac = T_roof / T_measured",
                     "probes": probes, "atomics": st["atomics"],
-                    "model_ms": round(model_ms, 2),
-                    "frac": round(model_ms / peel_step_ms, 4) if peel_step_ms > 0 else None}}
+                    "t_stream_ms": round(1000.0 * t_stream, 3),
+                    "t_probe_ms": round(1000.0 * t_probe, 3),
+                    "t_atomic_ms": round(1000.0 * t_atom, 3),
+                    "t_roof_ms": round(roof_ms, 3),
+                    "measured_ms": round(peel_step_ms, 3),
+                    "frac": round(roof_ms / peel_step_ms, 4) if peel_step_ms > 0 else None,
+                    "serial_model_ms": round(model_ms, 2),
+                    "serial_model_frac": round(model_ms / peel_step_ms, 4)
+                    if peel_step_ms > 0 else None}}
 
     base = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on the bounded sample")
         base = cpu_baseline(r, s)
         log(f"[bench] cpu baseline: {base['value']:.4g} {base['unit']} ({base['sample']})")
+        base["full_input"] = full_oracle_run(args.workload, g.sha256())
 
     out = {
         "metric": "s-clique peel updates/sec",

@@ -15,6 +15,10 @@
  * Conventions of every entry point:
  *   - All pointers named *_dev are DEVICE pointers on the current HIP device;
  *     the caller owns them.  Host pointers are named *_host or are structs.
+ *   - Memory: a plan owns its device state (relabeled graph, r-clique table,
+ *     index, round control) until nd_plan_destroy.  Everything a run needs
+ *     beyond that comes from a caller-owned device workspace whose exact size
+ *     nd_plan_sizes reports; nd_run itself allocates nothing.
  *   - Work is enqueued on the stream given at plan creation and runs in
  *     stream order; entry points that return sizes or statistics synchronise
  *     that stream before returning.
@@ -66,6 +70,16 @@ typedef struct {
   int32_t path;          /* 0 = auto; 1 = force the one-wave generic walker (Count-Func
                             atomics; each peeled r-clique's s-cliques listed by one wave
                             with edge tests) for every (r, s) */
+  int32_t canonical;     /* 1 = output rows in lexicographic order of their vertices
+                            (original ids); 0 = library order */
+  uint32_t trace_cap;    /* round-trace capacity the workspace provides at first;
+                            0 = min(n_r, 4096) */
+  uint64_t record_cap;   /* per-round record capacity the workspace provides at first
+                            (s = r+1 and s >= r+2 paths); 0 = max(2 n_r, 2^18) */
+  uint64_t debug_count_bias; /* debug: the 32-bit range check of the initial counts sees
+                                every count raised by this amount, so a bias above
+                                UINT32_MAX - (largest count) makes nd_run return
+                                ND_EOVERFLOW; 0 = off (results are never changed) */
 } nd_options;
 
 typedef struct {
@@ -80,13 +94,17 @@ typedef struct {
   uint32_t max_out_degree; /* of the orientation */
   float ms[8];           /* phase times: 0 validate, 1 orient+relabel, 2 table,
                             3 count, 4 bucket init, 5 peel loop, 6 emit, 7 total */
-  float count_kernel_ms; /* with options.timing: time of the s-clique listing kernels */
-  float peel_kernel_ms;  /* with options.timing: summed time of the peel-round kernels */
+  float count_kernel_ms; /* with options.timing: time of the s-clique count kernels */
+  float peel_kernel_ms;  /* with options.timing: summed time of every round's update
+                            (apply) kernel -- k_apply3 / k_apply / k_gen_apply / k_peel --
+                            alone, not the round's other passes */
   uint32_t count_launches;
-  uint32_t peel_launches;
+  uint32_t peel_launches; /* with options.timing: update kernels timed (one per round) */
   uint64_t atomics;      /* returning atomic decrements issued: a decrement of a count that
                             is already at or below the level (Algorithm 2 clamps it to k)
                             is counted in decrements but needs no memory operation */
+  uint64_t workspace_bytes;   /* workspace bytes the run carved */
+  uint64_t max_round_records; /* largest number of records one peel round wrote */
 } nd_stats;
 
 typedef struct nd_plan_s *nd_plan; /* opaque, library-owned */
@@ -94,27 +112,43 @@ typedef struct nd_plan_s *nd_plan; /* opaque, library-owned */
 /* Validate the graph (a1), orient and relabel it (a2: Section 2
  * "O(alpha)-Orientation", Section 4.4 "Graph Relabeling") and build the
  * two-level r-clique table (a3: Sections 4.1-4.3, contiguous last-level
- * tables, slot position = r-clique index).  hbm_budget_bytes = 0 means no
- * budget.  On success *out owns device memory until nd_plan_destroy. */
+ * tables, slot position = r-clique index).  hbm_budget_bytes bounds the
+ * plan's device memory plus the workspace its run needs (0 = no budget): a
+ * plan that would exceed it fails with ND_ENOMEM once n_r is known, before
+ * the table is allocated.  On success *out owns device memory until
+ * nd_plan_destroy. */
 nd_status nd_plan_create(const nd_csr *g, int r, int s, const nd_options *opt,
                          uint64_t hbm_budget_bytes, void *hip_stream, nd_plan *out);
 
-/* Number of r-cliques (rows of the output) and device bytes held by the plan. */
-nd_status nd_plan_sizes(nd_plan p, uint64_t *n_r, uint64_t *device_bytes);
+/* Number of r-cliques (rows of the output), the exact workspace bytes nd_run
+ * needs, and the device bytes the plan holds.  Any argument may be NULL. */
+nd_status nd_plan_sizes(nd_plan p, uint64_t *n_r, uint64_t *workspace_bytes,
+                        uint64_t *plan_bytes);
 
 /* Count (Algorithm 2 Count-Func), bucket and peel (Algorithm 2 main loop,
- * Update, Update-Func), then emit.  Outputs (DEVICE, caller-owned):
+ * Update, Update-Func), then emit (Algorithm 2 returns every r-clique with
+ * its bucket).  workspace_dev: DEVICE, caller-owned, 256-byte aligned, at
+ * least the workspace_bytes nd_plan_sizes reports (a larger one leaves more
+ * room for round records); its contents are scratch, overwritten by the run.
+ * Outputs (DEVICE, caller-owned):
  *   rcliques_dev[n_r * r]  int32: row i = the vertices (original ids,
- *                          ascending) of r-clique i; rows in library order;
+ *                          ascending) of r-clique i; rows in library order,
+ *                          or lexicographic with options.canonical;
  *   kappa_dev[n_r]         uint32: nucleus number of row i;
  *   counts_dev[n_r]        uint32, may be NULL: initial s-clique count of row i.
  * stats (host) may be NULL.  Every r-clique of G is a row, including those in
- * no s-clique (kappa 0).  Can be called once per plan. */
-nd_status nd_run(nd_plan p, int32_t *rcliques_dev, uint32_t *kappa_dev, uint32_t *counts_dev,
-                 nd_stats *stats);
+ * no s-clique (kappa 0).  Errors: ND_ENOMEM before any kernel when the
+ * workspace is smaller than required or plan + workspace exceed the budget;
+ * ND_ENOMEM after the peel started when one round needs more records (or
+ * round-trace entries) than the workspace holds -- the plan then reports
+ * the larger requirement through nd_plan_sizes and may be run again;
+ * ND_EOVERFLOW when a count does not fit 32 bits.  A plan may be run any
+ * number of times; each run starts again from the table. */
+nd_status nd_run(nd_plan p, void *workspace_dev, uint64_t workspace_bytes, int32_t *rcliques_dev,
+                 uint32_t *kappa_dev, uint32_t *counts_dev, nd_stats *stats);
 
-/* Round sizes |A_t| and levels k_t of the last nd_run (host arrays of
- * capacity cap); *rounds receives rho.  Either array may be NULL. */
+/* Round sizes |A_t| and levels k_t of the last successful nd_run (host
+ * arrays of capacity cap); *rounds receives rho.  Either array may be NULL. */
 nd_status nd_round_trace(nd_plan p, uint64_t *sizes_host, uint32_t *levels_host, uint64_t cap,
                          uint64_t *rounds);
 
@@ -134,16 +168,21 @@ nd_status nd_batch_create(const nd_csr *graphs, int32_t count, int r, int s,
                           const nd_options *opt, uint64_t hbm_budget_bytes, void *hip_stream,
                           nd_batch *out);
 
-/* Total rows over all graphs (sum of their r-clique counts) and the count. */
-nd_status nd_batch_sizes(nd_batch b, uint64_t *n_r_total, int32_t *count);
+/* Total rows over all graphs (sum of their r-clique counts), the count, and
+ * the exact workspace bytes nd_batch_run needs.  Any argument may be NULL. */
+nd_status nd_batch_sizes(nd_batch b, uint64_t *n_r_total, int32_t *count,
+                         uint64_t *workspace_bytes);
 
-/* Runs the decomposition.  Outputs are grouped by graph: the rows of graph g
- * are [row_offsets_host[g], row_offsets_host[g+1]) (host array of count+1),
- * with vertex ids local to graph g (ascending within a row) and rows in no
- * particular order within a graph.  rcliques_dev[n_r_total * r],
- * kappa_dev[n_r_total], counts_dev (nullable) as in nd_run.  Once per batch. */
-nd_status nd_batch_run(nd_batch b, int32_t *rcliques_dev, uint32_t *kappa_dev,
-                       uint32_t *counts_dev, uint64_t *row_offsets_host, nd_stats *stats);
+/* Runs the decomposition with a caller-owned DEVICE workspace as in nd_run.
+ * Outputs are grouped by graph: the rows of graph g are
+ * [row_offsets_host[g], row_offsets_host[g+1]) (host array of count+1), with
+ * vertex ids local to graph g (ascending within a row); rows within a graph
+ * are in no particular order, or lexicographic with options.canonical.
+ * rcliques_dev[n_r_total * r], kappa_dev[n_r_total], counts_dev (nullable)
+ * as in nd_run.  Errors as nd_run; may be run again. */
+nd_status nd_batch_run(nd_batch b, void *workspace_dev, uint64_t workspace_bytes,
+                       int32_t *rcliques_dev, uint32_t *kappa_dev, uint32_t *counts_dev,
+                       uint64_t *row_offsets_host, nd_stats *stats);
 
 /* Rounds of the shared peel (every graph's rounds interleaved). */
 nd_status nd_batch_round_trace(nd_batch b, uint64_t *sizes_host, uint32_t *levels_host,
@@ -153,20 +192,27 @@ nd_status nd_batch_destroy(nd_batch b);
 
 /* ---- Serving: continuous batching of (graph, r, s) jobs ----------------
  * A pool of `workers` threads, each with its own HIP stream on the device
- * current at creation, takes jobs from one FIFO queue.  A job starts when a
- * worker is idle and its device-memory estimate fits what is left of
- * hbm_budget_bytes (0 = no budget; a job larger than the budget runs
- * alone), so jobs that arrive while others run are admitted as slots and
- * memory free up and their peel rounds interleave on the GPU.  The caller
- * keeps each submitted graph's device memory alive until the job is done.
- * Results stay on the device until nd_server_release. */
+ * current at creation, takes jobs from one FIFO queue.  Admission is by
+ * hbm_budget_bytes (0 = no budget): a job starts its plan when a worker is
+ * idle and an estimate from its size fits what is left of the budget; once
+ * its plan exists the job holds exactly the plan's bytes plus its run's
+ * workspace and outputs (nd_plan_sizes).  A job whose exact figure does not
+ * fit gives its plan back and waits at the head of the queue for that
+ * figure; a job larger than the whole budget runs alone.  Jobs that arrive
+ * while others run are admitted as slots and memory free up, and their peel
+ * rounds interleave on the GPU.  The caller keeps each submitted graph's
+ * device memory alive until the job is done.  Results stay on the device
+ * until nd_server_release. */
 typedef struct nd_server_s *nd_server;
 
 nd_status nd_server_create(int32_t workers, uint64_t hbm_budget_bytes, nd_server *out);
 
-/* Queue one decomposition; *job receives its id.  opt may be NULL. */
+/* Queue one decomposition; *job receives its id.  opt may be NULL.
+ * hip_stream is the stream that produced the graph (NULL = the null
+ * stream): the job's first kernel waits for everything enqueued on it
+ * before this call. */
 nd_status nd_server_submit(nd_server sv, const nd_csr *g, int r, int s, const nd_options *opt,
-                           uint64_t *job);
+                           void *hip_stream, uint64_t *job);
 
 /* Wait up to timeout_ms (-1 = without limit); *done = 1 once the job ended. */
 nd_status nd_server_wait(nd_server sv, uint64_t job, int32_t timeout_ms, int32_t *done);

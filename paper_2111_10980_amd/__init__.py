@@ -16,6 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnd.so")
 
 ND_MAX_S = 7
+ND_ENOMEM = 5
+WS_ALIGN = 256
 STATUS = {0: "ND_OK", 1: "ND_EINVAL", 2: "ND_EGRAPH", 3: "ND_EKEYWIDTH", 4: "ND_EOVERFLOW",
           5: "ND_ENOMEM", 6: "ND_EHIP", 7: "ND_ESTATE"}
 PHASES = ("validate", "orient", "table", "count", "bucket", "peel", "emit", "total")
@@ -35,7 +37,9 @@ class nd_csr(ctypes.Structure):
 
 class nd_options(ctypes.Structure):
     _fields_ = [("orient", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("load_factor", ctypes.c_float), ("path", ctypes.c_int32)]
+                ("load_factor", ctypes.c_float), ("path", ctypes.c_int32),
+                ("canonical", ctypes.c_int32), ("trace_cap", ctypes.c_uint32),
+                ("record_cap", ctypes.c_uint64), ("debug_count_bias", ctypes.c_uint64)]
 
 
 class nd_roofline(ctypes.Structure):
@@ -50,7 +54,8 @@ class nd_stats(ctypes.Structure):
                 ("max_kappa", ctypes.c_uint32), ("max_out_degree", ctypes.c_uint32),
                 ("ms", ctypes.c_float * 8), ("count_kernel_ms", ctypes.c_float),
                 ("peel_kernel_ms", ctypes.c_float), ("count_launches", ctypes.c_uint32),
-                ("peel_launches", ctypes.c_uint32), ("atomics", ctypes.c_uint64)]
+                ("peel_launches", ctypes.c_uint32), ("atomics", ctypes.c_uint64),
+                ("workspace_bytes", ctypes.c_uint64), ("max_round_records", ctypes.c_uint64)]
 
 
 def _load():
@@ -63,8 +68,8 @@ def _load():
                                    ctypes.POINTER(nd_options), ctypes.c_uint64, P,
                                    ctypes.POINTER(P)]
     lib.nd_plan_sizes.argtypes = [P, ctypes.POINTER(ctypes.c_uint64),
-                                  ctypes.POINTER(ctypes.c_uint64)]
-    lib.nd_run.argtypes = [P, P, P, P, ctypes.POINTER(nd_stats)]
+                                  ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
+    lib.nd_run.argtypes = [P, P, ctypes.c_uint64, P, P, P, ctypes.POINTER(nd_stats)]
     lib.nd_round_trace.argtypes = [P, P, P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
     lib.nd_plan_destroy.argtypes = [P]
     lib.nd_release_cached.argtypes = []
@@ -75,8 +80,8 @@ def _load():
                                     ctypes.c_int, ctypes.POINTER(nd_options), ctypes.c_uint64, P,
                                     ctypes.POINTER(P)]
     lib.nd_batch_sizes.argtypes = [P, ctypes.POINTER(ctypes.c_uint64),
-                                   ctypes.POINTER(ctypes.c_int32)]
-    lib.nd_batch_run.argtypes = [P, P, P, P, P, ctypes.POINTER(nd_stats)]
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint64)]
+    lib.nd_batch_run.argtypes = [P, P, ctypes.c_uint64, P, P, P, P, ctypes.POINTER(nd_stats)]
     lib.nd_batch_round_trace.argtypes = [P, P, P, ctypes.c_uint64,
                                          ctypes.POINTER(ctypes.c_uint64)]
     lib.nd_batch_destroy.argtypes = [P]
@@ -85,7 +90,8 @@ def _load():
         getattr(lib, name).restype = ctypes.c_int
     lib.nd_server_create.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(P)]
     lib.nd_server_submit.argtypes = [P, ctypes.POINTER(nd_csr), ctypes.c_int, ctypes.c_int,
-                                     ctypes.POINTER(nd_options), ctypes.POINTER(ctypes.c_uint64)]
+                                     ctypes.POINTER(nd_options), P,
+                                     ctypes.POINTER(ctypes.c_uint64)]
     lib.nd_server_wait.argtypes = [P, ctypes.c_uint64, ctypes.c_int32,
                                    ctypes.POINTER(ctypes.c_int32)]
     lib.nd_server_result.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64),
@@ -149,9 +155,18 @@ def _stream_handle(stream):
 
 # ------------------------------------------------------------------ raw ABI
 
+def make_options(orient: int = 0, timing: bool = False, load_factor: float = 0.0,
+                 generic: bool = False, canonical: bool = False, trace_cap: int = 0,
+                 record_cap: int = 0, debug_count_bias: int = 0) -> nd_options:
+    return nd_options(int(orient), int(bool(timing)), float(load_factor), int(bool(generic)),
+                      int(bool(canonical)), int(trace_cap), int(record_cap),
+                      int(debug_count_bias))
+
+
 def nd_plan_create(row_ptr, col, r: int, s: int, orient: int = 0, load_factor: float = 0.0,
                    hbm_budget_bytes: int = 0, stream=None, timing: bool = False,
-                   generic: bool = False):
+                   generic: bool = False, canonical: bool = False, trace_cap: int = 0,
+                   record_cap: int = 0, debug_count_bias: int = 0):
     """row_ptr (int64, n+1) and col (int32) are CUDA tensors; returns a plan handle."""
     import torch
     if row_ptr.dtype != torch.int64 or col.dtype != torch.int32:
@@ -162,7 +177,8 @@ def nd_plan_create(row_ptr, col, r: int, s: int, orient: int = 0, load_factor: f
     col = col.contiguous()
     g = nd_csr(int(row_ptr.numel() - 1), int(col.numel()), row_ptr.data_ptr(),
                col.data_ptr() if col.numel() else None)
-    opt = nd_options(int(orient), int(bool(timing)), float(load_factor), int(bool(generic)))
+    opt = make_options(orient, timing, load_factor, generic, canonical, trace_cap, record_cap,
+                       debug_count_bias)
     h = ctypes.c_void_p()
     _check(_lib.nd_plan_create(ctypes.byref(g), int(r), int(s), ctypes.byref(opt),
                                int(hbm_budget_bytes), _stream_handle(stream), ctypes.byref(h)))
@@ -170,17 +186,31 @@ def nd_plan_create(row_ptr, col, r: int, s: int, orient: int = 0, load_factor: f
 
 
 def nd_plan_sizes(plan):
+    """(n_r, workspace bytes a run needs, device bytes the plan holds)."""
     n_r = ctypes.c_uint64()
-    nbytes = ctypes.c_uint64()
-    _check(_lib.nd_plan_sizes(plan, ctypes.byref(n_r), ctypes.byref(nbytes)))
-    return int(n_r.value), int(nbytes.value)
+    ws = ctypes.c_uint64()
+    held = ctypes.c_uint64()
+    _check(_lib.nd_plan_sizes(plan, ctypes.byref(n_r), ctypes.byref(ws), ctypes.byref(held)))
+    return int(n_r.value), int(ws.value), int(held.value)
 
 
-def nd_run(plan, rcliques, kappa, counts=None) -> dict:
+def workspace(nbytes: int, device="cuda"):
+    """A caller-owned device workspace (torch uint8, 256-byte aligned)."""
+    import torch
+    t = torch.empty(max(int(nbytes), 1) + WS_ALIGN, dtype=torch.uint8, device=device)
+    off = (-t.data_ptr()) % WS_ALIGN
+    return t[off: off + max(int(nbytes), 1)]
+
+
+def _ptr(t):
+    return t.data_ptr() if t is not None and t.numel() else None
+
+
+def nd_run(plan, ws, rcliques, kappa, counts=None, ws_bytes=None) -> dict:
+    """ws: device workspace tensor (see workspace()); ws_bytes defaults to its size."""
     st = nd_stats()
-    _check(_lib.nd_run(plan, rcliques.data_ptr() if rcliques.numel() else None,
-                       kappa.data_ptr() if kappa.numel() else None,
-                       counts.data_ptr() if counts is not None and counts.numel() else None,
+    nbytes = int(ws.numel() * ws.element_size()) if ws_bytes is None else int(ws_bytes)
+    _check(_lib.nd_run(plan, _ptr(ws), nbytes, _ptr(rcliques), _ptr(kappa), _ptr(counts),
                        ctypes.byref(st)))
     return stats_dict(st)
 
@@ -203,7 +233,7 @@ def nd_plan_destroy(plan):
 
 def nd_batch_create(graphs, r: int, s: int, orient: int = 0, load_factor: float = 0.0,
                     hbm_budget_bytes: int = 0, stream=None, timing: bool = False,
-                    generic: bool = False):
+                    generic: bool = False, canonical: bool = False):
     """graphs: sequence of (row_ptr int64, col int32) device tensor pairs."""
     arr = (nd_csr * max(1, len(graphs)))()
     keep = []
@@ -213,7 +243,7 @@ def nd_batch_create(graphs, r: int, s: int, orient: int = 0, load_factor: float 
         keep.append((rp, col))
         arr[i] = nd_csr(int(rp.numel() - 1), int(col.numel()), rp.data_ptr(),
                         col.data_ptr() if col.numel() else None)
-    opt = nd_options(int(orient), int(bool(timing)), float(load_factor), int(bool(generic)))
+    opt = make_options(orient, timing, load_factor, generic, canonical)
     h = ctypes.c_void_p()
     _check(_lib.nd_batch_create(arr, len(graphs), int(r), int(s), ctypes.byref(opt),
                                 int(hbm_budget_bytes), _stream_handle(stream), ctypes.byref(h)))
@@ -221,22 +251,23 @@ def nd_batch_create(graphs, r: int, s: int, orient: int = 0, load_factor: float 
 
 
 def nd_batch_sizes(batch):
+    """(total rows, graph count, workspace bytes a batch run needs)."""
     n_r = ctypes.c_uint64()
     count = ctypes.c_int32()
-    _check(_lib.nd_batch_sizes(batch, ctypes.byref(n_r), ctypes.byref(count)))
-    return int(n_r.value), int(count.value)
+    ws = ctypes.c_uint64()
+    _check(_lib.nd_batch_sizes(batch, ctypes.byref(n_r), ctypes.byref(count), ctypes.byref(ws)))
+    return int(n_r.value), int(count.value), int(ws.value)
 
 
-def nd_batch_run(batch, rcliques, kappa, counts=None):
+def nd_batch_run(batch, ws, rcliques, kappa, counts=None):
     """Returns (row_offsets numpy uint64[count+1], stats dict)."""
     import numpy as np
-    _, count = nd_batch_sizes(batch)
+    _, count, _ = nd_batch_sizes(batch)
     off = np.zeros(count + 1, dtype=np.uint64)
     st = nd_stats()
-    _check(_lib.nd_batch_run(batch, rcliques.data_ptr() if rcliques.numel() else None,
-                             kappa.data_ptr() if kappa.numel() else None,
-                             counts.data_ptr() if counts is not None and counts.numel() else None,
-                             off.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st)))
+    _check(_lib.nd_batch_run(batch, _ptr(ws), int(ws.numel()), _ptr(rcliques), _ptr(kappa),
+                             _ptr(counts), off.ctypes.data_as(ctypes.c_void_p),
+                             ctypes.byref(st)))
     return off, stats_dict(st)
 
 
@@ -264,14 +295,16 @@ def nd_server_create(workers: int, hbm_budget_bytes: int = 0):
 
 
 def nd_server_submit(server, row_ptr, col, r: int, s: int, orient: int = 0,
-                     generic: bool = False) -> int:
-    """The caller keeps row_ptr / col alive until the job is done."""
+                     generic: bool = False, stream=None) -> int:
+    """The caller keeps row_ptr / col alive until the job is done.  The job
+    waits for the work already queued on `stream` (default: torch's current
+    stream), which produced the graph."""
     g = nd_csr(int(row_ptr.numel() - 1), int(col.numel()), row_ptr.data_ptr(),
                col.data_ptr() if col.numel() else None)
-    opt = nd_options(int(orient), 0, 0.0, int(bool(generic)))
+    opt = make_options(orient, generic=generic)
     job = ctypes.c_uint64()
     _check(_lib.nd_server_submit(server, ctypes.byref(g), int(r), int(s), ctypes.byref(opt),
-                                 ctypes.byref(job)))
+                                 _stream_handle(stream), ctypes.byref(job)))
     return int(job.value)
 
 
@@ -361,20 +394,47 @@ class Decomposition:
     round_levels: object = None
 
 
+def run_requery(plan, rcl, kap, cnt=None, device="cuda", attempts: int = 10):
+    """nd_run with a workspace of the size nd_plan_sizes reports; when a
+    round outgrows it (ND_ENOMEM and a larger reported size) the workspace is
+    re-allocated and the plan run again.  Returns (stats, workspace bytes)."""
+    for i in range(attempts):
+        _, ws_bytes, _ = nd_plan_sizes(plan)
+        ws = workspace(ws_bytes, device)
+        try:
+            return nd_run(plan, ws, rcl, kap, cnt, ws_bytes=ws_bytes), ws_bytes
+        except NdError as e:
+            _, again, _ = nd_plan_sizes(plan)
+            if e.code != ND_ENOMEM or again <= ws_bytes or i + 1 == attempts:
+                raise
+        finally:
+            del ws
+    raise AssertionError("unreachable")
+
+
 def decompose(row_ptr, col, r: int, s: int, with_counts: bool = False, orient: int = 0,
               load_factor: float = 0.0, hbm_budget_bytes: int = 0, stream=None,
-              timing: bool = False, generic: bool = False) -> Decomposition:
-    """Whole hot path on the current device: plan, run, round trace, destroy."""
+              timing: bool = False, generic: bool = False, canonical: bool = False,
+              trace_cap: int = 0, record_cap: int = 0, debug_count_bias: int = 0,
+              requery: bool = True) -> Decomposition:
+    """Whole hot path on the current device: plan, workspace, run, round
+    trace, destroy.  With requery a run whose round outgrew the workspace is
+    repeated with the larger workspace the plan then reports."""
     import torch
     plan = nd_plan_create(row_ptr, col, r, s, orient, load_factor, hbm_budget_bytes, stream,
-                          timing, generic)
+                          timing, generic, canonical, trace_cap, record_cap, debug_count_bias)
     try:
-        n_r, _ = nd_plan_sizes(plan)
+        n_r, ws_bytes, _ = nd_plan_sizes(plan)
         dev = row_ptr.device
         rcl = torch.empty((n_r, r), dtype=torch.int32, device=dev)
         kap = torch.empty((n_r,), dtype=torch.int32, device=dev)
         cnt = torch.empty((n_r,), dtype=torch.int32, device=dev) if with_counts else None
-        stats = nd_run(plan, rcl, kap, cnt)
+        if requery:
+            stats, _ = run_requery(plan, rcl, kap, cnt, dev)
+        else:
+            ws = workspace(ws_bytes, dev)
+            stats = nd_run(plan, ws, rcl, kap, cnt, ws_bytes=ws_bytes)
+            del ws
         sizes, levels = nd_round_trace(plan)
     finally:
         nd_plan_destroy(plan)
@@ -399,18 +459,28 @@ class BatchDecomposition:
 
 def decompose_batch(graphs, r: int, s: int, with_counts: bool = False, orient: int = 0,
                     load_factor: float = 0.0, hbm_budget_bytes: int = 0, stream=None,
-                    timing: bool = False, generic: bool = False) -> BatchDecomposition:
+                    timing: bool = False, generic: bool = False,
+                    canonical: bool = False) -> BatchDecomposition:
     """All graphs in one fused decomposition (graphs: (row_ptr, col) device pairs)."""
     import torch
     b = nd_batch_create(graphs, r, s, orient, load_factor, hbm_budget_bytes, stream, timing,
-                        generic)
+                        generic, canonical)
     try:
-        n_r, _ = nd_batch_sizes(b)
         dev = graphs[0][0].device if graphs else torch.device("cuda")
-        rcl = torch.empty((n_r, r), dtype=torch.int32, device=dev)
-        kap = torch.empty((n_r,), dtype=torch.int32, device=dev)
-        cnt = torch.empty((n_r,), dtype=torch.int32, device=dev) if with_counts else None
-        off, stats = nd_batch_run(b, rcl, kap, cnt)
+        for i in range(10):
+            n_r, _, ws_bytes = nd_batch_sizes(b)
+            rcl = torch.empty((n_r, r), dtype=torch.int32, device=dev)
+            kap = torch.empty((n_r,), dtype=torch.int32, device=dev)
+            cnt = torch.empty((n_r,), dtype=torch.int32, device=dev) if with_counts else None
+            ws = workspace(ws_bytes, dev)
+            try:
+                off, stats = nd_batch_run(b, ws, rcl, kap, cnt)
+                break
+            except NdError as e:  # a round outgrew the workspace: run again with more
+                if e.code != ND_ENOMEM or nd_batch_sizes(b)[2] <= ws_bytes or i == 9:
+                    raise
+            finally:
+                del ws
     finally:
         nd_batch_destroy(b)
     return BatchDecomposition(r, s, rcl, kap, cnt, off, stats)
@@ -433,8 +503,9 @@ class Server:
         self.handle = nd_server_create(workers, hbm_budget_bytes)
         self._keep = {}
 
-    def submit(self, row_ptr, col, r: int, s: int, orient: int = 0, generic: bool = False) -> int:
-        job = nd_server_submit(self.handle, row_ptr, col, r, s, orient, generic)
+    def submit(self, row_ptr, col, r: int, s: int, orient: int = 0, generic: bool = False,
+               stream=None) -> int:
+        job = nd_server_submit(self.handle, row_ptr, col, r, s, orient, generic, stream)
         self._keep[job] = (row_ptr, col, r, s)
         return job
 

@@ -1,14 +1,19 @@
 // Host runtime and C ABI (include/nd.h).
 //
-// Memory: every device buffer comes from the device's stream-ordered memory
-// pool (hipMallocAsync / hipFreeAsync on the plan's stream) with the release
-// threshold raised, so buffers freed by one plan are reused by the next one
-// without returning to the driver.  nd_release_cached() trims the pool.
+// Memory.  A plan's own device state (relabeled graph, r-clique table, index,
+// round control block, liveness bitmaps) comes from the device's
+// stream-ordered memory pool (hipMallocAsync / hipFreeAsync on the plan's
+// stream) with the release threshold raised, so buffers freed by one plan
+// are reused by the next one without returning to the driver;
+// nd_release_cached() trims the pool.  Everything a run needs beyond that
+// (bucket lists, per-frontier scratch, round records, round trace, sort
+// buffers) is carved from the caller's workspace: nd_run allocates nothing.
+// run_ws_bytes() adds up exactly the buffers a run carves, so
+// nd_plan_sizes reports the workspace size a run needs.
 //
-// The peel loop (Algorithm 2, "while finished < |T|") runs on the host and
-// enqueues, per round: stamp(A_t), peel(A_t) -> A_{t+1}, then reads back the
-// 4-byte size of A_{t+1}.  When A_{t+1} is empty the level advances to the
-// minimum live count (reduction + partition of the live list).
+// The peel loop (Algorithm 2, "while finished < |T|") is driven by the
+// device (nd_peel.hip); the host queues rounds and reads the round state
+// every few rounds.
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -28,6 +33,7 @@ namespace {
 
 thread_local hipStream_t g_stream = nullptr;
 thread_local std::string g_last_error;
+thread_local Workspace *g_ws = nullptr;
 
 struct Failure {
   nd_status st;
@@ -95,14 +101,63 @@ __global__ void k_caps(int32_t n, int r, float lf, const uint32_t *__restrict__ 
   }
 }
 
+// out[0] += sum of the slot counts, out[1] = max(out[1], largest count)
 __global__ __launch_bounds__(256) void k_sum_slot_counts(const Slot *__restrict__ s, uint64_t n,
                                                          unsigned long long *out) {
   uint64_t acc = 0;
+  uint32_t mx = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    acc += s[i].cnt;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t c = s[i].cnt;
+    acc += c;
+    mx = c > mx ? c : mx;
+  }
   acc = wave_sum_u64(acc);
-  if (lane_id() == 0 && acc) atomicAdd(out, (unsigned long long)acc);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t o = __shfl_xor(mx, off);
+    mx = o > mx ? o : mx;
+  }
+  if (lane_id() == 0) {
+    if (acc) atomicAdd(&out[0], (unsigned long long)acc);
+    if (mx) atomicMax(&out[1], (unsigned long long)mx);
+  }
+}
+
+// A re-run starts from the table as built: counts 0, every r-clique live.
+__global__ void k_reset_slots(Slot *s, uint64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    s[i].cnt = 0;
+    s[i].stamp = kLive;
+  }
+}
+
+// Canonical row order: key of row idx[i] from its vertices [from, to) (ids
+// ascending in the row), first vertex most significant, b bits per vertex.
+__global__ void k_row_keys(const int32_t *__restrict__ rows, int r, uint64_t n_r,
+                           const uint32_t *__restrict__ idx, int from, int to, int b,
+                           uint64_t *keys) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)n_r;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t *row = rows + (uint64_t)idx[i] * r;
+    uint64_t k = 0;
+    for (int q = from; q < to; q++) k = (k << b) | (uint64_t)(uint32_t)row[q];
+    keys[i] = k;
+  }
+}
+
+__global__ void k_permute_rows(const int32_t *__restrict__ rows, const uint32_t *__restrict__ kap,
+                               const uint32_t *__restrict__ cnt, int r, uint64_t n_r,
+                               const uint32_t *__restrict__ idx, int32_t *rows_out,
+                               uint32_t *kap_out, uint32_t *cnt_out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)n_r;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t j = idx[i];
+    for (int q = 0; q < r; q++) rows_out[(uint64_t)i * r + q] = rows[j * r + q];
+    kap_out[i] = kap[j];
+    if (cnt_out) cnt_out[i] = cnt[j];
+  }
 }
 
 // ---- batched decomposition: the batch is one disjoint union (kappa is a
@@ -158,6 +213,21 @@ __global__ void k_union_cols(const GraphDesc *__restrict__ gd, const int64_t *__
   }
 }
 
+// canonical batch output: rows are already grouped by graph and ordered
+// within it; only the ids become graph-local
+__global__ void k_localise(const int32_t *__restrict__ rcl, const uint32_t *__restrict__ kap,
+                           const uint32_t *__restrict__ cnt, int r, uint64_t n_r,
+                           const int32_t *__restrict__ gid, const int32_t *__restrict__ vo,
+                           int32_t *rcl_out, uint32_t *kap_out, uint32_t *cnt_out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)n_r;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int g = gid[i];
+    for (int q = 0; q < r; q++) rcl_out[i * r + q] = rcl[i * r + q] - vo[g];
+    kap_out[i] = kap[i];
+    if (cnt_out) cnt_out[i] = cnt[i];
+  }
+}
+
 // graph of every output row (its first vertex's graph) and rows per graph
 __global__ void k_row_graph(const int32_t *__restrict__ rcl, int r, uint64_t n_r,
                             const int32_t *__restrict__ vo, int count, int32_t *gid,
@@ -197,23 +267,30 @@ int bits_for(uint64_t maxval) {
   return b;
 }
 
-struct Timer {
-  hipEvent_t ev[9];
-  bool ok = false;
-  Timer() {
-    ok = true;
+// HIP events created once per plan (a run creates none).
+struct EventSet {
+  std::vector<hipEvent_t> ev;
+  bool ok = true;
+  void create(int n) {
+    ev.assign((size_t)n, nullptr);
     for (auto &e : ev)
-      if (hipEventCreate(&e) != hipSuccess) ok = false;
+      if (hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
+        ok = false;
+      }
   }
-  ~Timer() {
-    for (auto &e : ev) hipEventDestroy(e);
+  ~EventSet() {
+    for (auto &e : ev)
+      if (e) hipEventDestroy(e);
   }
+  hipEvent_t at(int i) const { return ok && i < (int)ev.size() ? ev[i] : nullptr; }
   void mark(int i, hipStream_t st) {
-    if (ok) hipEventRecord(ev[i], st);
+    if (hipEvent_t e = at(i)) hipEventRecord(e, st);
   }
-  float between(int a, int b) {
+  float between(int a, int b) const {
     float ms = 0;
-    if (ok && hipEventElapsedTime(&ms, ev[a], ev[b]) == hipSuccess) return ms;
+    hipEvent_t x = at(a), y = at(b);
+    if (x && y && hipEventElapsedTime(&ms, x, y) == hipSuccess) return ms;
     return 0;
   }
 };
@@ -228,7 +305,26 @@ T read_dev(const T *p, hipStream_t st) {
 
 }  // namespace
 
+WorkspaceScope::WorkspaceScope(void *base, uint64_t size) : prev(g_ws) {
+  ws.base = (char *)base;
+  ws.size = size;
+  ws.used = 0;
+  g_ws = &ws;
+}
+
+WorkspaceScope::~WorkspaceScope() { g_ws = prev; }
+
 void *dev_alloc(size_t bytes) {
+  if (g_ws) {
+    const uint64_t b = ws_block(bytes);
+    if (g_ws->used + b > g_ws->size)
+      fail(ND_ENOMEM, "workspace of %llu bytes exhausted (%llu used, %llu more asked)",
+           (unsigned long long)g_ws->size, (unsigned long long)g_ws->used,
+           (unsigned long long)b);
+    void *p = g_ws->base + g_ws->used;
+    g_ws->used += b;
+    return p;
+  }
   void *p = nullptr;
   if (bytes == 0) bytes = 16;
   hipError_t e = hipMallocAsync(&p, bytes, g_stream);
@@ -240,7 +336,9 @@ void *dev_alloc(size_t bytes) {
 }
 
 void dev_free(void *p) {
-  if (p) hipFreeAsync(p, g_stream);
+  if (!p) return;
+  if (g_ws && (char *)p >= g_ws->base && (char *)p < g_ws->base + g_ws->size) return;
+  hipFreeAsync(p, g_stream);
 }
 
 }  // namespace nd
@@ -259,17 +357,73 @@ struct nd_plan_s {
   DevBuf<uint32_t> occ;
   DevBuf<Counters> ctr;
   DevBuf<unsigned long long> stats;  // kStatLines x kStatStride statistic lines
+  DevBuf<unsigned long long> total;  // [0] sum of the counts, [1] largest count
+  DevBuf<RoundCtl> rcb;              // device round state of the peel
+  RoundCtl *mirror = nullptr;        // its pinned host copy
   FastIndex fx;
   bool fast = false;  // s = r+1 path (bitmaps + apex lists)
+  int path = 0;       // peel path: 0 walker, 1 s = r+1 passes, 2 s >= r+2 passes
   uint64_t n_r = 0, n_slots = 0, held = 0;
   int bits = 1;
-  bool ran = false;
+  int runs = 0;
+  bool traced = false;
+  uint64_t rec_need = 0;     // record capacity the next run's workspace provides at least
+  uint32_t trace_need = 0;   // round-trace capacity likewise
   std::vector<uint64_t> round_sizes;
   std::vector<uint32_t> round_k;
   uint64_t k_advances = 0;
   float ms_create[3] = {0, 0, 0};
+  EventSet ev_create;  // 4: plan creation phases
+  EventSet ev_run;     // 5: run phases, 2: count kernels
+  EventSet ev_peel;    // timing: 2 * kPeelMaxDepth around the update passes
   TableView table() const { return TableView{bits, seg.get(), slots.get(), v1.get()}; }
+  ~nd_plan_s() {
+    if (mirror) hipHostFree(mirror);
+  }
 };
+
+namespace nd {
+namespace {
+
+// Workspace bytes of one run of plan p with the given round capacities: the
+// sum of ws_block() over every buffer the run carves (see run_impl).
+uint64_t run_ws_bytes(const nd_plan_s *p, uint64_t rec_cap, uint32_t tcap) {
+  uint64_t b = 0;
+  const uint64_t n_r = p->n_r;
+  if (!p->fast) b += count_scliques_ws_bytes(p->g);
+  b += peel_ws_bytes(p->r, p->path, n_r, (uint64_t)p->g.nnz, rec_cap, tcap);
+  if (p->opt.canonical && n_r > 1) {
+    const int r = p->r, bits = p->bits;
+    b += ws_buf<int32_t>(n_r * (uint64_t)r) + 2 * ws_buf<uint32_t>(n_r);  // staged outputs
+    b += ws_buf<uint64_t>(n_r) + ws_buf<uint32_t>(n_r);                   // keys, order
+    if (r * bits <= 64) {
+      b += radix_sort_ws_bytes((int64_t)n_r, r * bits, 0, true);
+    } else {
+      const int h = (r + 1) / 2;
+      b += radix_sort_ws_bytes((int64_t)n_r, (r - h) * bits, 0, true) +
+           radix_sort_ws_bytes((int64_t)n_r, h * bits, 0, true);
+    }
+  }
+  return b;
+}
+
+// bytes of records, for the record capacity a workspace leaves
+uint64_t rec_cap_for(const nd_plan_s *p, uint64_t ws_bytes) {
+  if (p->path == 0 || p->n_r == 0) return 0;
+  uint64_t lo = 0, hi = 1;
+  while (run_ws_bytes(p, hi, p->trace_need) <= ws_bytes && hi < (1ull << 40)) hi *= 2;
+  while (lo + 1 < hi) {  // largest capacity whose layout fits
+    const uint64_t mid = lo + (hi - lo) / 2;
+    if (run_ws_bytes(p, mid, p->trace_need) <= ws_bytes) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+uint64_t required_ws(const nd_plan_s *p) { return run_ws_bytes(p, p->rec_need, p->trace_need); }
+
+}  // namespace
+}  // namespace nd
 
 template <class F>
 static nd_status guarded(hipStream_t st, F &&f) {
@@ -338,12 +492,27 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
     if (p->opt.load_factor > 0.9f) fail(ND_EINVAL, "load_factor must be <= 0.9");
     if (p->opt.orient != 0 && p->opt.orient != 1) fail(ND_EINVAL, "orient must be 0 or 1");
     if (p->opt.path != 0 && p->opt.path != 1) fail(ND_EINVAL, "path must be 0 or 1");
+    if (p->opt.canonical != 0 && p->opt.canonical != 1) fail(ND_EINVAL, "canonical must be 0 or 1");
     p->fast = (s == r + 1) && r >= 2 && r <= 6 && p->opt.path == 0;
+    p->path = p->fast ? 1 : (s >= r + 2 && p->opt.path == 0 ? 2 : 0);
     p->budget = hbm_budget_bytes;
     const int32_t n = gin->n;
-    Timer tm;
+    // every event, pinned buffer and device buffer a run uses belongs to the plan
+    // or to the run's workspace, so a run itself allocates nothing
+    p->ev_create.create(4);
+    p->ev_run.create(7);
+    if (p->opt.timing) p->ev_peel.create(2 * kPeelMaxDepth);
+    if (hipHostMalloc((void **)&p->mirror, sizeof(RoundCtl), hipHostMallocDefault) != hipSuccess) {
+      hipGetLastError();
+      p->mirror = nullptr;
+      fail(ND_ENOMEM, "pinned host allocation failed");
+    }
+    EventSet &tm = p->ev_create;
     tm.mark(0, st);
     p->ctr.reset(1);
+    p->stats.reset((size_t)kStatLines * kStatStride);
+    p->total.reset(2);
+    p->rcb.reset(1);
     fill_u32((uint32_t *)p->ctr.get(), 0, sizeof(Counters) / 4, st);
     if (validate_csr(n, gin->nnz, gin->row_ptr, gin->col, p->ctr.get(), st))
       fail(ND_EGRAPH, "CSR is not a simple symmetric graph with sorted rows");
@@ -352,6 +521,9 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
     p->bits = vb < 1 ? 1 : vb;
     if ((r - 1) * p->bits > 63)
       fail(ND_EKEYWIDTH, "(r-1)*ceil(log2 n) = %d exceeds 63", (r - 1) * p->bits);
+    const uint64_t fixed_bytes = ws_buf<Counters>(1) + ws_buf<unsigned long long>(
+                                     (uint64_t)kStatLines * kStatStride) +
+                                 ws_buf<unsigned long long>(2) + ws_buf<RoundCtl>(1);
     uint64_t graph_bytes = (uint64_t)(n + 1) * 8 * 2 + (uint64_t)gin->nnz * 4 + (uint64_t)n * 4;
     if (p->budget && graph_bytes > p->budget) fail(ND_ENOMEM, "graph exceeds the HBM budget");
     orient_relabel(n, gin->nnz, gin->row_ptr, gin->col, p->opt.orient, &p->g, st);
@@ -379,13 +551,23 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
     p->n_r = read_dev((uint64_t *)&p->ctr.get()->n_s, st);
     if (p->n_slots >= (1ull << 32) - 1)
       fail(ND_EOVERFLOW, "table needs %llu slots (limit 2^32-1)", (unsigned long long)p->n_slots);
-    // round records carry the frontier position as a signed 32-bit index
+    // round records carry the frontier position as a signed 32-bit int
     if (p->n_r > 0x7FFFFFFFull)
       fail(ND_EOVERFLOW, "%llu r-cliques (limit 2^31-1)", (unsigned long long)p->n_r);
+    // round capacities the workspace provides (records only on the split paths)
+    if (p->path != 0)
+      p->rec_need = p->opt.record_cap ? p->opt.record_cap
+                                      : std::max<uint64_t>(2 * p->n_r, 1ull << 18);
+    p->trace_need = p->opt.trace_cap
+                        ? p->opt.trace_cap
+                        : (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(p->n_r, 4096));
     uint64_t table_bytes = p->n_slots * (sizeof(Slot) + 4) + p->n_r * 4 * 5;
-    p->held = graph_bytes + table_bytes + (uint64_t)(n + 1) * 8;
-    if (p->budget && p->held > p->budget)
-      fail(ND_ENOMEM, "plan needs %llu bytes, budget %llu", (unsigned long long)p->held,
+    p->held = graph_bytes + table_bytes + (uint64_t)(n + 1) * 8 + fixed_bytes;
+    // the budget covers the plan and the workspace of its run; checked before
+    // the table is allocated
+    if (p->budget && p->held + required_ws(p) > p->budget)
+      fail(ND_ENOMEM, "plan needs %llu bytes and its run a workspace of %llu, budget %llu",
+           (unsigned long long)p->held, (unsigned long long)required_ws(p),
            (unsigned long long)p->budget);
     p->slots.reset(p->n_slots ? p->n_slots : 1);
     p->v1.reset(p->n_slots ? p->n_slots : 1);
@@ -406,8 +588,18 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
       build_slot_loc(p->g, r, p->table(), p->n_slots, &p->fx, st);
       p->held += p->fx.bm_words * 8 + p->fx.n_tri * 4 + (uint64_t)(gin->nnz + 1) * 8 +
                  p->n_slots * 8;
-      if (p->budget && p->held > p->budget)
-        fail(ND_ENOMEM, "plan needs %llu bytes, budget %llu", (unsigned long long)p->held,
+      if (r == 3) {  // liveness and frontier bits, reset by every run
+        const uint64_t bw = p->fx.bm_words ? p->fx.bm_words : 1;
+        const uint64_t aw = (p->fx.n_tri + 63) / 64 ? (p->fx.n_tri + 63) / 64 : 1;
+        p->fx.alive.reset(bw);
+        p->fx.front.reset(bw);
+        p->fx.alive_apex.reset(aw);
+        p->fx.front_apex.reset(aw);
+        p->held += 16 * (bw + aw);
+      }
+      if (p->budget && p->held + required_ws(p) > p->budget)
+        fail(ND_ENOMEM, "plan needs %llu bytes and its run a workspace of %llu, budget %llu",
+             (unsigned long long)p->held, (unsigned long long)required_ws(p),
              (unsigned long long)p->budget);
     }
     tm.mark(3, st);
@@ -428,142 +620,240 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
   return ND_OK;
 }
 
-nd_status nd_plan_sizes(nd_plan p, uint64_t *n_r, uint64_t *device_bytes) {
+nd_status nd_plan_sizes(nd_plan p, uint64_t *n_r, uint64_t *workspace_bytes,
+                        uint64_t *plan_bytes) {
   if (!p) {
     g_last_error = "plan is null";
     return ND_EINVAL;
   }
   if (n_r) *n_r = p->n_r;
-  if (device_bytes) *device_bytes = p->held;
+  if (workspace_bytes) *workspace_bytes = required_ws(p);
+  if (plan_bytes) *plan_bytes = p->held;
   return ND_OK;
 }
 
-nd_status nd_run(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *counts_dev,
-                 nd_stats *stats) {
+}  // extern "C"
+
+namespace {
+
+// The run (a4-a8) of plan p inside an active workspace scope: every buffer
+// below is carved from the workspace in the order run_ws_bytes counts them.
+void run_impl(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *counts_dev,
+              nd_stats *stats) {
+  hipStream_t st = p->st;
+  const int r = p->r, s = p->s;
+  Counters *dc = p->ctr.get();
+  EventSet &tm = p->ev_run;  // 0..4 phases, 5/6 around the count listing
+  const bool timing = p->opt.timing != 0;
+  float count_kernel_ms = 0, peel_kernel_ms = 0;
+  uint32_t count_launches = 0, peel_launches = 0;
+  // what is left of the workspace (a batch run carves its own buffers first)
+  const uint64_t rec_cap = rec_cap_for(p, g_ws->size - g_ws->used);
+  const uint32_t tcap = p->trace_need;
+  tm.mark(0, st);
+  if (p->runs > 0 && p->n_slots)  // a re-run starts from the table as built
+    hipLaunchKernelGGL(k_reset_slots, dim3((unsigned)grid_for(p->n_slots, 256, 16384)),
+                       dim3(256), 0, st, p->slots.get(), p->n_slots);
+  p->runs++;
+  p->traced = false;
+  // ---- count (Count-Func)
+  fill_u32((uint32_t *)dc, 0, sizeof(Counters) / 4, st);
+  fill_u64((uint64_t *)p->stats.get(), 0, (int64_t)kStatLines * kStatStride, st);
+  if (p->fast) {
+    if (timing) tm.mark(5, st);
+    count_direct(p->g, r, p->table(), p->fx, p->occ.get(), p->n_r, dc, st);
+    if (timing) tm.mark(6, st);
+  } else {
+    count_scliques(p->g, r, s, p->table(), dc, p->stats.get(), st,
+                   timing ? tm.at(5) : nullptr, timing ? tm.at(6) : nullptr);
+    stats_collect(p->stats.get(), dc, st);
+    fill_u64((uint64_t *)p->stats.get(), 0, (int64_t)kStatLines * kStatStride, st);
+  }
+  unsigned long long *total = p->total.get();
+  fill_u64((uint64_t *)total, 0, 2, st);
+  if (p->n_slots)
+    hipLaunchKernelGGL(k_sum_slot_counts, dim3((unsigned)grid_for(p->n_slots, 256 * 16, 4096)),
+                       dim3(256), 0, st, p->slots.get(), p->n_slots, total);
+  Counters hc = read_dev(dc, st);
+  if (hc.err) fail(ND_EHIP, "s-clique count failed (flags %u)", hc.err);
+  if (timing) {
+    count_kernel_ms = tm.between(5, 6);
+    count_launches = 1;
+  }
+  const uint64_t sum = read_dev((uint64_t *)total, st);
+  const uint64_t maxc = read_dev((uint64_t *)total + 1, st);
+  const uint64_t per = binom_u64(s, r);
+  // direct counting: every s-clique is counted once by each of its r-subsets
+  const uint64_t n_s = p->fast ? sum / per : hc.n_s;
+  if (p->fast && sum % per != 0) fail(ND_EHIP, "direct counts are inconsistent");
+  if (sum != per * n_s) fail(ND_EOVERFLOW, "an s-clique count exceeds 32 bits");
+  if (maxc + p->opt.debug_count_bias > 0xFFFFFFFFull)
+    fail(ND_EOVERFLOW, "an s-clique count (%llu + bias %llu) exceeds 32 bits",
+         (unsigned long long)maxc, (unsigned long long)p->opt.debug_count_bias);
+  const bool canon = p->opt.canonical && p->n_r > 1;
+  // outputs are staged for the canonical row order; the initial counts are
+  // taken now, before the peel decrements them
+  DevBuf<int32_t> rows_tmp;
+  DevBuf<uint32_t> kap_tmp, cnt_tmp;
+  if (canon) {
+    rows_tmp.reset(p->n_r * (uint64_t)r);
+    kap_tmp.reset(p->n_r);
+    cnt_tmp.reset(p->n_r);
+  }
+  int32_t *rows_out = canon ? rows_tmp.get() : rcl_dev;
+  uint32_t *kap_out = canon ? kap_tmp.get() : kappa_dev;
+  uint32_t *cnt_out = canon ? cnt_tmp.get() : counts_dev;
+  if (cnt_out) gather_counts(p->occ.get(), p->n_r, p->slots.get(), cnt_out, st);
+  if (p->fast && r == 3) {  // liveness bitmaps start as the adjacency bitmaps
+    if (p->fx.bm_words)
+      hip_check(hipMemcpyAsync(p->fx.alive.get(), p->fx.bm.get(), 8 * p->fx.bm_words,
+                               hipMemcpyDeviceToDevice, st),
+                "copy bitmaps");
+    const uint64_t bw = p->fx.bm_words ? p->fx.bm_words : 1;
+    const uint64_t aw = (p->fx.n_tri + 63) / 64 ? (p->fx.n_tri + 63) / 64 : 1;
+    fill_u64(p->fx.alive_apex.get(), ~0ull, (int64_t)aw, st);  // every triangle alive
+    fill_u64(p->fx.front.get(), 0, (int64_t)bw, st);            // no triangle in a frontier yet
+    fill_u64(p->fx.front_apex.get(), 0, (int64_t)aw, st);
+  }
+  tm.mark(1, st);
+  // ---- bucket init + peel, driven by the device (the host polls the
+  // round state every few rounds)
+  PeelResult pr;
+  DevBuf<uint32_t> kround;
+  PeelState ps;
+  ps.rc = p->rcb.get();
+  ps.mirror = p->mirror;
+  ps.ev = timing && p->ev_peel.ok && !p->ev_peel.ev.empty() ? p->ev_peel.ev.data() : nullptr;
+  const uint32_t perr =
+      peel_all(p->g, r, s, p->path, p->table(), p->fast ? &p->fx : nullptr, p->occ.get(), p->n_r,
+               dc, p->stats.get(), ps, rec_cap, tcap, st, tm.at(2), &kround, &pr);
+  if (perr & kErrCapacity) {
+    // the workspace was too small for one round: raise the requirement so
+    // that nd_plan_sizes reports the size to run again with
+    if (pr.need_rec > rec_cap)  // later rounds may need more: grow at least 8-fold
+      p->rec_need = std::max<uint64_t>(pr.need_rec + pr.need_rec / 4, 8 * rec_cap);
+    if (pr.need_trace > tcap)  // rho is unknown: grow the trace 8-fold, to at least 4096
+      p->trace_need = (uint32_t)std::min<uint64_t>(
+          std::max<uint64_t>(std::max<uint64_t>(pr.need_trace, 8ull * tcap), 4096),
+          std::max<uint64_t>(p->n_r, 1));
+    fail(ND_ENOMEM,
+         "a peel round needs %llu records (workspace holds %llu) or %llu round-trace entries "
+         "(holds %u); run again with a workspace of %llu bytes",
+         (unsigned long long)pr.need_rec, (unsigned long long)rec_cap,
+         (unsigned long long)pr.need_trace, tcap, (unsigned long long)required_ws(p));
+  }
+  if (perr & kErrRuntime) fail(ND_EHIP, "HIP error in the peel loop: %s",
+                               hipGetErrorString(hipGetLastError()));
+  if (perr) fail(ND_EHIP, "peel failed (flags %u)", perr);
+  p->round_sizes = pr.sizes;
+  p->round_k = pr.levels;
+  p->k_advances = pr.advances;
+  if (timing) {
+    peel_kernel_ms = pr.apply_ms;
+    peel_launches = pr.apply_launches;
+  }
+  tm.mark(3, st);
+  // ---- emit (staged for the canonical row order)
+  stats_collect(p->stats.get(), dc, st);
+  emit(r, p->occ.get(), p->n_r, p->table(), p->g.new2old.get(), kround.get(),
+       (uint32_t)p->round_k.size(), rows_out, kap_out, st);
+  if (canon) {
+    // rows in lexicographic order of their vertices: radix sort of packed
+    // keys (two keys, low part first, when r vertices need more than 64 bits)
+    const uint64_t n_r = p->n_r;
+    const int b = p->bits;
+    DevBuf<uint64_t> keys(n_r);
+    DevBuf<uint32_t> idx(n_r);
+    iota_u32(idx.get(), (int64_t)n_r, st);
+    const dim3 g((unsigned)grid_for((int64_t)n_r, 256)), blk(256);
+    if (r * b <= 64) {
+      hipLaunchKernelGGL(k_row_keys, g, blk, 0, st, rows_tmp.get(), r, n_r, idx.get(), 0, r, b,
+                         keys.get());
+      radix_sort(keys.get(), idx.get(), (int64_t)n_r, r * b, st);
+    } else {
+      const int h = (r + 1) / 2;
+      hipLaunchKernelGGL(k_row_keys, g, blk, 0, st, rows_tmp.get(), r, n_r, idx.get(), h, r, b,
+                         keys.get());
+      radix_sort(keys.get(), idx.get(), (int64_t)n_r, (r - h) * b, st);
+      hipLaunchKernelGGL(k_row_keys, g, blk, 0, st, rows_tmp.get(), r, n_r, idx.get(), 0, h, b,
+                         keys.get());
+      radix_sort(keys.get(), idx.get(), (int64_t)n_r, h * b, st);
+    }
+    hipLaunchKernelGGL(k_permute_rows, g, blk, 0, st, rows_tmp.get(), kap_tmp.get(),
+                       cnt_tmp.get(), r, n_r, idx.get(), rcl_dev, kappa_dev,
+                       counts_dev ? counts_dev : nullptr);
+  }
+  tm.mark(4, st);
+  hc = read_dev(dc, st);
+  hip_check(hipGetLastError(), "kernel launch");
+  if (hc.err) fail(ND_EHIP, "peel failed (flags %u)", hc.err);
+  p->traced = true;
+  if (stats) {
+    memset(stats, 0, sizeof(*stats));
+    stats->n_r = p->n_r;
+    stats->n_s = n_s;
+    stats->rounds = p->round_sizes.size();
+    stats->k_advances = p->k_advances;
+    stats->decrements = hc.decrements;
+    stats->discoveries = hc.discoveries;
+    stats->atomics = hc.atomics;
+    stats->table_slots = p->n_slots;
+    stats->max_kappa = p->round_k.empty() ? 0 : p->round_k.back();
+    stats->max_out_degree = p->g.max_out;
+    stats->ms[0] = p->ms_create[0];
+    stats->ms[1] = p->ms_create[1];
+    stats->ms[2] = p->ms_create[2];
+    stats->ms[3] = tm.between(0, 1);
+    stats->ms[4] = tm.between(1, 2);
+    stats->ms[5] = tm.between(2, 3);
+    stats->ms[6] = tm.between(3, 4);
+    stats->ms[7] = p->ms_create[0] + p->ms_create[1] + p->ms_create[2] + tm.between(0, 4);
+    stats->count_kernel_ms = count_kernel_ms;
+    stats->peel_kernel_ms = peel_kernel_ms;
+    stats->count_launches = count_launches;
+    stats->peel_launches = peel_launches;
+    stats->workspace_bytes = g_ws->used;
+    stats->max_round_records = pr.max_rec;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+nd_status nd_run(nd_plan p, void *workspace_dev, uint64_t workspace_bytes, int32_t *rcl_dev,
+                 uint32_t *kappa_dev, uint32_t *counts_dev, nd_stats *stats) {
   if (!p) {
     g_last_error = "plan is null";
     return ND_EINVAL;
-  }
-  if (p->ran) {
-    g_last_error = "nd_run was already called on this plan";
-    return ND_ESTATE;
   }
   if (p->n_r && (!rcl_dev || !kappa_dev)) {
     g_last_error = "output pointer is null";
     return ND_EINVAL;
   }
-  hipStream_t st = p->st;
-  return guarded(st, [&] {
-    p->ran = true;
-    const int r = p->r, s = p->s;
-    Counters *dc = p->ctr.get();
-    Timer tm;
-    const bool timing = p->opt.timing != 0;
-    Timer kt;  // kernel timing: 0/1 around the count listing, 2/3 around each peel launch
-    float count_kernel_ms = 0, peel_kernel_ms = 0;
-    uint32_t count_launches = 0, peel_launches = 0;
-    tm.mark(0, st);
-    // ---- count (Count-Func)
-    fill_u32((uint32_t *)dc, 0, sizeof(Counters) / 4, st);
-    p->stats.reset((size_t)kStatLines * kStatStride);
-    fill_u64((uint64_t *)p->stats.get(), 0, (int64_t)kStatLines * kStatStride, st);
-    if (p->fast) {
-      if (timing) kt.mark(0, st);
-      count_direct(p->g, r, p->table(), p->fx, p->occ.get(), p->n_r, dc, st);
-      if (timing) kt.mark(1, st);
-    } else {
-      count_scliques(p->g, r, s, p->table(), dc, p->stats.get(), st,
-                     timing ? kt.ev[0] : nullptr, timing ? kt.ev[1] : nullptr);
-      stats_collect(p->stats.get(), dc, st);
-      fill_u64((uint64_t *)p->stats.get(), 0, (int64_t)kStatLines * kStatStride, st);
-    }
-    DevBuf<uint64_t> total(1);
-    fill_u64(total.get(), 0, 1, st);
-    if (p->n_slots)
-      hipLaunchKernelGGL(k_sum_slot_counts, dim3((unsigned)grid_for(p->n_slots, 256 * 16, 4096)),
-                         dim3(256), 0, st, p->slots.get(), p->n_slots,
-                         (unsigned long long *)total.get());
-    Counters hc = read_dev(dc, st);
-    if (hc.err) fail(ND_EHIP, "s-clique count failed (flags %u)", hc.err);
-    if (timing) {
-      count_kernel_ms = kt.between(0, 1);
-      count_launches = 1;
-    }
-    const uint64_t sum = read_dev(total.get(), st);
-    const uint64_t per = binom_u64(s, r);
-    // direct counting: every s-clique is counted once by each of its r-subsets
-    const uint64_t n_s = p->fast ? sum / per : hc.n_s;
-    if (p->fast && sum % per != 0) fail(ND_EHIP, "direct counts are inconsistent");
-    if (sum != per * n_s) fail(ND_EOVERFLOW, "an s-clique count exceeds 32 bits");
-    if (counts_dev) gather_counts(p->occ.get(), p->n_r, p->slots.get(), counts_dev, st);
-    if (p->fast && r == 3) {  // liveness bitmaps start as the adjacency bitmaps
-      p->fx.alive.reset(p->fx.bm_words ? p->fx.bm_words : 1);
-      if (p->fx.bm_words)
-        hip_check(hipMemcpyAsync(p->fx.alive.get(), p->fx.bm.get(), 8 * p->fx.bm_words,
-                                 hipMemcpyDeviceToDevice, st),
-                  "copy bitmaps");
-      const uint64_t aw = (p->fx.n_tri + 63) / 64;  // every triangle alive
-      p->fx.alive_apex.reset(aw ? aw : 1);
-      fill_u64(p->fx.alive_apex.get(), ~0ull, (int64_t)(aw ? aw : 1), st);
-      // no triangle in a frontier yet
-      p->fx.front.reset(p->fx.bm_words ? p->fx.bm_words : 1);
-      fill_u64(p->fx.front.get(), 0, (int64_t)(p->fx.bm_words ? p->fx.bm_words : 1), st);
-      p->fx.front_apex.reset(aw ? aw : 1);
-      fill_u64(p->fx.front_apex.get(), 0, (int64_t)(aw ? aw : 1), st);
-    }
-    tm.mark(1, st);
-    // ---- bucket init + peel, driven by the device (the host polls the
-    // round state every few rounds)
-    const int path = p->fast ? 1 : (s >= r + 2 && p->opt.path == 0 ? 2 : 0);
-    PeelResult pr;
-    DevBuf<uint32_t> kround;
-    const uint32_t perr =
-        peel_all(p->g, r, s, path, p->table(), p->fast ? &p->fx : nullptr, p->occ.get(), p->n_r,
-                 dc, p->stats.get(), timing, st, tm.ev[2], &kround, &pr);
-    if (perr & kErrRuntime) fail(ND_EHIP, "HIP error in the peel loop: %s",
-                                 hipGetErrorString(hipGetLastError()));
-    if (perr) fail(ND_EHIP, "peel failed (flags %u)", perr);
-    p->round_sizes = pr.sizes;
-    p->round_k = pr.levels;
-    p->k_advances = pr.advances;
-    if (timing) {
-      peel_kernel_ms = pr.apply_ms;
-      peel_launches = pr.apply_launches;
-    }
-    tm.mark(3, st);
-    // ---- emit
-    stats_collect(p->stats.get(), dc, st);
-    emit(r, p->occ.get(), p->n_r, p->table(), p->g.new2old.get(), kround.get(),
-         (uint32_t)p->round_k.size(), rcl_dev, kappa_dev, st);
-    tm.mark(4, st);
-    hc = read_dev(dc, st);
-    hip_check(hipGetLastError(), "kernel launch");
-    if (hc.err) fail(ND_EHIP, "peel failed (flags %u)", hc.err);
-    if (stats) {
-      memset(stats, 0, sizeof(*stats));
-      stats->n_r = p->n_r;
-      stats->n_s = n_s;
-      stats->rounds = p->round_sizes.size();
-      stats->k_advances = p->k_advances;
-      stats->decrements = hc.decrements;
-      stats->discoveries = hc.discoveries;
-      stats->atomics = hc.atomics;
-      stats->table_slots = p->n_slots;
-      stats->max_kappa = p->round_k.empty() ? 0 : p->round_k.back();
-      stats->max_out_degree = p->g.max_out;
-      stats->ms[0] = p->ms_create[0];
-      stats->ms[1] = p->ms_create[1];
-      stats->ms[2] = p->ms_create[2];
-      stats->ms[3] = tm.between(0, 1);
-      stats->ms[4] = tm.between(1, 2);
-      stats->ms[5] = tm.between(2, 3);
-      stats->ms[6] = tm.between(3, 4);
-      stats->ms[7] = p->ms_create[0] + p->ms_create[1] + p->ms_create[2] + tm.between(0, 4);
-      stats->count_kernel_ms = count_kernel_ms;
-      stats->peel_kernel_ms = peel_kernel_ms;
-      stats->count_launches = count_launches;
-      stats->peel_launches = peel_launches;
-    }
+  const uint64_t need = required_ws(p);
+  if (workspace_bytes < need || (need && !workspace_dev)) {
+    char buf[200];
+    snprintf(buf, sizeof(buf), "workspace of %llu bytes given, the run needs %llu",
+             (unsigned long long)workspace_bytes, (unsigned long long)need);
+    g_last_error = buf;
+    return ND_ENOMEM;
+  }
+  if (((uintptr_t)workspace_dev & (kWsAlign - 1)) != 0) {
+    g_last_error = "workspace must be 256-byte aligned";
+    return ND_EINVAL;
+  }
+  if (p->budget && p->held + workspace_bytes > p->budget) {
+    char buf[200];
+    snprintf(buf, sizeof(buf), "plan %llu bytes + workspace %llu bytes exceed the budget %llu",
+             (unsigned long long)p->held, (unsigned long long)workspace_bytes,
+             (unsigned long long)p->budget);
+    g_last_error = buf;
+    return ND_ENOMEM;
+  }
+  return guarded(p->st, [&] {
+    WorkspaceScope ws(workspace_dev, workspace_bytes);
+    run_impl(p, rcl_dev, kappa_dev, counts_dev, stats);
   });
 }
 
@@ -573,8 +863,8 @@ nd_status nd_round_trace(nd_plan p, uint64_t *sizes_host, uint32_t *levels_host,
     g_last_error = "plan is null";
     return ND_EINVAL;
   }
-  if (!p->ran) {
-    g_last_error = "nd_run has not been called";
+  if (!p->traced) {
+    g_last_error = "no successful nd_run on this plan";
     return ND_ESTATE;
   }
   uint64_t n = p->round_sizes.size();
@@ -605,8 +895,23 @@ struct nd_batch_s {
   DevBuf<int32_t> col, vo;
   nd_plan plan = nullptr;
   uint64_t n_r = 0;
-  bool ran = false;
 };
+
+}  // extern "C"
+
+namespace {
+
+// bytes a batch run carves before the union plan's run: staged outputs,
+// per-graph row counts and cursors, row graph ids
+uint64_t batch_extra_ws(const nd_batch_s *b) {
+  const uint64_t n1 = b->n_r ? b->n_r : 1;
+  return ws_buf<int32_t>(b->n_r ? b->n_r * (uint64_t)b->r : 1) + 2 * ws_buf<uint32_t>(n1) +
+         2 * ws_buf<unsigned long long>((uint64_t)b->count + 1) + ws_buf<int32_t>(n1);
+}
+
+}  // namespace
+
+extern "C" {
 
 nd_status nd_batch_create(const nd_csr *graphs, int32_t count, int r, int s,
                           const nd_options *opt, uint64_t hbm_budget_bytes, void *hip_stream,
@@ -669,8 +974,7 @@ nd_status nd_batch_create(const nd_csr *graphs, int32_t count, int r, int s,
     nd_csr u{(int32_t)nv, ne, b->rp.get(), b->col.get()};
     nd_status prc = nd_plan_create(&u, r, s, opt, hbm_budget_bytes, hip_stream, &b->plan);
     if (prc != ND_OK) throw Failure{prc};
-    uint64_t bytes = 0;
-    nd_plan_sizes(b->plan, &b->n_r, &bytes);
+    b->n_r = b->plan->n_r;
   });
   if (rc != ND_OK) {
     nd_batch_destroy(b);
@@ -680,57 +984,89 @@ nd_status nd_batch_create(const nd_csr *graphs, int32_t count, int r, int s,
   return ND_OK;
 }
 
-nd_status nd_batch_sizes(nd_batch b, uint64_t *n_r_total, int32_t *count) {
+nd_status nd_batch_sizes(nd_batch b, uint64_t *n_r_total, int32_t *count,
+                         uint64_t *workspace_bytes) {
   if (!b) {
     g_last_error = "batch is null";
     return ND_EINVAL;
   }
   if (n_r_total) *n_r_total = b->n_r;
   if (count) *count = b->count;
+  if (workspace_bytes) *workspace_bytes = batch_extra_ws(b) + required_ws(b->plan);
   return ND_OK;
 }
 
-nd_status nd_batch_run(nd_batch b, int32_t *rcliques_dev, uint32_t *kappa_dev,
-                       uint32_t *counts_dev, uint64_t *row_offsets_host, nd_stats *stats) {
+nd_status nd_batch_run(nd_batch b, void *workspace_dev, uint64_t workspace_bytes,
+                       int32_t *rcliques_dev, uint32_t *kappa_dev, uint32_t *counts_dev,
+                       uint64_t *row_offsets_host, nd_stats *stats) {
   if (!b || !row_offsets_host) {
     g_last_error = "batch or row_offsets is null";
     return ND_EINVAL;
-  }
-  if (b->ran) {
-    g_last_error = "nd_batch_run was already called on this batch";
-    return ND_ESTATE;
   }
   if (b->n_r && (!rcliques_dev || !kappa_dev)) {
     g_last_error = "output pointer is null";
     return ND_EINVAL;
   }
+  const uint64_t need = batch_extra_ws(b) + required_ws(b->plan);
+  if (workspace_bytes < need || !workspace_dev) {
+    char buf[200];
+    snprintf(buf, sizeof(buf), "workspace of %llu bytes given, the batch run needs %llu",
+             (unsigned long long)workspace_bytes, (unsigned long long)need);
+    g_last_error = buf;
+    return ND_ENOMEM;
+  }
+  if (((uintptr_t)workspace_dev & (kWsAlign - 1)) != 0) {
+    g_last_error = "workspace must be 256-byte aligned";
+    return ND_EINVAL;
+  }
+  nd_plan p = b->plan;
+  if (p->budget && p->held + workspace_bytes > p->budget) {
+    g_last_error = "plan and workspace exceed the budget";
+    return ND_ENOMEM;
+  }
   hipStream_t st = b->st;
   return guarded(st, [&] {
-    b->ran = true;
+    WorkspaceScope ws(workspace_dev, workspace_bytes);
     const int r = b->r;
     const uint64_t n_r = b->n_r;
-    DevBuf<int32_t> rcl(n_r ? n_r * r : 1);
-    DevBuf<uint32_t> kap(n_r ? n_r : 1), cnt(counts_dev && n_r ? n_r : 1);
-    nd_status prc = nd_run(b->plan, rcl.get(), kap.get(), counts_dev ? cnt.get() : nullptr, stats);
-    if (prc != ND_OK) throw Failure{prc};
     const int count = b->count;
+    DevBuf<int32_t> rcl(n_r ? n_r * r : 1);
+    DevBuf<uint32_t> kap(n_r ? n_r : 1), cnt(n_r ? n_r : 1);
     DevBuf<unsigned long long> per((size_t)count + 1), cur((size_t)count + 1);
+    DevBuf<int32_t> gid(n_r ? n_r : 1);
+    run_impl(p, rcl.get(), kap.get(), counts_dev ? cnt.get() : nullptr, stats);
     fill_u64((uint64_t *)per.get(), 0, count + 1, st);
     fill_u64((uint64_t *)cur.get(), 0, count + 1, st);
-    DevBuf<int32_t> gid(n_r ? n_r : 1);
     if (n_r && count > 0)
       hipLaunchKernelGGL(k_row_graph, dim3((unsigned)grid_for(n_r, 256)), dim3(256), 0, st,
                          rcl.get(), r, n_r, b->vo.get(), count, gid.get(), per.get());
-    scan_exclusive_u64((uint64_t *)per.get(), (uint64_t *)per.get(), (int64_t)count + 1, st);
-    if (n_r && count > 0)
-      hipLaunchKernelGGL(k_regroup, dim3((unsigned)grid_for(n_r, 256)), dim3(256), 0, st,
-                         rcl.get(), kap.get(), cnt.get(), r, n_r, gid.get(), b->vo.get(),
-                         per.get(), cur.get(), rcliques_dev, kappa_dev,
-                         counts_dev ? counts_dev : nullptr);
-    hip_check(hipMemcpyAsync(row_offsets_host, per.get(), 8 * ((size_t)count + 1),
-                             hipMemcpyDeviceToHost, st), "copy row offsets");
+    // row offsets: prefix sum of the per-graph row counts (count + 1 values)
+    std::vector<uint64_t> off((size_t)count + 1);
+    hip_check(hipMemcpyAsync(off.data(), per.get(), 8 * off.size(), hipMemcpyDeviceToHost, st),
+              "copy row counts");
+    hip_check(hipStreamSynchronize(st), "synchronize");
+    uint64_t acc = 0;
+    for (auto &x : off) {
+      const uint64_t c = x;
+      x = acc;
+      acc += c;
+    }
+    hip_check(hipMemcpyAsync(per.get(), off.data(), 8 * off.size(), hipMemcpyHostToDevice, st),
+              "copy row offsets");
+    if (n_r && count > 0) {
+      if (p->opt.canonical)  // rows sorted by union ids are grouped by graph already
+        hipLaunchKernelGGL(k_localise, dim3((unsigned)grid_for(n_r, 256)), dim3(256), 0, st,
+                           rcl.get(), kap.get(), cnt.get(), r, n_r, gid.get(), b->vo.get(),
+                           rcliques_dev, kappa_dev, counts_dev ? counts_dev : nullptr);
+      else
+        hipLaunchKernelGGL(k_regroup, dim3((unsigned)grid_for(n_r, 256)), dim3(256), 0, st,
+                           rcl.get(), kap.get(), cnt.get(), r, n_r, gid.get(), b->vo.get(),
+                           per.get(), cur.get(), rcliques_dev, kappa_dev,
+                           counts_dev ? counts_dev : nullptr);
+    }
     hip_check(hipStreamSynchronize(st), "synchronize");
     hip_check(hipGetLastError(), "kernel launch");
+    memcpy(row_offsets_host, off.data(), 8 * off.size());
   });
 }
 

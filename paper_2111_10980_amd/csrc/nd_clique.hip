@@ -503,6 +503,10 @@ void stats_collect(unsigned long long *stats, Counters *dctr, hipStream_t st) {
   hipLaunchKernelGGL(k_stats_collect, dim3(1), dim3(256), 0, st, stats, dctr);
 }
 
+uint64_t count_scliques_ws_bytes(const OrientedGraph &g) {
+  return g.n == 0 ? 0 : ws_buf<uint32_t>((uint64_t)5 * (uint64_t)g.n);
+}
+
 #define ND_COUNT_CASE(R_, S_) \
   case (R_) * 16 + (S_): count_s_impl<R_, S_>(g, T, dctr, stats, st, ev0, ev1); break;
 

@@ -11,9 +11,39 @@
 
 namespace nd {
 
-// Device memory from the library's caching pool (never hipMalloc directly).
+// Device memory from the library's caching pool (never hipMalloc directly),
+// or, while a workspace is active on the calling thread, carved from it.
 void *dev_alloc(size_t bytes);
 void dev_free(void *p);
+
+// Caller-owned device workspace.  While a WorkspaceScope is alive on a
+// thread, every dev_alloc of that thread takes the next 256-byte aligned
+// block of the workspace (blocks are never reused within the scope and
+// dev_free of a block does nothing); a request past the end fails with
+// ND_ENOMEM.  The workspace a run needs is therefore the sum of ws_block()
+// over every buffer it allocates, which the sizing functions below add up.
+constexpr uint64_t kWsAlign = 256;
+inline uint64_t ws_block(uint64_t bytes) {
+  if (bytes == 0) bytes = 16;
+  return (bytes + kWsAlign - 1) & ~(kWsAlign - 1);
+}
+// bytes one DevBuf<T>(count) takes from a workspace (none for count 0)
+template <class T>
+inline uint64_t ws_buf(uint64_t count) {
+  return count ? ws_block(count * sizeof(T)) : 0;
+}
+struct Workspace {
+  char *base = nullptr;
+  uint64_t size = 0, used = 0;
+};
+struct WorkspaceScope {
+  Workspace ws;
+  Workspace *prev;
+  WorkspaceScope(void *base, uint64_t size);
+  ~WorkspaceScope();
+  WorkspaceScope(const WorkspaceScope &) = delete;
+  WorkspaceScope &operator=(const WorkspaceScope &) = delete;
+};
 
 // Scratch buffer that returns to the pool when it goes out of scope.
 template <class T>
@@ -63,6 +93,9 @@ void radix_sort(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t
 // sum of a u32 array into *out (device u64, accumulated)
 void sum_u32(const uint32_t *p, int64_t n, uint64_t *out, hipStream_t st);
 uint32_t max_u32_host(const uint32_t *p, int64_t n, hipStream_t st);
+// workspace bytes one call allocates
+uint64_t scan_ws_bytes(int64_t n, size_t elem);
+uint64_t radix_sort_ws_bytes(int64_t n, int bits, int lo_bit, bool vals);
 
 // ---- graph (nd_graph.hip)
 struct OrientedGraph {
@@ -89,6 +122,8 @@ void insert_rcliques(const OrientedGraph &g, int r, const TableView &T, Counters
 void count_scliques(const OrientedGraph &g, int r, int s, const TableView &T, Counters *dctr,
                     unsigned long long *stats, hipStream_t st, hipEvent_t ev0 = nullptr,
                     hipEvent_t ev1 = nullptr);
+// workspace bytes count_scliques allocates
+uint64_t count_scliques_ws_bytes(const OrientedGraph &g);
 // sum the statistic lines into dctr->decrements, discoveries, n_s (adds)
 void stats_collect(unsigned long long *stats, Counters *dctr, hipStream_t st);
 
@@ -153,14 +188,33 @@ struct PeelResult {
   uint32_t advances = 0;         // level advances
   float apply_ms = 0;            // update-pass kernel time (timing only)
   uint32_t apply_launches = 0;
+  uint64_t need_rec = 0;         // kErrCapacity: record capacity the halted round needs
+  uint64_t need_trace = 0;       // kErrCapacity: round-trace capacity needed
+  uint64_t max_rec = 0, max_arcs = 0;  // largest per-round record / out-arc totals
 };
+constexpr int kPeelMaxDepth = 32;      // rounds queued between two reads of the state
+constexpr uint64_t kArcsPerRecord = 4; // s >= r+2: out-arc capacity per record slot
+// Plan-owned state of the peel loop (no allocation happens in a run): the
+// device round control block, its pinned host mirror and, with timing,
+// 2 * kPeelMaxDepth events (else null).
+struct PeelState {
+  RoundCtl *rc = nullptr;
+  RoundCtl *mirror = nullptr;
+  hipEvent_t *ev = nullptr;
+};
+// Workspace bytes peel_all allocates with the given capacities.
+uint64_t peel_ws_bytes(int r, int path, uint64_t n_r, uint64_t nnz, uint64_t rec_cap,
+                       uint32_t trace_cap);
 // Whole bucketed peel (Algorithm 2 after the count) on the device.  path: 0
 // the one-wave walker, 1 the s = r+1 expand/apply passes (needs fx), 2 the
-// flattened s >= r+2 passes.  kround receives the level of every round (for
-// emit).  Returns 0 or kErr* bits.
+// flattened s >= r+2 passes.  rec_cap records (and kArcsPerRecord * rec_cap
+// out-arcs) per round and trace_cap rounds; a round that needs more stops the
+// peel with kErrCapacity and the capacity it needs in res.  kround receives
+// the level of every round (for emit).  Returns 0 or kErr* bits.
 uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableView &T,
                   const FastIndex *fx, const uint32_t *occ, uint64_t n_r, Counters *dc,
-                  unsigned long long *stats, bool timing, hipStream_t st, hipEvent_t ev_first,
+                  unsigned long long *stats, const PeelState &ps, uint64_t rec_cap,
+                  uint32_t trace_cap, hipStream_t st, hipEvent_t ev_first,
                   DevBuf<uint32_t> *kround, PeelResult *res);
 void occupied_list(const Slot *slots, uint64_t n_slots, uint32_t *occ, hipStream_t st);
 void gather_counts(const uint32_t *occ, uint64_t n_r, const Slot *slots, uint32_t *out,

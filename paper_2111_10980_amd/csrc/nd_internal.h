@@ -54,6 +54,7 @@ enum : uint32_t {
   kErrTable = 8u,
   kErrBucket = 16u,  // a level advance found no live r-clique, or an empty bucket
   kErrRuntime = 32u, // host side: a HIP call of the peel loop failed
+  kErrCapacity = 64u, // host side: a round needs more records or trace than the workspace holds
 };
 
 // ----------------------------------------------------------------- helpers
@@ -95,6 +96,23 @@ __device__ __forceinline__ bool adjacent(const GraphView &g, int32_t x, int32_t 
   int32_t b = x < y ? y : x;
   if (a == b) return false;
   return sorted_contains(g.col, g.up[a], g.rp[a + 1], b);
+}
+
+// Position of the arc between x and y in the lower-ranked endpoint's
+// out-neighbour list, or -1 when they are not adjacent.
+__device__ __forceinline__ int64_t arc_pos(const GraphView &g, int32_t x, int32_t y) {
+  const int32_t a = x < y ? x : y;
+  const int32_t b = x < y ? y : x;
+  if (a == b) return -1;
+  int64_t lo = g.up[a], hi = g.rp[a + 1];
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    const int32_t v = g.col[mid];
+    if (v == b) return mid;
+    if (v < b) lo = mid + 1;
+    else hi = mid;
+  }
+  return -1;
 }
 
 // Key of a sorted r-tuple: fields v[1..R-1], bits each, plus the occupied bit.
@@ -369,6 +387,7 @@ struct RoundCtl {
   uint64_t total2;         // second record list (member records)
   uint64_t total3, cap3;   // third list (out-arcs of members) / capacity
   uint64_t need;           // capacity asked for when a round halted (halt 1: total, 4: total3)
+  uint64_t max_total, max_total3;  // largest record / out-arc totals of a finished round
   uint32_t t, k, kw, nF;   // round, level, window top, |A_t|
   uint32_t nW, nH;         // window list and high list sizes
   uint32_t selF, selW, selH;

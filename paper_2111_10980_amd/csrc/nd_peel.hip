@@ -131,6 +131,8 @@ __device__ void round_begin_body(RoundCtl *rc, Counters *dc) {
 // empty round (one that only dropped the window list) is not counted.
 __device__ void round_end_body(RoundCtl *rc, const Counters *dc) {
   if (rc->nF == 0) return;
+  if (rc->total > rc->max_total) rc->max_total = rc->total;
+  if (rc->total3 > rc->max_total3) rc->max_total3 = rc->total3;
   rc->trace_size[rc->t] = rc->nF;
   rc->trace_k[rc->t] = rc->k;
   rc->finished += rc->nF;
@@ -1595,13 +1597,18 @@ __global__ __launch_bounds__(256) void k_gen_spread(RoundCtl *rc, const uint64_t
 
 // A thread per candidate x of the round: flag x when it lies in I(R) and
 // list the members that have out-arcs as (frontier index, x).
+// r = 2: dead[e] = 1 once the edge of arc position e (either direction) was
+// peeled in an earlier round.  A candidate x joins I(R) only if both its
+// edges to R are alive, so no s-clique destroyed earlier through one of
+// them is listed again (Update-Func would skip it after probing).
 template <int R>
 __global__ __launch_bounds__(256) void k_gen_member(GraphView g, RoundCtl *rc,
                                                     const uint64_t *__restrict__ ioff,
                                                     const uint32_t *__restrict__ owner,
                                                     const int32_t *__restrict__ fv,
                                                     const int32_t *__restrict__ drv, uint8_t *flag,
-                                                    int2 *mrec, uint64_t *mbeg, uint32_t *aown) {
+                                                    int2 *mrec, uint64_t *mbeg, uint32_t *aown,
+                                                    const uint8_t *__restrict__ dead) {
   if (rc_idle(rc)) return;
   const uint64_t C = rc->total;
   const uint64_t cap3 = rc->cap3;
@@ -1616,11 +1623,18 @@ __global__ __launch_bounds__(256) void k_gen_member(GraphView g, RoundCtl *rc,
     if (in) {
       f = owner[k];
       const int32_t v = drv[f];
-      x = g.col[g.rp[v] + (int64_t)(k - ioff[f])];
+      const int64_t ev = g.rp[v] + (int64_t)(k - ioff[f]);
+      x = g.col[ev];
+      if constexpr (R == 2) {
+        const int32_t u = fv[(int64_t)f * 2] == v ? fv[(int64_t)f * 2 + 1] : fv[(int64_t)f * 2];
+        const int64_t eu = arc_pos(g, x, u);
+        in = eu >= 0 && dead[ev] == 0 && dead[eu] == 0;
+      } else {
 #pragma unroll
-      for (int i = 0; i < R; i++) {
-        const int32_t u = fv[(int64_t)f * R + i];
-        if (in && u != v) in = adjacent(g, x, u);
+        for (int i = 0; i < R; i++) {
+          const int32_t u = fv[(int64_t)f * R + i];
+          if (in && u != v) in = adjacent(g, x, u);
+        }
       }
       flag[k] = in ? 1 : 0;
     }
@@ -1678,13 +1692,24 @@ __device__ __forceinline__ void merge_rq(const int32_t (&Rv)[R], const int32_t (
 template <int L, int R, int S>
 __device__ void gen_extend(const PeelArgs &a, const uint8_t *__restrict__ flag, int64_t lo,
                            int64_t hi, uint64_t fbase, const int32_t (&Rv)[R],
-                           int32_t (&Qv)[S - R], uint32_t p, LaneStats &ls) {
+                           int32_t (&Qv)[S - R], uint32_t p, LaneStats &ls,
+                           const uint8_t *__restrict__ dead) {
   const int32_t x = Qv[L - 1];
   for (int64_t e = a.g.up[x]; e < a.g.rp[x + 1]; e++) {
     const int32_t z = a.g.col[e];
     bool ok = gen_in(a.g, flag, lo, hi, fbase, z);
+    if constexpr (R == 2) {  // every edge of S other than R still alive
+      ok = ok && dead[e] == 0;
 #pragma unroll
-    for (int j = 0; j < L - 1; j++) ok = ok && adjacent(a.g, Qv[j], z);
+      for (int j = 0; j < L - 1; j++) {
+        if (!ok) break;
+        const int64_t q = arc_pos(a.g, Qv[j], z);
+        ok = q >= 0 && dead[q] == 0;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < L - 1; j++) ok = ok && adjacent(a.g, Qv[j], z);
+    }
     if (!ok) continue;
     Qv[L] = z;
     if constexpr (L + 1 == S - R) {
@@ -1693,7 +1718,7 @@ __device__ void gen_extend(const PeelArgs &a, const uint8_t *__restrict__ flag, 
       merge_rq<R, S - R>(Rv, Qv, Sv, rmask);
       update_func<R, S, false>(a, Sv, rmask, p, true, ls, nullptr);
     } else {
-      gen_extend<L + 1, R, S>(a, flag, lo, hi, fbase, Rv, Qv, p, ls);
+      gen_extend<L + 1, R, S>(a, flag, lo, hi, fbase, Rv, Qv, p, ls, dead);
     }
   }
 }
@@ -1708,7 +1733,8 @@ __global__ __launch_bounds__(256) void k_gen_apply(PeelArgs base, RoundCtl *rc,
                                                    const uint8_t *__restrict__ flag,
                                                    const int2 *__restrict__ mrec,
                                                    const uint64_t *__restrict__ mbeg,
-                                                   const uint32_t *__restrict__ aown) {
+                                                   const uint32_t *__restrict__ aown,
+                                                   const uint8_t *__restrict__ dead) {
   if (rc_idle(rc)) return;
   if (rc->total3 > rc->cap3) {  // arcs did not fit: the host grows the buffer, reruns the round
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1748,8 +1774,10 @@ __global__ __launch_bounds__(256) void k_gen_apply(PeelArgs base, RoundCtl *rc,
       lo = a.g.rp[v];
       hi = a.g.rp[v + 1];
       fbase = ioff[f];
-      const int32_t y = a.g.col[a.g.up[x] + (int64_t)(j - mbeg[i])];
+      const int64_t exy = a.g.up[x] + (int64_t)(j - mbeg[i]);
+      const int32_t y = a.g.col[exy];
       in = gen_in(a.g, flag, lo, hi, fbase, y);
+      if constexpr (R == 2) in = in && dead[exy] == 0;
       p = F[f];
 #pragma unroll
       for (int q = 0; q < R; q++) Rv[q] = fv[(int64_t)f * R + q];
@@ -1762,7 +1790,7 @@ __global__ __launch_bounds__(256) void k_gen_apply(PeelArgs base, RoundCtl *rc,
       merge_rq<R, 2>(Rv, Qv, Sv, rmask);
       update_func<R, S, true>(a, Sv, rmask, p, in, ls, ap);
     } else {
-      if (in) gen_extend<2, R, S>(a, flag, lo, hi, fbase, Rv, Qv, p, ls);
+      if (in) gen_extend<2, R, S>(a, flag, lo, hi, fbase, Rv, Qv, p, ls, dead);
     }
   }
   ap[0].flush();
@@ -1773,6 +1801,26 @@ __global__ __launch_bounds__(256) void k_gen_apply(PeelArgs base, RoundCtl *rc,
   if (ls.err) atomicOr(&a.ctr->err, ls.err);
 }
 
+// r = 2, end of the round's update: the frontier's edges become dead for
+// the candidate tests of later rounds (both arc directions).
+__global__ __launch_bounds__(256) void k_gen_retire2(GraphView g, const RoundCtl *rc,
+                                                     const int32_t *__restrict__ fv,
+                                                     uint8_t *dead) {
+  if (rc_idle(rc)) return;
+  const uint32_t nF = rc->nF;
+  for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nF;
+       f += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t a = fv[f * 2], b = fv[f * 2 + 1];
+    const int64_t e = arc_pos(g, a, b);
+    if (e < 0) continue;
+    const int32_t lo = a < b ? a : b, hi = a < b ? b : a;
+    dead[e] = 1;
+    const int64_t r0 = g.rp[hi], r1 = g.up[hi];  // lo sits in hi's lower part
+    const int64_t q = lower_pos(g.col, r0, r1, lo);
+    if (q < r1 && g.col[q] == lo) dead[q] = 1;
+  }
+}
+
 dim3 blocks_for(uint64_t n, uint64_t per, uint64_t lo, uint64_t hi) {
   uint64_t b = (n + per - 1) / per;
   b = b < lo ? lo : b;
@@ -1780,7 +1828,8 @@ dim3 blocks_for(uint64_t n, uint64_t per, uint64_t lo, uint64_t hi) {
   return dim3((unsigned)b);
 }
 
-// Buffers and launch parameters of one peel loop.
+// Buffers and launch parameters of one peel loop.  Every device buffer is a
+// DevBuf taken from the run's workspace; peel_ws_bytes adds up the same list.
 struct Engine {
   int r = 0, s = 0, path = 0;
   GraphView gv{};
@@ -1790,7 +1839,7 @@ struct Engine {
   Counters *dc = nullptr;
   unsigned long long *stats = nullptr;
   hipStream_t st = nullptr;
-  DevBuf<RoundCtl> rc;
+  RoundCtl *rc = nullptr;  // owned by the plan
   DevBuf<uint32_t> lists;  // F, F', W, W', H, H' (n_r each)
   DevBuf<uint64_t> off;    // per frontier entry: first record / flag
   DevBuf<uint32_t> len;    // per frontier entry: records / flags
@@ -1804,6 +1853,7 @@ struct Engine {
   DevBuf<uint32_t> owner;  // s >= r+2: frontier index of each candidate
   DevBuf<uint64_t> mbeg;   // s >= r+2: first out-arc of each member
   DevBuf<uint32_t> aown;   // s >= r+2: member of each out-arc
+  DevBuf<uint8_t> dead;    // s >= r+2, r = 2: per arc position, edge peeled earlier
   uint64_t cap3 = 0;
   DevBuf<uint32_t> tsize, tk;
   uint64_t cap = 0;
@@ -1813,25 +1863,25 @@ struct Engine {
 template <int R, int S>
 void launch_walker(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, hipEvent_t e0,
                    hipEvent_t e1) {
-  hipLaunchKernelGGL(k_stamp, gf, dim3(256), 0, E.st, E.rc.get(), E.T.slots);
+  hipLaunchKernelGGL(k_stamp, gf, dim3(256), 0, E.st, E.rc, E.T.slots);
   if (e0) hipEventRecord(e0, E.st);
-  hipLaunchKernelGGL((k_peel<R, S>), gw, dim3(256), 0, E.st, base, E.rc.get());
+  hipLaunchKernelGGL((k_peel<R, S>), gw, dim3(256), 0, E.st, base, E.rc);
   if (e1) hipEventRecord(e1, E.st);
 }
 
 template <int R>
 void launch_fast(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, dim3 ga, hipEvent_t e0,
                  hipEvent_t e1) {
-  hipLaunchKernelGGL(k_expand_bound<R>, gf, dim3(256), 0, E.st, base, E.rc.get(), E.fxv, E.loc,
+  hipLaunchKernelGGL(k_expand_bound<R>, gf, dim3(256), 0, E.st, base, E.rc, E.fxv, E.loc,
                      E.off.get(), E.len.get(), E.fv.get(), E.desc.get(), E.f23.get());
-  hipLaunchKernelGGL(k_expand<R>, gw, dim3(256), 0, E.st, base, E.rc.get(), E.fxv, E.desc.get(),
+  hipLaunchKernelGGL(k_expand<R>, gw, dim3(256), 0, E.st, base, E.rc, E.fxv, E.desc.get(),
                      E.off.get(), E.len.get(), E.fv.get(), E.rec.get(), E.rloc.get());
   if (e0) hipEventRecord(e0, E.st);
   if constexpr (R == 3)
-    hipLaunchKernelGGL(k_apply3, ga, dim3(256), 0, E.st, base, E.rc.get(), E.rec.get(),
+    hipLaunchKernelGGL(k_apply3, ga, dim3(256), 0, E.st, base, E.rc, E.rec.get(),
                        E.fv.get(), E.fxv, E.loc, E.rloc.get(), E.f23.get());
   else
-    hipLaunchKernelGGL(k_apply<R>, ga, dim3(256), 0, E.st, base, E.rc.get(), E.rec.get(),
+    hipLaunchKernelGGL(k_apply<R>, ga, dim3(256), 0, E.st, base, E.rc, E.rec.get(),
                        E.fv.get(), E.fxv, E.loc, E.rloc.get(), E.f23.get());
   if (e1) hipEventRecord(e1, E.st);
 }
@@ -1839,18 +1889,21 @@ void launch_fast(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, dim3 ga, hip
 template <int R, int S>
 void launch_gen(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, dim3 gc, dim3 ga,
                 hipEvent_t e0, hipEvent_t e1) {
-  hipLaunchKernelGGL(k_gen_bound<R>, gf, dim3(256), 0, E.st, base, E.rc.get(), E.off.get(),
+  hipLaunchKernelGGL(k_gen_bound<R>, gf, dim3(256), 0, E.st, base, E.rc, E.off.get(),
                      E.len.get(), E.fv.get(), E.drv.get());
-  hipLaunchKernelGGL(k_gen_spread, gw, dim3(256), 0, E.st, E.rc.get(), E.off.get(), E.len.get(),
+  hipLaunchKernelGGL(k_gen_spread, gw, dim3(256), 0, E.st, E.rc, E.off.get(), E.len.get(),
                      E.owner.get());
-  hipLaunchKernelGGL(k_gen_member<R>, gc, dim3(256), 0, E.st, E.gv, E.rc.get(), E.off.get(),
+  hipLaunchKernelGGL(k_gen_member<R>, gc, dim3(256), 0, E.st, E.gv, E.rc, E.off.get(),
                      E.owner.get(), E.fv.get(), E.drv.get(), E.flag.get(), E.rec.get(),
-                     E.mbeg.get(), E.aown.get());
+                     E.mbeg.get(), E.aown.get(), E.dead.get());
   if (e0) hipEventRecord(e0, E.st);
-  hipLaunchKernelGGL((k_gen_apply<R, S>), ga, dim3(256), 0, E.st, base, E.rc.get(), E.off.get(),
+  hipLaunchKernelGGL((k_gen_apply<R, S>), ga, dim3(256), 0, E.st, base, E.rc, E.off.get(),
                      E.fv.get(), E.drv.get(), E.flag.get(), E.rec.get(), E.mbeg.get(),
-                     E.aown.get());
+                     E.aown.get(), E.dead.get());
   if (e1) hipEventRecord(e1, E.st);
+  if constexpr (R == 2)
+    hipLaunchKernelGGL(k_gen_retire2, gf, dim3(256), 0, E.st, E.gv, E.rc, E.fv.get(),
+                       E.dead.get());
 }
 
 #define ND_WALK(R_, S_) \
@@ -1864,7 +1917,7 @@ void launch_gen(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, dim3 gc, dim3
 void enqueue_round(Engine &E, const RoundCtl &m, bool exact, hipEvent_t e0, hipEvent_t e1,
                    hipEvent_t e_adv) {
   const hipStream_t st = E.st;
-  RoundCtl *rc = E.rc.get();
+  RoundCtl *rc = E.rc;
   // r = 3 on the s = r+1 path: frontier marks at selection
   const bool r3 = E.path == 1 && E.r == 3;
   if (!exact || m.nF == 0) {
@@ -1920,12 +1973,6 @@ void enqueue_round(Engine &E, const RoundCtl &m, bool exact, hipEvent_t e0, hipE
   hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, st, rc, E.dc);
 }
 
-template <class T>
-void set_field(RoundCtl *rc, size_t offset, T value, hipStream_t st) {
-  hipMemcpyAsync((char *)rc + offset, &value, sizeof(T), hipMemcpyHostToDevice, st);
-  hipStreamSynchronize(st);
-}
-
 void alloc_records(Engine &E, uint64_t cap) {
   E.rec.reset(cap);
   E.rloc.reset(E.path == 1 && E.r == 3 ? cap : 1);
@@ -1933,36 +1980,59 @@ void alloc_records(Engine &E, uint64_t cap) {
     E.flag.reset(cap);
     E.owner.reset(cap);
     E.mbeg.reset(cap);
+    E.cap3 = kArcsPerRecord * cap;
+    E.aown.reset(E.cap3);
   }
   E.cap = cap;
 }
-
-constexpr int kMaxDepth = 32;
 
 // Most rounds queued between two reads of the round state (ND_PEEL_DEPTH,
 // 1..32, default 32).
 int max_depth() {
   const char *e = getenv("ND_PEEL_DEPTH");
-  const int d = e ? atoi(e) : kMaxDepth;
-  return d < 1 ? 1 : (d > kMaxDepth ? kMaxDepth : d);
+  const int d = e ? atoi(e) : kPeelMaxDepth;
+  return d < 1 ? 1 : (d > kPeelMaxDepth ? kPeelMaxDepth : d);
 }
 
 }  // namespace
 
+uint64_t peel_ws_bytes(int r, int path, uint64_t n_r, uint64_t nnz, uint64_t rec_cap,
+                       uint32_t trace_cap) {
+  if (n_r == 0) return ws_buf<uint32_t>(1);  // the empty round trace
+  uint64_t b = ws_buf<uint32_t>(6 * n_r) + ws_buf<uint64_t>(n_r) + ws_buf<uint32_t>(n_r) +
+               ws_buf<int32_t>(n_r * (uint64_t)r);
+  if (path == 2) b += ws_buf<int32_t>(n_r);
+  if (path == 2 && r == 2) b += ws_buf<uint8_t>(nnz ? nnz : 1);
+  if (path == 1) b += ws_buf<ExpandDesc>(n_r) + ws_buf<uint32_t>(r == 3 ? n_r : 1);
+  if (path != 0) {
+    b += ws_buf<int2>(rec_cap) + ws_buf<uint16_t>(path == 1 && r == 3 ? rec_cap : 1);
+    if (path == 2)
+      b += ws_buf<uint8_t>(rec_cap) + ws_buf<uint32_t>(rec_cap) + ws_buf<uint64_t>(rec_cap) +
+           ws_buf<uint32_t>(kArcsPerRecord * rec_cap);
+  }
+  return b + 2 * ws_buf<uint32_t>(trace_cap);
+}
+
 uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableView &T,
                   const FastIndex *fx, const uint32_t *occ, uint64_t n_r, Counters *dc,
-                  unsigned long long *stats, bool timing, hipStream_t st, hipEvent_t ev_first,
+                  unsigned long long *stats, const PeelState &ps, uint64_t rec_cap,
+                  uint32_t trace_cap, hipStream_t st, hipEvent_t ev_first,
                   DevBuf<uint32_t> *kround, PeelResult *res) {
   res->sizes.clear();
   res->levels.clear();
   res->advances = 0;
   res->apply_ms = 0;
   res->apply_launches = 0;
+  res->need_rec = 0;
+  res->need_trace = 0;
+  res->max_rec = 0;
+  res->max_arcs = 0;
   if (n_r == 0) {
     if (ev_first) hipEventRecord(ev_first, st);
     kround->reset(1);
     return 0;
   }
+  const bool timing = ps.ev != nullptr;
   Engine E;
   E.r = r;
   E.s = s;
@@ -1976,29 +2046,29 @@ uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableVie
   E.dc = dc;
   E.stats = stats;
   E.st = st;
-  E.rc.reset(1);
+  E.rc = ps.rc;
   E.lists.reset(6 * n_r);
   uint32_t *L = E.lists.get();
-  hipMemcpyAsync(L + 4 * n_r, occ, 4 * n_r, hipMemcpyDeviceToDevice, st);  // H = every r-clique
+  // H = every r-clique
+  if (hipMemcpyAsync(L + 4 * n_r, occ, 4 * n_r, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return kErrRuntime;
   E.off.reset(n_r);
   E.len.reset(n_r);
   E.fv.reset(n_r * (uint64_t)r);
   if (path == 2) E.drv.reset(n_r);
+  if (path == 2 && r == 2) {
+    const uint64_t na = g.nnz > 0 ? (uint64_t)g.nnz : 1;
+    E.dead.reset(na);
+    fill_u32((uint32_t *)E.dead.get(), 0, (int64_t)(ws_block(na) / 4), st);
+  }
   if (path == 1) {
     E.desc.reset(n_r);
     E.f23.reset(r == 3 ? n_r : 1);
   }
-  // initial capacities; ND_PEEL_CAP / ND_PEEL_TRACE_CAP override them (small
-  // values exercise the grow-and-rerun path)
-  uint64_t cap0 = n_r > (1u << 20) ? n_r : (1u << 20);
-  E.tcap = 1024;
-  if (const char *e = getenv("ND_PEEL_CAP")) cap0 = strtoull(e, nullptr, 10) > 0 ? strtoull(e, nullptr, 10) : cap0;
-  if (const char *e = getenv("ND_PEEL_TRACE_CAP")) E.tcap = atoi(e) > 0 ? (uint32_t)atoi(e) : E.tcap;
-  if (path != 0) alloc_records(E, cap0);
-  if (path == 2) {
-    E.cap3 = 4 * E.cap;
-    E.aown.reset(E.cap3);
-  }
+  // capacities fixed by the workspace layout: a round that needs more stops
+  // the peel and reports what it needs
+  E.tcap = trace_cap;
+  if (path != 0) alloc_records(E, rec_cap);
   E.tsize.reset(E.tcap);
   E.tk.reset(E.tcap);
 
@@ -2018,14 +2088,12 @@ uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableVie
   h.nH = (uint32_t)n_r;
   h.mw = kNone;
   h.mh = kNone;
-  hipMemcpyAsync(E.rc.get(), &h, sizeof(h), hipMemcpyHostToDevice, st);
-
-  RoundCtl *mirror = nullptr;
-  if (hipHostMalloc((void **)&mirror, sizeof(RoundCtl), hipHostMallocDefault) != hipSuccess)
-    throw OutOfMemory{};
-  hipEvent_t ev[2 * kMaxDepth] = {};
-  if (timing)
-    for (auto &e : ev) hipEventCreate(&e);
+  RoundCtl *mirror = ps.mirror;
+  *mirror = h;  // staged through pinned memory: the copy is asynchronous
+  if (hipMemcpyAsync(E.rc, mirror, sizeof(h), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return kErrRuntime;
+  hipEvent_t *ev = ps.ev;
   uint32_t status = 0;
   RoundCtl m = h;
   int depth = 1;
@@ -2038,8 +2106,8 @@ uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableVie
                     first && d == 0 ? ev_first : nullptr);
     }
     first = false;
-    hipMemcpyAsync(mirror, E.rc.get(), sizeof(RoundCtl), hipMemcpyDeviceToHost, st);
-    if (hipStreamSynchronize(st) != hipSuccess) {
+    if (hipMemcpyAsync(mirror, E.rc, sizeof(RoundCtl), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
       status = kErrRuntime;
       break;
     }
@@ -2055,49 +2123,17 @@ uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableVie
       status = m.err;
       break;
     }
-    if (m.halt == 1) {  // grow the record buffers and run the round again
-      uint64_t want = m.need + m.need / 4;
-      if (want < 2 * E.cap) want = 2 * E.cap;
-      E.rec.release();
-      E.rloc.release();
-      E.flag.release();
-      E.owner.release();
-      E.mbeg.release();
-      alloc_records(E, want);
-      set_field(E.rc.get(), offsetof(RoundCtl, cap), E.cap, st);
-      set_field(E.rc.get(), offsetof(RoundCtl, halt), 0u, st);
-      m.cap = E.cap;
-      m.halt = 0;
-      depth = 1;
-      continue;
-    }
-    if (m.halt == 4) {  // grow the out-arc buffer and run the round again
-      uint64_t want = m.need + m.need / 4;
-      if (want < 2 * E.cap3) want = 2 * E.cap3;
-      E.aown.release();
-      E.aown.reset(want);
-      E.cap3 = want;
-      set_field(E.rc.get(), offsetof(RoundCtl, cap3), E.cap3, st);
-      set_field(E.rc.get(), offsetof(RoundCtl, halt), 0u, st);
-      m.cap3 = E.cap3;
-      m.halt = 0;
-      depth = 1;
-      continue;
-    }
-    if (m.halt == 2) {  // grow the round trace
-      const uint32_t nt = E.tcap * 2;
-      DevBuf<uint32_t> ns(nt), nk(nt);
-      hipMemcpyAsync(ns.get(), E.tsize.get(), 4ull * E.tcap, hipMemcpyDeviceToDevice, st);
-      hipMemcpyAsync(nk.get(), E.tk.get(), 4ull * E.tcap, hipMemcpyDeviceToDevice, st);
-      E.tsize = std::move(ns);
-      E.tk = std::move(nk);
-      E.tcap = nt;
-      set_field(E.rc.get(), offsetof(RoundCtl, trace_size), E.tsize.get(), st);
-      set_field(E.rc.get(), offsetof(RoundCtl, trace_k), E.tk.get(), st);
-      set_field(E.rc.get(), offsetof(RoundCtl, trace_cap), E.tcap, st);
-      set_field(E.rc.get(), offsetof(RoundCtl, halt), 0u, st);
-      m.halt = 0;
-      continue;
+    if (m.halt == 1 || m.halt == 4 || m.halt == 2) {
+      // a round outgrew the workspace: nothing of it has been applied; report
+      // the capacity it needs (records, arcs in units of kArcsPerRecord
+      // records, or round-trace entries)
+      if (m.halt == 1) res->need_rec = m.need;
+      if (m.halt == 4) res->need_rec = (m.need + kArcsPerRecord - 1) / kArcsPerRecord;
+      if (m.halt == 2) res->need_trace = 2ull * E.tcap;
+      res->max_rec = m.max_total;
+      res->max_arcs = m.max_total3;
+      status = kErrCapacity;
+      break;
     }
     if (m.halt) {
       status = kErrBucket;
@@ -2111,18 +2147,20 @@ uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableVie
     else if (dt < 2.0 && depth < dmax) depth = depth * 2 < dmax ? depth * 2 : dmax;
     else if (dt > 20.0 && depth > 1) depth /= 2;
   }
-  if (timing)
-    for (auto &e : ev) hipEventDestroy(e);
-  hipHostFree(mirror);
   if (status) return status;
   res->advances = m.advances;
+  res->max_rec = m.max_total;
+  res->max_arcs = m.max_total3;
   res->apply_launches = m.t;
   std::vector<uint32_t> sz(m.t);
   res->levels.resize(m.t);
   if (m.t) {
-    hipMemcpyAsync(sz.data(), E.tsize.get(), 4ull * m.t, hipMemcpyDeviceToHost, st);
-    hipMemcpyAsync(res->levels.data(), E.tk.get(), 4ull * m.t, hipMemcpyDeviceToHost, st);
-    hipStreamSynchronize(st);
+    if (hipMemcpyAsync(sz.data(), E.tsize.get(), 4ull * m.t, hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(res->levels.data(), E.tk.get(), 4ull * m.t, hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return kErrRuntime;
   }
   res->sizes.assign(sz.begin(), sz.end());
   *kround = std::move(E.tk);

@@ -263,6 +263,21 @@ void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_
   scan_impl<uint32_t>(in, out, n, st);
 }
 
+uint64_t scan_ws_bytes(int64_t n, size_t elem) {
+  if (n <= 0) return 0;
+  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  if (nb == 1) return 0;
+  return ws_block((uint64_t)nb * elem) + scan_ws_bytes(nb, elem);
+}
+
+uint64_t radix_sort_ws_bytes(int64_t n, int bits, int lo_bit, bool vals) {
+  if (n <= 1 || bits <= lo_bit) return 0;
+  const int passes = (bits - lo_bit + 7) / 8;
+  const int64_t nb = (n + kSortTile - 1) / kSortTile;
+  return ws_buf<uint64_t>((uint64_t)n) + (vals ? ws_buf<uint32_t>((uint64_t)n) : 0) +
+         ws_buf<uint32_t>((uint64_t)(256 * nb)) + (uint64_t)passes * scan_ws_bytes(256 * nb, 4);
+}
+
 void radix_sort(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t st,
                 int lo_bit) {
   if (n <= 1 || bits <= lo_bit) return;

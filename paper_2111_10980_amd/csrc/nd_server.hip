@@ -1,17 +1,25 @@
 // Serving loop: continuous batching of (graph, r, s) decomposition jobs.
 //
 // A fixed pool of worker threads, each with its own HIP stream, takes jobs
-// from one FIFO queue.  A job is admitted when a worker is idle and its
-// device-memory estimate fits the remaining budget (a job larger than the
-// whole budget runs alone).  An admitted job keeps its plan — oriented
-// graph, r-clique table, bucket state — on the device until its last round,
-// and the rounds of the jobs in flight interleave on the GPU through their
-// streams; a job that arrives while others run starts as soon as a slot and
-// memory are free, instead of waiting for the GPU to drain.  Results stay on
-// the device until the caller releases them.
+// from one FIFO queue.  Admission is by the device-memory budget, in two
+// steps.  A job at the head of the queue starts its plan when a worker is
+// idle and its estimate fits what is left of the budget.  The estimate is
+// computed from the graph's size, scaled by the largest ratio of exact to
+// estimated bytes seen so far for its (r, s).  Once the plan exists, the job
+// holds exactly its plan's bytes, its run's workspace and its outputs
+// (nd_plan_sizes).  When that exact figure does not fit, the job destroys
+// its plan and waits at the head of the queue for the exact figure.  A job
+// larger than the whole budget runs alone.  An admitted job keeps its plan
+// (oriented graph, r-clique table, bucket state) on the device until its
+// last round.  The rounds of the jobs in flight interleave on the GPU
+// through their streams.  A job that arrives while others run starts as
+// soon as a slot and memory are free, instead of waiting for the GPU to
+// drain.  Results stay on the device until the caller releases them, and
+// their bytes count against the budget until then.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -32,7 +40,11 @@ struct Job {
   nd_csr g{};
   int r = 0, s = 0;
   nd_options opt{};
-  uint64_t est = 0;
+  hipEvent_t ready = nullptr;  // recorded on the caller's stream at submit
+  uint64_t est_raw = 0;        // size-only estimate
+  uint64_t exact = 0;          // plan + workspace + outputs, once known
+  uint64_t held = 0;           // bytes counted against the budget right now
+  uint64_t out_bytes = 0;      // outputs, counted until release
   nd_status st = ND_OK;
   std::string err;
   bool done = false;
@@ -41,6 +53,7 @@ struct Job {
   uint32_t *kappa = nullptr;
   hipStream_t stream = nullptr;  // stream its outputs were allocated on
   nd_stats stats{};
+  uint32_t requeues = 0;
   Clock::time_point t_submit, t_start, t_end;
 };
 
@@ -67,29 +80,113 @@ struct nd_server_s {
   std::vector<std::thread> workers;
   std::vector<hipStream_t> streams;
   int running = 0;
+  double scale[ND_MAX_S + 1][ND_MAX_S + 1];  // exact / estimate seen per (r, s)
+  nd_server_s() {
+    for (auto &row : scale)
+      for (auto &x : row) x = 1.0;
+  }
+  // bytes the head job asks for at admission (under mu)
+  uint64_t want(const Job *j) const {
+    if (j->exact) return j->exact;
+    const double x = (double)j->est_raw * scale[j->r][j->s];
+    return x > 1.8e19 ? UINT64_MAX : (uint64_t)x;
+  }
+  // whether `extra` more bytes fit the budget (under mu); alone = no other job holds memory
+  bool fits(uint64_t extra, bool alone) const {
+    return budget == 0 || in_use + extra <= budget || alone;
+  }
 };
 
-static void run_job(Job *j, hipStream_t st) {
+// Runs one admitted job on stream st.  Returns false when the job gave its
+// memory back and went to the head of the queue again (its exact figure did
+// not fit the budget).
+static bool run_job(nd_server sv, Job *j, hipStream_t st) {
+  if (j->ready && hipStreamWaitEvent(st, j->ready, 0) != hipSuccess) {
+    hipGetLastError();
+    j->st = ND_EHIP;
+    j->err = "cannot order the job after the submitting stream";
+    return true;
+  }
   nd_plan plan = nullptr;
+  void *ws = nullptr;
   j->st = nd_plan_create(&j->g, j->r, j->s, &j->opt, 0, st, &plan);
-  if (j->st == ND_OK) {
-    uint64_t bytes = 0;
-    nd_plan_sizes(plan, &j->n_r, &bytes);
-    const size_t rb = (size_t)(j->n_r ? j->n_r : 1) * (size_t)j->r * 4;
-    const size_t kb = (size_t)(j->n_r ? j->n_r : 1) * 4;
-    if (hipMallocAsync((void **)&j->rcl, rb, st) != hipSuccess ||
-        hipMallocAsync((void **)&j->kappa, kb, st) != hipSuccess) {
-      hipGetLastError();
-      j->st = ND_ENOMEM;
-      j->err = "output allocation failed";
-    } else {
-      j->stream = st;
-      j->st = nd_run(plan, j->rcl, j->kappa, nullptr, &j->stats);
+  for (int attempt = 0; j->st == ND_OK; attempt++) {
+    uint64_t ws_bytes = 0, plan_bytes = 0;
+    nd_plan_sizes(plan, &j->n_r, &ws_bytes, &plan_bytes);
+    const uint64_t n1 = j->n_r ? j->n_r : 1;
+    j->out_bytes = n1 * (uint64_t)j->r * 4 + n1 * 4;
+    const uint64_t exact = plan_bytes + ws_bytes + j->out_bytes;
+    bool fit;
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      if (!j->exact && j->est_raw) {  // learn how far off the size-only estimate was
+        const double ratio = (double)exact / (double)j->est_raw;
+        double &sc = sv->scale[j->r][j->s];
+        sc = std::min(64.0, std::max(sc, ratio));
+      }
+      fit = exact <= j->held || sv->fits(exact - j->held, sv->running == 1);
+      if (fit) {
+        sv->in_use = sv->in_use - j->held + exact;
+        j->held = exact;
+      }
+      j->exact = exact;
     }
+    if (!fit) {
+      // free the plan first, then give the reservation back and wait at the
+      // head of the queue for the exact figure
+      nd_plan_destroy(plan);
+      if (ws) hipFreeAsync(ws, st);
+      if (j->rcl) hipFreeAsync(j->rcl, st);
+      if (j->kappa) hipFreeAsync(j->kappa, st);
+      j->rcl = nullptr;
+      j->kappa = nullptr;
+      hipStreamSynchronize(st);
+      {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->in_use -= j->held;
+        j->held = 0;
+        j->requeues++;
+        sv->running--;
+        sv->queue.push_front(j);
+      }
+      sv->cv_work.notify_all();
+      return false;
+    }
+    sv->cv_work.notify_all();  // a smaller exact figure frees budget for others
+    if (ws) hipFreeAsync(ws, st);
+    ws = nullptr;
+    if (!j->rcl) {
+      if (hipMallocAsync((void **)&j->rcl, n1 * (size_t)j->r * 4, st) != hipSuccess ||
+          hipMallocAsync((void **)&j->kappa, n1 * 4, st) != hipSuccess) {
+        hipGetLastError();
+        j->st = ND_ENOMEM;
+        j->err = "output allocation failed";
+        break;
+      }
+      j->stream = st;
+    }
+    if (hipMallocAsync(&ws, ws_bytes ? ws_bytes : 256, st) != hipSuccess) {
+      hipGetLastError();
+      ws = nullptr;
+      j->st = ND_ENOMEM;
+      j->err = "workspace allocation failed";
+      break;
+    }
+    j->st = nd_run(plan, ws, ws_bytes, j->rcl, j->kappa, nullptr, &j->stats);
+    uint64_t again = 0;
+    nd_plan_sizes(plan, nullptr, &again, nullptr);
+    // a round outgrew the workspace: the plan now reports a larger one
+    if (j->st == ND_ENOMEM && again > ws_bytes && attempt < 4) {
+      j->st = ND_OK;
+      continue;
+    }
+    break;
   }
   if (j->st != ND_OK && j->err.empty()) j->err = nd_last_error();
+  if (ws) hipFreeAsync(ws, st);
   if (plan) nd_plan_destroy(plan);
   hipStreamSynchronize(st);
+  return true;
 }
 
 static void worker_main(nd_server sv, int w) {
@@ -102,23 +199,26 @@ static void worker_main(nd_server sv, int w) {
       sv->cv_work.wait(lk, [&] {
         if (sv->stop) return true;
         if (sv->queue.empty()) return false;
-        const Job *h = sv->queue.front();
         // FIFO admission by the memory budget; an oversized job runs alone
-        return sv->budget == 0 || sv->in_use + h->est <= sv->budget || sv->running == 0;
+        return sv->fits(sv->want(sv->queue.front()), sv->running == 0);
       });
       if (sv->stop && sv->queue.empty()) return;
       if (sv->queue.empty()) continue;
       j = sv->queue.front();
       sv->queue.pop_front();
-      sv->in_use += j->est;
+      j->held = sv->want(j);
+      sv->in_use += j->held;
       sv->running++;
     }
-    j->t_start = Clock::now();
-    run_job(j, st);
+    if (j->requeues == 0) j->t_start = Clock::now();
+    if (!run_job(sv, j, st)) continue;  // back in the queue with its exact figure
     j->t_end = Clock::now();
     {
       std::lock_guard<std::mutex> lk(sv->mu);
-      sv->in_use -= j->est;
+      // the outputs stay counted until the job is released
+      const uint64_t keep = j->st == ND_OK ? std::min(j->out_bytes, j->held) : 0;
+      sv->in_use -= j->held - keep;
+      j->held = keep;
       sv->running--;
       j->done = true;
     }
@@ -154,7 +254,7 @@ nd_status nd_server_create(int32_t workers, uint64_t hbm_budget_bytes, nd_server
 }
 
 nd_status nd_server_submit(nd_server sv, const nd_csr *g, int r, int s, const nd_options *opt,
-                           uint64_t *job) {
+                           void *hip_stream, uint64_t *job) {
   if (!sv || !g || !job) return ND_EINVAL;
   if (r < 1 || s <= r || s > ND_MAX_S) return ND_EINVAL;
   Job *j = new (std::nothrow) Job();
@@ -163,11 +263,20 @@ nd_status nd_server_submit(nd_server sv, const nd_csr *g, int r, int s, const nd
   j->r = r;
   j->s = s;
   if (opt) j->opt = *opt;
-  j->est = estimate(*g, r);
+  j->est_raw = estimate(*g, r);
   j->t_submit = Clock::now();
+  // the job's first kernel waits for the work that produced the graph
+  if (hipEventCreateWithFlags(&j->ready, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(j->ready, (hipStream_t)hip_stream) != hipSuccess) {
+    hipGetLastError();
+    if (j->ready) hipEventDestroy(j->ready);
+    delete j;
+    return ND_EHIP;
+  }
   {
     std::lock_guard<std::mutex> lk(sv->mu);
     if (sv->stop) {
+      hipEventDestroy(j->ready);
       delete j;
       return ND_ESTATE;
     }
@@ -246,10 +355,14 @@ nd_status nd_server_release(nd_server sv, uint64_t job) {
     j = it->second;
     if (!j->done) return ND_ESTATE;
     sv->jobs.erase(it);
+    sv->in_use -= j->held;  // the outputs
+    j->held = 0;
   }
+  sv->cv_work.notify_all();
   if (j->rcl) hipFreeAsync(j->rcl, j->stream);
   if (j->kappa) hipFreeAsync(j->kappa, j->stream);
   if (j->stream) hipStreamSynchronize(j->stream);
+  if (j->ready) hipEventDestroy(j->ready);
   delete j;
   return ND_OK;
 }
@@ -267,6 +380,7 @@ nd_status nd_server_destroy(nd_server sv) {
     if (j->rcl) hipFreeAsync(j->rcl, j->stream);
     if (j->kappa) hipFreeAsync(j->kappa, j->stream);
     if (j->stream) hipStreamSynchronize(j->stream);
+    if (j->ready) hipEventDestroy(j->ready);
     delete j;
   }
   for (hipStream_t st : sv->streams) hipStreamDestroy(st);

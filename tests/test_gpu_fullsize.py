@@ -1,18 +1,24 @@
 """GPU results at the full sizes of the measured workloads, in the launch
 configuration bench.py times (default options, one decomposition of the
-whole graph), checked on sampled r-cliques the oracle can verify one by one:
+whole graph), compared EXACTLY with the oracle's run of the same input.
 
-- the initial count of a sampled R equals the oracle's count of the
-  s-cliques containing R (Algorithm 2, Count-Func);
-- the nucleus number k of a sampled R satisfies the local certificate of a
-  peeling result: at least k s-cliques containing R have every other
-  r-subset at level >= k, and at most k have every other r-subset at level
-  >= k+1 (Definition of the (r,s) nucleus; the fixed point the peel reaches);
-- global identities: sum of counts = C(s,r) * n_s, and the table holds each
-  r-clique once.
+The oracle takes minutes to hours on these inputs, so its results are
+stored once, by ``oracle/fullsize_golden.py`` (which imports only the
+oracle and the seeded generators), under ``tests/golden/fullsize_*.json``:
+the input's SHA-256, n_r, n_s, rho, every round's size |A_t| and level k_t,
+the maximum nucleus number, the total of decrements, and SHA-256 digests of
+the canonical output (rows in lexicographic order, initial counts, nucleus
+numbers).  The GPU run asks the library for the canonical row order
+(options.canonical), hashes the same bytes and must reproduce every field
+(Algorithm 2 returns each r-clique's nucleus number; rounds and their sizes
+follow from the bucket loop).
 
-Samples mix uniform draws with the r-cliques of the highest levels, where the
-deep rounds of the peel decide the value."""
+A few sampled r-cliques are also checked one by one against the oracle's
+own count of the s-cliques containing them (Count-Func), as an extra.
+"""
+import hashlib
+import json
+import os
 from math import comb
 
 import numpy as np
@@ -23,51 +29,74 @@ from paper_2111_10980_amd import inputs
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
 
 def _nd():
     import paper_2111_10980_amd as nd
     return nd
 
 
-def check_sampled(g, r, s, n_uniform=40, n_top=24, seed=0):
+def sha(a, dtype):
+    return hashlib.sha256(np.ascontiguousarray(a, dtype=dtype).tobytes()).hexdigest()
+
+
+def load_golden(name):
+    path = os.path.join(GOLDEN, f"fullsize_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not written yet (python oracle/fullsize_golden.py {name})")
+    return json.load(open(path))
+
+
+def check_exact(name, g, r, s, n_samples=16, seed=0):
     nd = _nd()
+    gold = load_golden(name)
+    assert (gold["r"], gold["s"]) == (r, s)
+    assert g.sha256() == gold["input_sha256"], "the generator no longer yields the stored input"
     rp, col = nd.to_device(g)
-    print(f"[fullsize] n={g.n} m={g.m} r={r} s={s}", flush=True)
-    d = nd.decompose(rp, col, r, s, with_counts=True)
+    print(f"[fullsize] {name}: n={g.n} m={g.m} r={r} s={s}", flush=True)
+    d = nd.decompose(rp, col, r, s, with_counts=True, canonical=True)
+    st = d.stats
+    print(f"[fullsize] n_r={st['n_r']} n_s={st['n_s']} rounds={st['rounds']} "
+          f"max kappa={st['max_kappa']}; hashing", flush=True)
+    assert st["n_r"] == gold["n_r"]
+    assert st["n_s"] == gold["n_s"]
+    assert st["rounds"] == gold["rounds"]
+    assert st["max_kappa"] == gold["max_kappa"]
+    assert st["decrements"] == gold["decrements"]
+    np.testing.assert_array_equal(d.round_sizes.astype(np.uint64),
+                                  np.asarray(gold["round_sizes"], dtype=np.uint64))
+    np.testing.assert_array_equal(d.round_levels.astype(np.uint64),
+                                  np.asarray(gold["round_k"], dtype=np.uint64))
+    assert sha(d.round_sizes, "<u4") == gold["round_sizes_sha256"]
+    assert sha(d.round_levels, "<u4") == gold["round_k_sha256"]
     rcl = d.rcliques.cpu().numpy()
     kap = d.kappa.cpu().numpy().view(np.uint32)
     cnt = d.counts.cpu().numpy().view(np.uint32)
-    n_r = rcl.shape[0]
-    assert n_r == d.stats["n_r"]
-    assert int(cnt.astype(np.uint64).sum()) == comb(s, r) * d.stats["n_s"]
-    assert (np.diff(np.sort(rcl, axis=1), axis=1) > 0).all()  # r distinct vertices
-    print(f"[fullsize] n_r={n_r} n_s={d.stats['n_s']} max kappa={int(kap.max())}; "
-          "building the lookup table", flush=True)
-    table = oracle.KappaTable(g.n, rcl, kap)
-    assert (np.diff(table.tab, axis=0) != 0).any(axis=1).all()  # no r-clique twice
+    hist_k, hist_n = np.unique(kap, return_counts=True)
+    assert [[int(a), int(b)] for a, b in zip(hist_k, hist_n)] == gold["kappa_hist"]
+    assert sha(rcl, "<i4") == gold["rows_sha256"]
+    assert sha(cnt, "<u4") == gold["counts_sha256"]
+    assert sha(kap, "<u4") == gold["kappa_sha256"]
+    assert int(cnt.astype(np.uint64).sum()) == comb(s, r) * st["n_s"]
     rng = np.random.default_rng(seed)
-    pick = list(rng.choice(n_r, size=min(n_uniform, n_r), replace=False))
-    pick += list(np.argsort(kap, kind="stable")[-n_top:])
-    for i in pick:
+    for i in rng.choice(rcl.shape[0], size=min(n_samples, rcl.shape[0]), replace=False):
         R = [int(v) for v in rcl[i]]
-        k = int(kap[i])
         assert oracle.count_one(g.n, g.row_ptr, g.col, r, s, R) == int(cnt[i]), R
-        assert oracle.support_at(g.n, g.row_ptr, g.col, r, s, table, R, k) >= k, (R, k)
-        assert oracle.support_at(g.n, g.row_ptr, g.col, r, s, table, R, k + 1) <= k, (R, k)
     return d
 
 
 def test_rmat18_34_full():
     """rMAT scale 18, edge factor 16, (3,4): the single-graph workload."""
-    check_sampled(inputs.rmat18(), 3, 4)
+    check_exact("rmat18_34", inputs.rmat18(), 3, 4)
 
 
 def test_chung_lu_1m_45_full():
     """Chung-Lu n = 1e6 with 200 planted cliques of 20-60 vertices, (4,5)."""
-    check_sampled(inputs.chung_lu_1m(), 4, 5)
+    check_exact("chunglu1m_45", inputs.chung_lu_1m(), 4, 5)
 
 
 def test_chung_lu_1m_24_full():
     """The same graph, (2,4): edges of the planted cliques reach the deepest
     levels of the peel."""
-    check_sampled(inputs.chung_lu_1m(), 2, 4)
+    check_exact("chunglu1m_24", inputs.chung_lu_1m(), 2, 4)

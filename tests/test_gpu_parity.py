@@ -287,11 +287,46 @@ def test_key_width_rejected():
 
 
 def test_budget_rejected():
+    """A budget below what the plan and its run's workspace need fails at plan
+    creation, once n_r is known and before the table is allocated."""
     nd = _nd()
     rp, col = nd.to_device(inputs.rmat(10, 8, 3))
     with pytest.raises(nd.NdError) as e:
         nd.decompose(rp, col, 3, 4, hbm_budget_bytes=4096)
     assert e.value.name == "ND_ENOMEM"
+    plan = nd.nd_plan_create(rp, col, 3, 4)
+    _, ws, held = nd.nd_plan_sizes(plan)
+    nd.nd_plan_destroy(plan)
+    # just below the plan + workspace need: refused; at the need: accepted
+    with pytest.raises(nd.NdError) as e:
+        nd.nd_plan_create(rp, col, 3, 4, hbm_budget_bytes=held + ws - 1)
+    assert e.value.name == "ND_ENOMEM"
+    plan = nd.nd_plan_create(rp, col, 3, 4, hbm_budget_bytes=held + ws)
+    nd.nd_plan_destroy(plan)
+
+
+def test_workspace_too_small_rejected_before_any_kernel():
+    """nd_run refuses a workspace below nd_plan_sizes' figure with ND_ENOMEM
+    and leaves the outputs untouched (no kernel ran)."""
+    nd = _nd()
+    import torch
+    g = inputs.rmat(9, 8, 4)
+    rp, col = nd.to_device(g)
+    plan = nd.nd_plan_create(rp, col, 3, 4)
+    try:
+        n_r, ws_bytes, _ = nd.nd_plan_sizes(plan)
+        rcl = torch.full((n_r, 3), -7, dtype=torch.int32, device="cuda")
+        kap = torch.full((n_r,), -7, dtype=torch.int32, device="cuda")
+        ws = nd.workspace(ws_bytes)
+        with pytest.raises(nd.NdError) as e:
+            nd.nd_run(plan, ws, rcl, kap, ws_bytes=ws_bytes - 1)
+        assert e.value.name == "ND_ENOMEM"
+        torch.cuda.synchronize()
+        assert int((rcl != -7).sum()) == 0 and int((kap != -7).sum()) == 0
+        st = nd.nd_run(plan, ws, rcl, kap, ws_bytes=ws_bytes)
+        assert st["workspace_bytes"] == ws_bytes  # the reported size is what a run carves
+    finally:
+        nd.nd_plan_destroy(plan)
 
 
 def test_plan_lifecycle():
@@ -299,17 +334,24 @@ def test_plan_lifecycle():
     import torch
     rp, col = nd.to_device(inputs.worked_example())
     plan = nd.nd_plan_create(rp, col, 3, 4)
-    n_r, nbytes = nd.nd_plan_sizes(plan)
-    assert n_r == 14 and nbytes > 0
+    n_r, ws_bytes, held = nd.nd_plan_sizes(plan)
+    assert n_r == 14 and ws_bytes > 0 and held > 0
     with pytest.raises(nd.NdError) as e:
         nd.nd_round_trace(plan)
     assert e.value.name == "ND_ESTATE"
     rcl = torch.empty((n_r, 3), dtype=torch.int32, device="cuda")
     kap = torch.empty((n_r,), dtype=torch.int32, device="cuda")
-    nd.nd_run(plan, rcl, kap)
-    with pytest.raises(nd.NdError) as e:
-        nd.nd_run(plan, rcl, kap)
-    assert e.value.name == "ND_ESTATE"
+    ws = nd.workspace(ws_bytes)
+    nd.nd_run(plan, ws, rcl, kap)
+    first = (rcl.cpu().numpy().copy(), kap.cpu().numpy().copy())
+    sizes, levels = nd.nd_round_trace(plan)
+    assert sizes.tolist() == [1, 3, 10] and levels.tolist() == [0, 1, 2]
+    # a plan runs again from its table and gives the same result
+    rcl.fill_(-1)
+    kap.fill_(-1)
+    nd.nd_run(plan, ws, rcl, kap)
+    assert np.array_equal(rcl.cpu().numpy(), first[0])
+    assert np.array_equal(kap.cpu().numpy(), first[1])
     sizes, levels = nd.nd_round_trace(plan)
     assert sizes.tolist() == [1, 3, 10] and levels.tolist() == [0, 1, 2]
     nd.nd_plan_destroy(plan)
@@ -317,13 +359,67 @@ def test_plan_lifecycle():
 
 
 @pytest.mark.parametrize("r,s", [(3, 4), (2, 4), (1, 3), (2, 3), (3, 5)])
-def test_round_buffers_grow_and_rerun(r, s, monkeypatch):
-    """Tiny initial record / arc / round-trace capacities: rounds halt, the
-    host grows the buffers and reruns them; results stay exact."""
-    monkeypatch.setenv("ND_PEEL_CAP", "64")
-    monkeypatch.setenv("ND_PEEL_TRACE_CAP", "2")
+def test_round_capacity_requery(r, s):
+    """Tiny record / out-arc / round-trace capacities: a round that outgrows
+    the workspace stops the run with ND_ENOMEM and the plan reports a larger
+    workspace; the run repeated with it is exact."""
+    nd = _nd()
+    import torch
     g = inputs.rmat(10, 8, 321)
-    check_against_oracle(g, r, s)
+    rp, col = nd.to_device(g)
+    plan = nd.nd_plan_create(rp, col, r, s, record_cap=64, trace_cap=2)
+    try:
+        n_r, ws0, _ = nd.nd_plan_sizes(plan)
+        rcl = torch.empty((n_r, r), dtype=torch.int32, device="cuda")
+        kap = torch.empty((n_r,), dtype=torch.int32, device="cuda")
+        with pytest.raises(nd.NdError) as e:
+            nd.nd_run(plan, nd.workspace(ws0), rcl, kap)
+        assert e.value.name == "ND_ENOMEM"
+        assert nd.nd_plan_sizes(plan)[1] > ws0
+    finally:
+        nd.nd_plan_destroy(plan)
+    check_against_oracle(g, r, s, record_cap=64, trace_cap=2)
+
+
+@pytest.mark.parametrize("r,s", [(3, 4), (2, 3), (2, 4), (4, 5), (1, 2)])
+def test_canonical_rows(r, s):
+    """options.canonical: rows come out in lexicographic order, equal to the
+    oracle's table row for row with no host-side sort."""
+    g = inputs.planted_er(300, 8.0, 3, 6, 12, 77)
+    rcl, kap, cnt, d = run_gpu(g, r, s, canonical=True)
+    ref = oracle.decompose(g.n, g.row_ptr, g.col, r, s)
+    np.testing.assert_array_equal(rcl, ref.rcliques)
+    np.testing.assert_array_equal(cnt.astype(np.uint64), ref.counts)
+    np.testing.assert_array_equal(kap.astype(np.uint64), ref.kappa)
+
+
+def test_canonical_two_keys():
+    """r vertices wider than 64 bits (r = 4, n > 2^16 ids): the canonical
+    sort runs on two keys."""
+    base = inputs.planted_er(400, 6.0, 3, 7, 12, 5)
+    g, _ = inputs.permute(inputs.disjoint_union([base, inputs.erdos_renyi(70000, 1000, 6)]), 8)
+    rcl, kap, cnt, d = run_gpu(g, 4, 5, canonical=True)
+    ref = oracle.decompose(g.n, g.row_ptr, g.col, 4, 5)
+    np.testing.assert_array_equal(rcl, ref.rcliques)
+    np.testing.assert_array_equal(kap.astype(np.uint64), ref.kappa)
+
+
+def test_count_bias_overflow():
+    """options.debug_count_bias drives the 32-bit range check of the initial
+    counts: a bias that lifts the largest count past UINT32_MAX gives
+    ND_EOVERFLOW, one that reaches it exactly does not (and changes nothing)."""
+    nd = _nd()
+    g = inputs.planted_er(200, 6.0, 2, 8, 12, 9)
+    ref = oracle.decompose(g.n, g.row_ptr, g.col, 3, 4)
+    top = int(ref.counts.max())
+    rp, col = nd.to_device(g)
+    with pytest.raises(nd.NdError) as e:
+        nd.decompose(rp, col, 3, 4, debug_count_bias=(1 << 32) - top)
+    assert e.value.name == "ND_EOVERFLOW"
+    check_against_oracle(g, 3, 4, debug_count_bias=(1 << 32) - 1 - top)
+    with pytest.raises(nd.NdError) as e:  # the generic (Count-Func atomics) path too
+        nd.decompose(rp, col, 3, 4, generic=True, debug_count_bias=(1 << 32) - top)
+    assert e.value.name == "ND_EOVERFLOW"
 
 
 @pytest.mark.parametrize("depth", ["1", "4"])
