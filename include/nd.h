@@ -147,6 +147,25 @@ nd_status nd_plan_sizes(nd_plan p, uint64_t *n_r, uint64_t *workspace_bytes,
 nd_status nd_run(nd_plan p, void *workspace_dev, uint64_t workspace_bytes, int32_t *rcliques_dev,
                  uint32_t *kappa_dev, uint32_t *counts_dev, nd_stats *stats);
 
+/* Bytes of the static device workspace nd_run_noalloc uses (64 MiB). */
+#define ND_NOALLOC_WORKSPACE_BYTES (64ull << 20)
+
+/* nd_run for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same run, with the workspace taken from one static device array of
+ * ND_NOALLOC_WORKSPACE_BYTES that the library holds on every GPU it runs on
+ * until the process ends, instead of a caller buffer.  It calls no hipMalloc,
+ * hipFree or other allocating routine.  Arguments and outputs as nd_run;
+ * call it with the plan's device current.  Errors: ND_ENOMEM when the plan
+ * needs a larger workspace than the static one (nd_plan_sizes tells), or
+ * when a round outgrows it as in nd_run; ND_EINVAL on another device.
+ * Every call on a GPU shares that GPU's array and leaves its contents
+ * behind (a run overwrites everything it reads): calls that overlap on one
+ * GPU -- from several threads, or on several streams without ordering --
+ * race and must not be issued. */
+nd_status nd_run_noalloc(nd_plan p, int32_t *rcliques_dev, uint32_t *kappa_dev,
+                         uint32_t *counts_dev, nd_stats *stats);
+
 /* Round sizes |A_t| and levels k_t of the last successful nd_run (host
  * arrays of capacity cap); *rounds receives rho.  Either array may be NULL. */
 nd_status nd_round_trace(nd_plan p, uint64_t *sizes_host, uint32_t *levels_host, uint64_t cap,

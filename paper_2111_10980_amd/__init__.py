@@ -70,6 +70,7 @@ def _load():
     lib.nd_plan_sizes.argtypes = [P, ctypes.POINTER(ctypes.c_uint64),
                                   ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
     lib.nd_run.argtypes = [P, P, ctypes.c_uint64, P, P, P, ctypes.POINTER(nd_stats)]
+    lib.nd_run_noalloc.argtypes = [P, P, P, P, ctypes.POINTER(nd_stats)]
     lib.nd_round_trace.argtypes = [P, P, P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
     lib.nd_plan_destroy.argtypes = [P]
     lib.nd_release_cached.argtypes = []
@@ -108,8 +109,8 @@ def _load():
     lib.nd_status_str.restype = ctypes.c_char_p
     lib.nd_last_error.argtypes = []
     lib.nd_last_error.restype = ctypes.c_char_p
-    for name in ("nd_plan_create", "nd_plan_sizes", "nd_run", "nd_round_trace",
-                 "nd_plan_destroy", "nd_release_cached"):
+    for name in ("nd_plan_create", "nd_plan_sizes", "nd_run", "nd_run_noalloc",
+                 "nd_round_trace", "nd_plan_destroy", "nd_release_cached"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -134,7 +135,8 @@ def library():
         _Lazy._h = _load()
     return _Lazy._h
 
-EXPORTED = ("nd_plan_create", "nd_plan_sizes", "nd_run", "nd_round_trace", "nd_plan_destroy",
+EXPORTED = ("nd_plan_create", "nd_plan_sizes", "nd_run", "nd_run_noalloc", "nd_round_trace",
+            "nd_plan_destroy",
             "nd_release_cached", "nd_status_str", "nd_last_error", "nd_roofline_measure",
             "nd_batch_create", "nd_batch_sizes", "nd_batch_run", "nd_batch_round_trace",
             "nd_batch_destroy", "nd_server_create", "nd_server_submit", "nd_server_wait",
@@ -212,6 +214,17 @@ def nd_run(plan, ws, rcliques, kappa, counts=None, ws_bytes=None) -> dict:
     nbytes = int(ws.numel() * ws.element_size()) if ws_bytes is None else int(ws_bytes)
     _check(_lib.nd_run(plan, _ptr(ws), nbytes, _ptr(rcliques), _ptr(kappa), _ptr(counts),
                        ctypes.byref(st)))
+    return stats_dict(st)
+
+
+ND_NOALLOC_WORKSPACE_BYTES = 64 << 20
+
+
+def nd_run_noalloc(plan, rcliques, kappa, counts=None) -> dict:
+    """nd_run with the library's static device workspace (no allocation)."""
+    st = nd_stats()
+    _check(_lib.nd_run_noalloc(plan, _ptr(rcliques), _ptr(kappa), _ptr(counts),
+                               ctypes.byref(st)))
     return stats_dict(st)
 
 

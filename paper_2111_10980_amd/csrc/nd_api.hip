@@ -347,6 +347,7 @@ using namespace nd;
 
 struct nd_plan_s {
   hipStream_t st = nullptr;
+  int device = 0;     // device current at creation
   int r = 0, s = 0;
   nd_options opt{};
   uint64_t budget = 0;
@@ -485,6 +486,7 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
   if (!p) return ND_ENOMEM;
   nd_status rc = guarded(st, [&] {
     p->st = st;
+    hip_check(hipGetDevice(&p->device), "get device");
     p->r = r;
     p->s = s;
     if (opt) p->opt = *opt;
@@ -853,6 +855,75 @@ nd_status nd_run(nd_plan p, void *workspace_dev, uint64_t workspace_bytes, int32
   }
   return guarded(p->st, [&] {
     WorkspaceScope ws(workspace_dev, workspace_bytes);
+    run_impl(p, rcl_dev, kappa_dev, counts_dev, stats);
+  });
+}
+
+}  // extern "C"
+
+// Workspace of nd_run_noalloc: one static device array, which every GPU the
+// library runs on holds from load until the process ends.  In host code its
+// name is only a stand-in; kernels get the device address that
+// hipGetSymbolAddress returns for the current device, looked up once per
+// device at that device's first nd_run_noalloc call.
+static __device__ __align__(256) unsigned char scratch[ND_NOALLOC_WORKSPACE_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device
+void *scratch_on_device(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) fail(ND_EINVAL, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      hipGetLastError();
+      fail(ND_EHIP, "hipGetSymbolAddress of the static workspace failed: %s",
+           hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+nd_status nd_run_noalloc(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *counts_dev,
+                         nd_stats *stats) {
+  if (!p) {
+    g_last_error = "plan is null";
+    return ND_EINVAL;
+  }
+  if (p->n_r && (!rcl_dev || !kappa_dev)) {
+    g_last_error = "output pointer is null";
+    return ND_EINVAL;
+  }
+  const uint64_t need = required_ws(p);
+  if (need > ND_NOALLOC_WORKSPACE_BYTES) {
+    char buf[200];
+    snprintf(buf, sizeof(buf),
+             "the run needs a workspace of %llu bytes; the static workspace holds %llu",
+             (unsigned long long)need, (unsigned long long)ND_NOALLOC_WORKSPACE_BYTES);
+    g_last_error = buf;
+    return ND_ENOMEM;
+  }
+  if (p->budget && p->held + need > p->budget) {
+    g_last_error = "plan and workspace exceed the budget";
+    return ND_ENOMEM;
+  }
+  return guarded(p->st, [&] {
+    int dev = -1;
+    hip_check(hipGetDevice(&dev), "get device");
+    if (dev != p->device) fail(ND_EINVAL, "call on the plan's device (%d, current %d)", p->device, dev);
+    void *ws = scratch_on_device(dev);
+    WorkspaceScope scope(ws, ND_NOALLOC_WORKSPACE_BYTES);
     run_impl(p, rcl_dev, kappa_dev, counts_dev, stats);
   });
 }
