@@ -73,9 +73,10 @@ typedef struct {
   int32_t canonical;     /* 1 = output rows in lexicographic order of their vertices
                             (original ids); 0 = library order */
   uint32_t trace_cap;    /* round-trace capacity the workspace provides at first;
-                            0 = min(n_r, 4096) */
+                            0 = min(n_r, 2^20) */
   uint64_t record_cap;   /* per-round record capacity the workspace provides at first
-                            (s = r+1 and s >= r+2 paths); 0 = max(2 n_r, 2^18) */
+                            (s = r+1 and s >= r+2 paths); 0 = max(8 n_r, 2^18) for
+                            s = r+1, max(4 n_r, 2^18) for s >= r+2 */
   uint64_t debug_count_bias; /* debug: the 32-bit range check of the initial counts sees
                                 every count raised by this amount, so a bias above
                                 UINT32_MAX - (largest count) makes nd_run return
@@ -105,6 +106,7 @@ typedef struct {
                             is counted in decrements but needs no memory operation */
   uint64_t workspace_bytes;   /* workspace bytes the run carved */
   uint64_t max_round_records; /* largest number of records one peel round wrote */
+  uint64_t max_round_arcs;    /* s >= r+2: largest number of out-arcs one round walked */
 } nd_stats;
 
 typedef struct nd_plan_s *nd_plan; /* opaque, library-owned */

@@ -55,7 +55,8 @@ class nd_stats(ctypes.Structure):
                 ("ms", ctypes.c_float * 8), ("count_kernel_ms", ctypes.c_float),
                 ("peel_kernel_ms", ctypes.c_float), ("count_launches", ctypes.c_uint32),
                 ("peel_launches", ctypes.c_uint32), ("atomics", ctypes.c_uint64),
-                ("workspace_bytes", ctypes.c_uint64), ("max_round_records", ctypes.c_uint64)]
+                ("workspace_bytes", ctypes.c_uint64), ("max_round_records", ctypes.c_uint64),
+                ("max_round_arcs", ctypes.c_uint64)]
 
 
 def _load():

@@ -557,12 +557,20 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
     if (p->n_r > 0x7FFFFFFFull)
       fail(ND_EOVERFLOW, "%llu r-cliques (limit 2^31-1)", (unsigned long long)p->n_r);
     // round capacities the workspace provides (records only on the split paths)
+    // round capacities the workspace provides.  A round's records are its
+    // candidate s-cliques (at most the s-cliques its frontier still lies in);
+    // the largest round of rMAT-18 (3,4) writes 4.8 n_r of them, so the
+    // default leaves room for 8 n_r (s = r+1) or 4 n_r candidates with 16 n_r
+    // out-arcs (s >= r+2).  A round that still needs more stops the run, and
+    // the plan then reports the larger workspace.
     if (p->path != 0)
-      p->rec_need = p->opt.record_cap ? p->opt.record_cap
-                                      : std::max<uint64_t>(2 * p->n_r, 1ull << 18);
+      p->rec_need = p->opt.record_cap
+                        ? p->opt.record_cap
+                        : std::max<uint64_t>((p->path == 1 ? 8 : 4) * p->n_r, 1ull << 18);
+    // rounds <= n_r; 2^20 rounds (8 MB of trace) cover every measured peel
     p->trace_need = p->opt.trace_cap
                         ? p->opt.trace_cap
-                        : (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(p->n_r, 4096));
+                        : (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(p->n_r, 1u << 20));
     uint64_t table_bytes = p->n_slots * (sizeof(Slot) + 4) + p->n_r * 4 * 5;
     p->held = graph_bytes + table_bytes + (uint64_t)(n + 1) * 8 + fixed_bytes;
     // the budget covers the plan and the workspace of its run; checked before
@@ -816,6 +824,7 @@ void run_impl(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *counts
     stats->peel_launches = peel_launches;
     stats->workspace_bytes = g_ws->used;
     stats->max_round_records = pr.max_rec;
+    stats->max_round_arcs = pr.max_arcs;
   }
 }
 

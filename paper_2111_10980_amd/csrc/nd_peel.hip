@@ -1533,9 +1533,24 @@ __global__ void k_emit(const uint32_t *__restrict__ occ, uint64_t n_r, TableView
 //   apply:  the out-arcs (x, y) of 64 members spread over a wave: y in I(R)
 //           closes R + {x, y} (s = r + 2) or starts a deeper extension.
 
+// r = 2 arc states of the s >= r+2 path, one byte per arc position of G'
+// (both directions of an edge carry the same state).
+constexpr uint8_t kArcAlive = 0, kArcFront = 1, kArcDead = 2;
+
+__device__ __forceinline__ void set_edge_state(const GraphView &g, int32_t a, int32_t b,
+                                               uint8_t *st, uint8_t v) {
+  const int32_t lo = a < b ? a : b, hi = a < b ? b : a;
+  const int64_t e = arc_pos(g, lo, hi);
+  if (e < 0) return;
+  st[e] = v;
+  const int64_t q = lower_pos(g.col, g.rp[hi], g.up[hi], lo);  // lo sits in hi's lower part
+  if (q < g.up[hi] && g.col[q] == lo) st[q] = v;
+}
+
 template <int R>
 __global__ __launch_bounds__(256) void k_gen_bound(PeelArgs base, RoundCtl *rc, uint64_t *ioff,
-                                                   uint32_t *ilen, int32_t *fv, int32_t *drv) {
+                                                   uint32_t *ilen, int32_t *fv, int32_t *drv,
+                                                   uint8_t *arcst) {
   if (rc_idle(rc)) return;
   const PeelArgs a = round_args(base, rc);
   const uint32_t *__restrict__ F = rc->F;
@@ -1563,6 +1578,7 @@ __global__ __launch_bounds__(256) void k_gen_bound(PeelArgs base, RoundCtl *rc, 
       }
       drv[f] = best_v;
       bound = sl.cnt != 0 ? (uint64_t)best : 0;  // cnt 0: every s-clique of R is gone
+      if constexpr (R == 2) set_edge_state(a.g, Rv[0], Rv[1], arcst, kArcFront);
     }
     const uint64_t at = block_alloc(bound, (unsigned long long *)&rc->total);
     if (f < nF) {
@@ -1597,10 +1613,13 @@ __global__ __launch_bounds__(256) void k_gen_spread(RoundCtl *rc, const uint64_t
 
 // A thread per candidate x of the round: flag x when it lies in I(R) and
 // list the members that have out-arcs as (frontier index, x).
-// r = 2: dead[e] = 1 once the edge of arc position e (either direction) was
-// peeled in an earlier round.  A candidate x joins I(R) only if both its
-// edges to R are alive, so no s-clique destroyed earlier through one of
-// them is listed again (Update-Func would skip it after probing).
+// r = 2: arcst[e] says whether the edge of arc position e was peeled in an
+// earlier round (dead) or is in this round's frontier.  A candidate x joins
+// I(R), R = {u < v}, only if both its edges to R are alive (no s-clique
+// destroyed earlier is listed again) and neither is a frontier edge that
+// comes before R in the subset order of every s-clique containing R and x:
+// {x,u} does when x < v, {x,v} when x < u.  Such an s-clique is owned by
+// that edge (Update-Func's owner rule), so R would only probe it to skip it.
 template <int R>
 __global__ __launch_bounds__(256) void k_gen_member(GraphView g, RoundCtl *rc,
                                                     const uint64_t *__restrict__ ioff,
@@ -1608,7 +1627,7 @@ __global__ __launch_bounds__(256) void k_gen_member(GraphView g, RoundCtl *rc,
                                                     const int32_t *__restrict__ fv,
                                                     const int32_t *__restrict__ drv, uint8_t *flag,
                                                     int2 *mrec, uint64_t *mbeg, uint32_t *aown,
-                                                    const uint8_t *__restrict__ dead) {
+                                                    const uint8_t *__restrict__ arcst) {
   if (rc_idle(rc)) return;
   const uint64_t C = rc->total;
   const uint64_t cap3 = rc->cap3;
@@ -1626,9 +1645,17 @@ __global__ __launch_bounds__(256) void k_gen_member(GraphView g, RoundCtl *rc,
       const int64_t ev = g.rp[v] + (int64_t)(k - ioff[f]);
       x = g.col[ev];
       if constexpr (R == 2) {
-        const int32_t u = fv[(int64_t)f * 2] == v ? fv[(int64_t)f * 2 + 1] : fv[(int64_t)f * 2];
-        const int64_t eu = arc_pos(g, x, u);
-        in = eu >= 0 && dead[ev] == 0 && dead[eu] == 0;
+        const int32_t u0 = fv[(int64_t)f * 2], u1 = fv[(int64_t)f * 2 + 1];  // u0 < u1
+        const int32_t w = u0 == v ? u1 : u0;
+        const int64_t ew = arc_pos(g, x, w);
+        if (ew < 0) {
+          in = false;
+        } else {
+          const uint8_t sv = arcst[ev], sw = arcst[ew];
+          const uint8_t s0 = v == u0 ? sv : sw, s1 = v == u0 ? sw : sv;  // {x,u0}, {x,u1}
+          in = sv != kArcDead && sw != kArcDead && !(s0 == kArcFront && x < u1) &&
+               !(s1 == kArcFront && x < u0);
+        }
       } else {
 #pragma unroll
         for (int i = 0; i < R; i++) {
@@ -1693,18 +1720,20 @@ template <int L, int R, int S>
 __device__ void gen_extend(const PeelArgs &a, const uint8_t *__restrict__ flag, int64_t lo,
                            int64_t hi, uint64_t fbase, const int32_t (&Rv)[R],
                            int32_t (&Qv)[S - R], uint32_t p, LaneStats &ls,
-                           const uint8_t *__restrict__ dead) {
+                           const uint8_t *__restrict__ arcst) {
   const int32_t x = Qv[L - 1];
   for (int64_t e = a.g.up[x]; e < a.g.rp[x + 1]; e++) {
     const int32_t z = a.g.col[e];
     bool ok = gen_in(a.g, flag, lo, hi, fbase, z);
-    if constexpr (R == 2) {  // every edge of S other than R still alive
-      ok = ok && dead[e] == 0;
+    if constexpr (R == 2) {
+      // every edge of S other than R alive; an edge {q, z} of Q (q < z)
+      // that is in the frontier comes before R = {u0, ...} when q < u0
+      ok = ok && arcst[e] != kArcDead && !(arcst[e] == kArcFront && x < Rv[0]);
 #pragma unroll
       for (int j = 0; j < L - 1; j++) {
         if (!ok) break;
         const int64_t q = arc_pos(a.g, Qv[j], z);
-        ok = q >= 0 && dead[q] == 0;
+        ok = q >= 0 && arcst[q] != kArcDead && !(arcst[q] == kArcFront && Qv[j] < Rv[0]);
       }
     } else {
 #pragma unroll
@@ -1718,7 +1747,7 @@ __device__ void gen_extend(const PeelArgs &a, const uint8_t *__restrict__ flag, 
       merge_rq<R, S - R>(Rv, Qv, Sv, rmask);
       update_func<R, S, false>(a, Sv, rmask, p, true, ls, nullptr);
     } else {
-      gen_extend<L + 1, R, S>(a, flag, lo, hi, fbase, Rv, Qv, p, ls, dead);
+      gen_extend<L + 1, R, S>(a, flag, lo, hi, fbase, Rv, Qv, p, ls, arcst);
     }
   }
 }
@@ -1734,7 +1763,7 @@ __global__ __launch_bounds__(256) void k_gen_apply(PeelArgs base, RoundCtl *rc,
                                                    const int2 *__restrict__ mrec,
                                                    const uint64_t *__restrict__ mbeg,
                                                    const uint32_t *__restrict__ aown,
-                                                   const uint8_t *__restrict__ dead) {
+                                                   const uint8_t *__restrict__ arcst) {
   if (rc_idle(rc)) return;
   if (rc->total3 > rc->cap3) {  // arcs did not fit: the host grows the buffer, reruns the round
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1777,7 +1806,9 @@ __global__ __launch_bounds__(256) void k_gen_apply(PeelArgs base, RoundCtl *rc,
       const int64_t exy = a.g.up[x] + (int64_t)(j - mbeg[i]);
       const int32_t y = a.g.col[exy];
       in = gen_in(a.g, flag, lo, hi, fbase, y);
-      if constexpr (R == 2) in = in && dead[exy] == 0;
+      if constexpr (R == 2)  // {x, y} alive, and not a frontier edge before R
+        in = in && arcst[exy] != kArcDead &&
+             !(arcst[exy] == kArcFront && x < fv[(int64_t)f * 2]);
       p = F[f];
 #pragma unroll
       for (int q = 0; q < R; q++) Rv[q] = fv[(int64_t)f * R + q];
@@ -1790,7 +1821,7 @@ __global__ __launch_bounds__(256) void k_gen_apply(PeelArgs base, RoundCtl *rc,
       merge_rq<R, 2>(Rv, Qv, Sv, rmask);
       update_func<R, S, true>(a, Sv, rmask, p, in, ls, ap);
     } else {
-      if (in) gen_extend<2, R, S>(a, flag, lo, hi, fbase, Rv, Qv, p, ls, dead);
+      if (in) gen_extend<2, R, S>(a, flag, lo, hi, fbase, Rv, Qv, p, ls, arcst);
     }
   }
   ap[0].flush();
@@ -1805,20 +1836,12 @@ __global__ __launch_bounds__(256) void k_gen_apply(PeelArgs base, RoundCtl *rc,
 // the candidate tests of later rounds (both arc directions).
 __global__ __launch_bounds__(256) void k_gen_retire2(GraphView g, const RoundCtl *rc,
                                                      const int32_t *__restrict__ fv,
-                                                     uint8_t *dead) {
+                                                     uint8_t *arcst) {
   if (rc_idle(rc)) return;
   const uint32_t nF = rc->nF;
   for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nF;
-       f += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t a = fv[f * 2], b = fv[f * 2 + 1];
-    const int64_t e = arc_pos(g, a, b);
-    if (e < 0) continue;
-    const int32_t lo = a < b ? a : b, hi = a < b ? b : a;
-    dead[e] = 1;
-    const int64_t r0 = g.rp[hi], r1 = g.up[hi];  // lo sits in hi's lower part
-    const int64_t q = lower_pos(g.col, r0, r1, lo);
-    if (q < r1 && g.col[q] == lo) dead[q] = 1;
-  }
+       f += (int64_t)gridDim.x * blockDim.x)
+    set_edge_state(g, fv[f * 2], fv[f * 2 + 1], arcst, kArcDead);
 }
 
 dim3 blocks_for(uint64_t n, uint64_t per, uint64_t lo, uint64_t hi) {
@@ -1853,7 +1876,7 @@ struct Engine {
   DevBuf<uint32_t> owner;  // s >= r+2: frontier index of each candidate
   DevBuf<uint64_t> mbeg;   // s >= r+2: first out-arc of each member
   DevBuf<uint32_t> aown;   // s >= r+2: member of each out-arc
-  DevBuf<uint8_t> dead;    // s >= r+2, r = 2: per arc position, edge peeled earlier
+  DevBuf<uint8_t> dead;    // s >= r+2, r = 2: per arc position, alive / frontier / dead
   uint64_t cap3 = 0;
   DevBuf<uint32_t> tsize, tk;
   uint64_t cap = 0;
@@ -1890,7 +1913,7 @@ template <int R, int S>
 void launch_gen(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, dim3 gc, dim3 ga,
                 hipEvent_t e0, hipEvent_t e1) {
   hipLaunchKernelGGL(k_gen_bound<R>, gf, dim3(256), 0, E.st, base, E.rc, E.off.get(),
-                     E.len.get(), E.fv.get(), E.drv.get());
+                     E.len.get(), E.fv.get(), E.drv.get(), E.dead.get());
   hipLaunchKernelGGL(k_gen_spread, gw, dim3(256), 0, E.st, E.rc, E.off.get(), E.len.get(),
                      E.owner.get());
   hipLaunchKernelGGL(k_gen_member<R>, gc, dim3(256), 0, E.st, E.gv, E.rc, E.off.get(),
@@ -1933,7 +1956,12 @@ void enqueue_round(Engine &E, const RoundCtl &m, bool exact, hipEvent_t e0, hipE
   hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, st, rc, E.dc);
   // Grids: sized to the frontier when it is known (nothing in flight and no
   // level advance), otherwise wide enough to fill the chip, so that a large
-  // round queued behind small ones never runs on a small grid.
+  // round queued behind small ones never runs on a small grid.  Measured and
+  // dropped: sizing queued rounds from the recent ones (on rMAT-18 (3,4) a
+  // batch of 32 rounds swings between a few dozen and 10^6 records, and the
+  // big rounds on small grids tripled the update pass), and record-pass
+  // floors of 256 or 512 blocks or caps of 2048 (up to 1.9x slower peels on
+  // rMAT-18 (3,4) and Chung-Lu 1M (4,5), no gain on (2,4)).
   const bool known = exact && m.nF != 0;
   const dim3 gf = known ? blocks_for(m.nF, 256, 1, 4096) : dim3(1024);
   const dim3 gw = known ? blocks_for(m.nF, 256 / kWave, 1, 1u << 16) : dim3(4096);
