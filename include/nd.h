@@ -49,7 +49,7 @@ typedef enum {
   ND_ESTATE = 7      /* entry point called in the wrong order */
 } nd_status;
 
-#define ND_MAX_S 7
+#define ND_MAX_S 8
 
 /* Simple undirected graph in CSR form, DEVICE pointers, caller-owned.
  * row_ptr[n+1] (int64, row_ptr[0] = 0, row_ptr[n] = nnz), col[nnz] (int32);
@@ -81,6 +81,13 @@ typedef struct {
                                 every count raised by this amount, so a bias above
                                 UINT32_MAX - (largest count) makes nd_run return
                                 ND_EOVERFLOW; 0 = off (results are never changed) */
+  int32_t queue_depth;   /* most peel rounds queued between two reads of the device round
+                            state, 1..32; 0 = 32 */
+  int32_t graph_rounds;  /* 1 = the rounds queued after the first of each batch are
+                            captured once into a HIP graph (per queue depth and grid
+                            class) and replayed with one launch; 0 = plain launches.
+                            Ignored with timing (events recorded by graph nodes cannot
+                            be timed) */
 } nd_options;
 
 typedef struct {

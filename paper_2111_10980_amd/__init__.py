@@ -15,7 +15,7 @@ from dataclasses import dataclass, field
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnd.so")
 
-ND_MAX_S = 7
+ND_MAX_S = 8
 ND_ENOMEM = 5
 WS_ALIGN = 256
 STATUS = {0: "ND_OK", 1: "ND_EINVAL", 2: "ND_EGRAPH", 3: "ND_EKEYWIDTH", 4: "ND_EOVERFLOW",
@@ -39,7 +39,8 @@ class nd_options(ctypes.Structure):
     _fields_ = [("orient", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("load_factor", ctypes.c_float), ("path", ctypes.c_int32),
                 ("canonical", ctypes.c_int32), ("trace_cap", ctypes.c_uint32),
-                ("record_cap", ctypes.c_uint64), ("debug_count_bias", ctypes.c_uint64)]
+                ("record_cap", ctypes.c_uint64), ("debug_count_bias", ctypes.c_uint64),
+                ("queue_depth", ctypes.c_int32), ("graph_rounds", ctypes.c_int32)]
 
 
 class nd_roofline(ctypes.Structure):
@@ -160,16 +161,18 @@ def _stream_handle(stream):
 
 def make_options(orient: int = 0, timing: bool = False, load_factor: float = 0.0,
                  generic: bool = False, canonical: bool = False, trace_cap: int = 0,
-                 record_cap: int = 0, debug_count_bias: int = 0) -> nd_options:
+                 record_cap: int = 0, debug_count_bias: int = 0, queue_depth: int = 0,
+                 graph_rounds: bool = False) -> nd_options:
     return nd_options(int(orient), int(bool(timing)), float(load_factor), int(bool(generic)),
                       int(bool(canonical)), int(trace_cap), int(record_cap),
-                      int(debug_count_bias))
+                      int(debug_count_bias), int(queue_depth), int(bool(graph_rounds)))
 
 
 def nd_plan_create(row_ptr, col, r: int, s: int, orient: int = 0, load_factor: float = 0.0,
                    hbm_budget_bytes: int = 0, stream=None, timing: bool = False,
                    generic: bool = False, canonical: bool = False, trace_cap: int = 0,
-                   record_cap: int = 0, debug_count_bias: int = 0):
+                   record_cap: int = 0, debug_count_bias: int = 0, queue_depth: int = 0,
+                   graph_rounds: bool = False):
     """row_ptr (int64, n+1) and col (int32) are CUDA tensors; returns a plan handle."""
     import torch
     if row_ptr.dtype != torch.int64 or col.dtype != torch.int32:
@@ -181,7 +184,7 @@ def nd_plan_create(row_ptr, col, r: int, s: int, orient: int = 0, load_factor: f
     g = nd_csr(int(row_ptr.numel() - 1), int(col.numel()), row_ptr.data_ptr(),
                col.data_ptr() if col.numel() else None)
     opt = make_options(orient, timing, load_factor, generic, canonical, trace_cap, record_cap,
-                       debug_count_bias)
+                       debug_count_bias, queue_depth, graph_rounds)
     h = ctypes.c_void_p()
     _check(_lib.nd_plan_create(ctypes.byref(g), int(r), int(s), ctypes.byref(opt),
                                int(hbm_budget_bytes), _stream_handle(stream), ctypes.byref(h)))
@@ -247,7 +250,8 @@ def nd_plan_destroy(plan):
 
 def nd_batch_create(graphs, r: int, s: int, orient: int = 0, load_factor: float = 0.0,
                     hbm_budget_bytes: int = 0, stream=None, timing: bool = False,
-                    generic: bool = False, canonical: bool = False):
+                    generic: bool = False, canonical: bool = False, queue_depth: int = 0,
+                    graph_rounds: bool = False):
     """graphs: sequence of (row_ptr int64, col int32) device tensor pairs."""
     arr = (nd_csr * max(1, len(graphs)))()
     keep = []
@@ -257,7 +261,8 @@ def nd_batch_create(graphs, r: int, s: int, orient: int = 0, load_factor: float 
         keep.append((rp, col))
         arr[i] = nd_csr(int(rp.numel() - 1), int(col.numel()), rp.data_ptr(),
                         col.data_ptr() if col.numel() else None)
-    opt = make_options(orient, timing, load_factor, generic, canonical)
+    opt = make_options(orient, timing, load_factor, generic, canonical,
+                       queue_depth=queue_depth, graph_rounds=graph_rounds)
     h = ctypes.c_void_p()
     _check(_lib.nd_batch_create(arr, len(graphs), int(r), int(s), ctypes.byref(opt),
                                 int(hbm_budget_bytes), _stream_handle(stream), ctypes.byref(h)))
@@ -430,13 +435,15 @@ def decompose(row_ptr, col, r: int, s: int, with_counts: bool = False, orient: i
               load_factor: float = 0.0, hbm_budget_bytes: int = 0, stream=None,
               timing: bool = False, generic: bool = False, canonical: bool = False,
               trace_cap: int = 0, record_cap: int = 0, debug_count_bias: int = 0,
+              queue_depth: int = 0, graph_rounds: bool = False,
               requery: bool = True) -> Decomposition:
     """Whole hot path on the current device: plan, workspace, run, round
     trace, destroy.  With requery a run whose round outgrew the workspace is
     repeated with the larger workspace the plan then reports."""
     import torch
     plan = nd_plan_create(row_ptr, col, r, s, orient, load_factor, hbm_budget_bytes, stream,
-                          timing, generic, canonical, trace_cap, record_cap, debug_count_bias)
+                          timing, generic, canonical, trace_cap, record_cap, debug_count_bias,
+                          queue_depth, graph_rounds)
     try:
         n_r, ws_bytes, _ = nd_plan_sizes(plan)
         dev = row_ptr.device
@@ -474,11 +481,12 @@ class BatchDecomposition:
 def decompose_batch(graphs, r: int, s: int, with_counts: bool = False, orient: int = 0,
                     load_factor: float = 0.0, hbm_budget_bytes: int = 0, stream=None,
                     timing: bool = False, generic: bool = False,
-                    canonical: bool = False) -> BatchDecomposition:
+                    canonical: bool = False, queue_depth: int = 0,
+                    graph_rounds: bool = False) -> BatchDecomposition:
     """All graphs in one fused decomposition (graphs: (row_ptr, col) device pairs)."""
     import torch
     b = nd_batch_create(graphs, r, s, orient, load_factor, hbm_budget_bytes, stream, timing,
-                        generic, canonical)
+                        generic, canonical, queue_depth, graph_rounds)
     try:
         dev = graphs[0][0].device if graphs else torch.device("cuda")
         for i in range(10):

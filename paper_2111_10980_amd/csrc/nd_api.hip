@@ -314,6 +314,13 @@ WorkspaceScope::WorkspaceScope(void *base, uint64_t size) : prev(g_ws) {
 
 WorkspaceScope::~WorkspaceScope() { g_ws = prev; }
 
+void hip_ok(hipError_t e, const char *what) { hip_check(e, what); }
+
+void read_back(void *dst, const void *src, size_t bytes, hipStream_t st) {
+  hip_check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st), "read back");
+  hip_check(hipStreamSynchronize(st), "synchronize");
+}
+
 void *dev_alloc(size_t bytes) {
   if (g_ws) {
     const uint64_t b = ws_block(bytes);
@@ -377,9 +384,11 @@ struct nd_plan_s {
   EventSet ev_create;  // 4: plan creation phases
   EventSet ev_run;     // 5: run phases, 2: count kernels
   EventSet ev_peel;    // timing: 2 * kPeelMaxDepth around the update passes
+  hipStream_t graph_stream = nullptr;  // graph_rounds: capture stream of queued rounds
   TableView table() const { return TableView{bits, seg.get(), slots.get(), v1.get()}; }
   ~nd_plan_s() {
     if (mirror) hipHostFree(mirror);
+    if (graph_stream) hipStreamDestroy(graph_stream);
   }
 };
 
@@ -495,6 +504,10 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
     if (p->opt.orient != 0 && p->opt.orient != 1) fail(ND_EINVAL, "orient must be 0 or 1");
     if (p->opt.path != 0 && p->opt.path != 1) fail(ND_EINVAL, "path must be 0 or 1");
     if (p->opt.canonical != 0 && p->opt.canonical != 1) fail(ND_EINVAL, "canonical must be 0 or 1");
+    if (p->opt.queue_depth < 0 || p->opt.queue_depth > kPeelMaxDepth)
+      fail(ND_EINVAL, "queue_depth must be in 0..%d", kPeelMaxDepth);
+    if (p->opt.graph_rounds != 0 && p->opt.graph_rounds != 1)
+      fail(ND_EINVAL, "graph_rounds must be 0 or 1");
     p->fast = (s == r + 1) && r >= 2 && r <= 6 && p->opt.path == 0;
     p->path = p->fast ? 1 : (s >= r + 2 && p->opt.path == 0 ? 2 : 0);
     p->budget = hbm_budget_bytes;
@@ -504,6 +517,9 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
     p->ev_create.create(4);
     p->ev_run.create(7);
     if (p->opt.timing) p->ev_peel.create(2 * kPeelMaxDepth);
+    if (p->opt.graph_rounds)
+      hip_check(hipStreamCreateWithFlags(&p->graph_stream, hipStreamNonBlocking),
+                "create the capture stream");
     if (hipHostMalloc((void **)&p->mirror, sizeof(RoundCtl), hipHostMallocDefault) != hipSuccess) {
       hipGetLastError();
       p->mirror = nullptr;
@@ -734,6 +750,9 @@ void run_impl(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *counts
   ps.rc = p->rcb.get();
   ps.mirror = p->mirror;
   ps.ev = timing && p->ev_peel.ok && !p->ev_peel.ev.empty() ? p->ev_peel.ev.data() : nullptr;
+  ps.queue_depth = p->opt.queue_depth ? p->opt.queue_depth : kPeelMaxDepth;
+  // events recorded by graph nodes cannot be timed: timed runs launch plainly
+  ps.graph_stream = timing ? nullptr : p->graph_stream;
   const uint32_t perr =
       peel_all(p->g, r, s, p->path, p->table(), p->fast ? &p->fx : nullptr, p->occ.get(), p->n_r,
                dc, p->stats.get(), ps, rec_cap, tcap, st, tm.at(2), &kround, &pr);

@@ -362,8 +362,7 @@ void bin_roots(const OrientedGraph &g, int minout, Counters *dctr, Bins *b, hipS
   if (g.n > 0)
     hipLaunchKernelGGL(k_bin_roots, dim3((unsigned)grid_for(g.n, 256)), dim3(256), 0, st,
                        g.view(), minout, b->lists.get(), g.n, dctr->class_size);
-  hipMemcpyAsync(b->size, dctr->class_size, sizeof(uint32_t) * 5, hipMemcpyDeviceToHost, st);
-  hipStreamSynchronize(st);
+  read_back(b->size, dctr->class_size, sizeof(uint32_t) * 5, st);
 }
 
 template <int C, class Op>
@@ -441,6 +440,7 @@ void count_rcliques(const OrientedGraph &g, int r, uint32_t *cnt, hipStream_t st
     case 4: count_r_impl<4>(g, cnt, tmp.get(), st); break;
     case 5: count_r_impl<5>(g, cnt, tmp.get(), st); break;
     case 6: count_r_impl<6>(g, cnt, tmp.get(), st); break;
+    case 7: count_r_impl<7>(g, cnt, tmp.get(), st); break;
     default: break;
   }
 }
@@ -458,6 +458,7 @@ void insert_rcliques(const OrientedGraph &g, int r, const TableView &T, Counters
     case 4: insert_r_impl<4>(g, T, dctr, st); break;
     case 5: insert_r_impl<5>(g, T, dctr, st); break;
     case 6: insert_r_impl<6>(g, T, dctr, st); break;
+    case 7: insert_r_impl<7>(g, T, dctr, st); break;
     default: break;
   }
 }
@@ -526,6 +527,8 @@ void count_scliques(const OrientedGraph &g, int r, int s, const TableView &T, Co
     ND_COUNT_CASE(4, 5) ND_COUNT_CASE(4, 6) ND_COUNT_CASE(4, 7)
     ND_COUNT_CASE(5, 6) ND_COUNT_CASE(5, 7)
     ND_COUNT_CASE(6, 7)
+    ND_COUNT_CASE(1, 8) ND_COUNT_CASE(2, 8) ND_COUNT_CASE(3, 8) ND_COUNT_CASE(4, 8)
+    ND_COUNT_CASE(5, 8) ND_COUNT_CASE(6, 8) ND_COUNT_CASE(7, 8)
     default: break;
   }
 }

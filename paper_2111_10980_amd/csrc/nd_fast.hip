@@ -266,8 +266,7 @@ void build_fast_index(const OrientedGraph &g, FastIndex *fx, Counters *dctr, hip
                      fx->bm_off.get());
   scan_exclusive_u64(fx->bm_off.get(), fx->bm_off.get(), (int64_t)n + 1, st);
   uint64_t words = 0;
-  hipMemcpyAsync(&words, fx->bm_off.get() + n, 8, hipMemcpyDeviceToHost, st);
-  hipStreamSynchronize(st);
+  read_back(&words, fx->bm_off.get() + n, 8, st);
   fx->bm_words = words;
   fx->bm.reset(words ? words : 1);
   {
@@ -276,8 +275,7 @@ void build_fast_index(const OrientedGraph &g, FastIndex *fx, Counters *dctr, hip
     hipLaunchKernelGGL(k_bitmap_classes, dim3((unsigned)grid_for(n, 256)), dim3(256), 0, st, gv,
                        lists.get(), n, dctr->class_size);
     uint32_t sz[4];
-    hipMemcpyAsync(sz, dctr->class_size, sizeof(sz), hipMemcpyDeviceToHost, st);
-    hipStreamSynchronize(st);
+    read_back(sz, dctr->class_size, sizeof(sz), st);
     auto grid = [](uint32_t k) { return dim3(k < 262144u ? k : 262144u); };
     if (sz[0])
       hipLaunchKernelGGL((k_build_bitmap<1, 64>), grid(sz[0]), dim3(64), 0, st, gv, lists.get(),
@@ -304,8 +302,7 @@ void build_fast_index(const OrientedGraph &g, FastIndex *fx, Counters *dctr, hip
   widen_u32_to_u64(tri, cur.get(), n, st);
   fill_u64(cur.get() + n, 0, 1, st);
   scan_exclusive_u64(cur.get(), cur.get(), (int64_t)n + 1, st);
-  hipMemcpyAsync(&fx->n_tri, cur.get() + n, 8, hipMemcpyDeviceToHost, st);
-  hipStreamSynchronize(st);
+  read_back(&fx->n_tri, cur.get() + n, 8, st);
   const uint64_t T = fx->n_tri;
   fx->lval.reset(T ? T : 1);
   if (T) {

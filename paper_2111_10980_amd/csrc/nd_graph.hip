@@ -194,13 +194,11 @@ void core_rounds(int32_t n, const int64_t *rp, const int32_t *col, uint32_t *rou
       fill_u32(ctr.get() + 1, 0, 1, st);
       hipLaunchKernelGGL(k_core_min, dim3((unsigned)gb), dim3(256), 0, st, n, deg.get(),
                          round_out, ctr.get());
-      hipMemcpyAsync(h, ctr.get(), 4, hipMemcpyDeviceToHost, st);
-      hipStreamSynchronize(st);
+      read_back(h, ctr.get(), 4, st);
       if (h[0] > k) k = h[0];
       hipLaunchKernelGGL(k_core_frontier, dim3((unsigned)gb), dim3(256), 0, st, n, deg.get(),
                          round_out, k, F.get(), ctr.get() + 1);
-      hipMemcpyAsync(&nF, ctr.get() + 1, 4, hipMemcpyDeviceToHost, st);
-      hipStreamSynchronize(st);
+      read_back(&nF, ctr.get() + 1, 4, st);
       if (nF == 0) break;
     }
     hipLaunchKernelGGL(k_core_stamp, dim3((unsigned)grid_for(nF, 256)), dim3(256), 0, st, F.get(),
@@ -209,8 +207,7 @@ void core_rounds(int32_t n, const int64_t *rp, const int32_t *col, uint32_t *rou
     hipLaunchKernelGGL(k_core_peel, dim3((unsigned)grid_for(nF, 4, 16384)), dim3(256), 0, st, rp,
                        col, F.get(), nF, k, deg.get(), round_out, Fn.get(), ctr.get() + 2);
     done += nF;
-    hipMemcpyAsync(&nF, ctr.get() + 2, 4, hipMemcpyDeviceToHost, st);
-    hipStreamSynchronize(st);
+    read_back(&nF, ctr.get() + 2, 4, st);
     std::swap(F.p, Fn.p);
     t++;
   }
@@ -241,14 +238,12 @@ uint32_t validate_csr(int32_t n, int64_t nnz, const int64_t *rp, const int32_t *
   hipLaunchKernelGGL(k_validate_rows, dim3((unsigned)grid_for(n, 256)), dim3(256), 0, st, n, nnz,
                      rp, err);
   uint32_t h = 0;
-  hipMemcpyAsync(&h, err, 4, hipMemcpyDeviceToHost, st);
-  hipStreamSynchronize(st);
+  read_back(&h, err, 4, st);
   if (h) return h;
   if (nnz > 0)
     hipLaunchKernelGGL(k_validate_arcs, dim3((unsigned)grid_for(nnz, 256)), dim3(256), 0, st, n,
                        nnz, rp, col, err);
-  hipMemcpyAsync(&h, err, 4, hipMemcpyDeviceToHost, st);
-  hipStreamSynchronize(st);
+  read_back(&h, err, 4, st);
   return h;
 }
 

@@ -78,6 +78,14 @@ struct DevBuf {
 
 struct OutOfMemory {};
 
+// Raises the library's error (ND_ENOMEM for out-of-memory, else ND_EHIP,
+// with `what` and HIP's message) when e is not hipSuccess.
+void hip_ok(hipError_t e, const char *what);
+// Copies bytes from device memory to the host on stream st and waits for
+// the copy; a failed copy or wait raises the library's error instead of
+// leaving dst uninitialised.
+void read_back(void *dst, const void *src, size_t bytes, hipStream_t st);
+
 // ---- primitives (nd_prims.hip)
 void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
 void fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st);
@@ -194,13 +202,17 @@ struct PeelResult {
 };
 constexpr int kPeelMaxDepth = 32;      // rounds queued between two reads of the state
 constexpr uint64_t kArcsPerRecord = 4; // s >= r+2: out-arc capacity per record slot
-// Plan-owned state of the peel loop (no allocation happens in a run): the
-// device round control block, its pinned host mirror and, with timing,
-// 2 * kPeelMaxDepth events (else null).
+// Plan-owned state of the peel loop (no device allocation happens in a
+// run): the device round control block, its pinned host mirror, with timing
+// 2 * kPeelMaxDepth events (else null), the queue depth and, for graph
+// replay of queued rounds, the capture stream.
 struct PeelState {
   RoundCtl *rc = nullptr;
   RoundCtl *mirror = nullptr;
   hipEvent_t *ev = nullptr;
+  int queue_depth = kPeelMaxDepth;       // most rounds queued between two state reads
+  hipStream_t graph_stream = nullptr;    // non-null: queued rounds replayed from captured
+                                         // graphs, captured on this (plan-owned) stream
 };
 // Workspace bytes peel_all allocates with the given capacities.
 uint64_t peel_ws_bytes(int r, int path, uint64_t n_r, uint64_t nnz, uint64_t rec_cap,

@@ -22,7 +22,7 @@ namespace nd {
 constexpr uint32_t kLive = 0xFFFFFFFFu;      // stamp of an unpeeled r-clique
 constexpr uint64_t kOcc = 1ull << 63;        // key bit marking an occupied slot
 constexpr int kWave = 64;
-constexpr int kMaxS = 7;
+constexpr int kMaxS = 8;
 constexpr int kMaxBitmapWords = 8;           // 8 x 64 = 512 out-neighbours per root
 
 struct alignas(16) Slot {

@@ -1934,26 +1934,34 @@ void launch_gen(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, dim3 gc, dim3
 #define ND_GEN(R_, S_) \
   case (R_) * 16 + (S_): launch_gen<R_, S_>(E, base, gf, gw, gc, ga, e0, e1); break;
 
-// Queue one round.  m is the last state read back: exact when nothing is in
-// flight (the first round of a batch), otherwise only a guide for the grid
+// Grids of one round's kernels.
+struct RoundGrids {
+  bool advance;         // queue the two level-advance kernels
+  dim3 amin, apart;     // level advance
+  dim3 gf, gw, ga, gc;  // per frontier entry, per frontier wave, record passes
+};
+
+uint32_t pow2_at_least(uint64_t x) {
+  uint32_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// Grids for one round.  m is the last state read back: exact when nothing is
+// in flight (the first round of a batch), otherwise only a guide for the grid
 // sizes (every kernel loops over the true sizes it reads on the device).
-void enqueue_round(Engine &E, const RoundCtl &m, bool exact, hipEvent_t e0, hipEvent_t e1,
-                   hipEvent_t e_adv) {
-  const hipStream_t st = E.st;
-  RoundCtl *rc = E.rc;
-  // r = 3 on the s = r+1 path: frontier marks at selection
-  const bool r3 = E.path == 1 && E.r == 3;
-  if (!exact || m.nF == 0) {
-    // queued behind other rounds these act only now and then: small grids
-    const uint64_t cap_b = exact ? 8192 : 256;
-    const uint64_t nl = m.nW != 0 ? m.nW : m.nH;
-    hipLaunchKernelGGL(k_adv_min, blocks_for(nl, 256 * 8, 1, cap_b), dim3(256), 0, st, rc,
-                       E.T.slots);
-    hipLaunchKernelGGL(k_adv_partition, blocks_for(nl, kPartThreads * kPartItems, 1, cap_b),
-                       dim3(kPartThreads), 0, st, rc, E.T.slots, r3, E.gv, E.T.v1, E.fxv, E.loc);
-  }
-  if (e_adv) hipEventRecord(e_adv, st);
-  hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, st, rc, E.dc);
+// With `quantized` every size is rounded up to a power of two, so that the
+// captured graphs of queued rounds are reused across batches.
+RoundGrids round_grids(const Engine &E, const RoundCtl &m, bool exact, bool quantized) {
+  RoundGrids g{};
+  auto q = [&](dim3 d) { return quantized ? dim3(pow2_at_least(d.x)) : d; };
+  g.advance = !exact || m.nF == 0;
+  // queued behind other rounds the advance kernels act only now and then:
+  // small grids
+  const uint64_t cap_b = exact ? 8192 : 256;
+  const uint64_t nl = m.nW != 0 ? m.nW : m.nH;
+  g.amin = q(blocks_for(nl, 256 * 8, 1, cap_b));
+  g.apart = q(blocks_for(nl, kPartThreads * kPartItems, 1, cap_b));
   // Grids: sized to the frontier when it is known (nothing in flight and no
   // level advance), otherwise wide enough to fill the chip, so that a large
   // round queued behind small ones never runs on a small grid.  Measured and
@@ -1963,11 +1971,36 @@ void enqueue_round(Engine &E, const RoundCtl &m, bool exact, hipEvent_t e0, hipE
   // floors of 256 or 512 blocks or caps of 2048 (up to 1.9x slower peels on
   // rMAT-18 (3,4) and Chung-Lu 1M (4,5), no gain on (2,4)).
   const bool known = exact && m.nF != 0;
-  const dim3 gf = known ? blocks_for(m.nF, 256, 1, 4096) : dim3(1024);
-  const dim3 gw = known ? blocks_for(m.nF, 256 / kWave, 1, 1u << 16) : dim3(4096);
+  g.gf = known ? blocks_for(m.nF, 256, 1, 4096) : dim3(1024);
+  g.gw = known ? blocks_for(m.nF, 256 / kWave, 1, 1u << 16) : dim3(4096);
+  if (E.path == 2) {
+    g.gc = q(blocks_for(2 * m.total, 256, 1024, 8192));
+    g.ga = q(blocks_for(2 * m.total3, 256, 1024, 8192));
+  } else {
+    g.ga = q(blocks_for(2 * m.total, 256, 1024, 8192));
+    g.gc = g.ga;
+  }
+  return g;
+}
+
+// Queue one round with the given grids on E.st.
+void launch_round(Engine &E, const RoundGrids &G, hipEvent_t e0, hipEvent_t e1,
+                  hipEvent_t e_adv) {
+  const hipStream_t st = E.st;
+  RoundCtl *rc = E.rc;
+  // r = 3 on the s = r+1 path: frontier marks at selection
+  const bool r3 = E.path == 1 && E.r == 3;
+  if (G.advance) {
+    hipLaunchKernelGGL(k_adv_min, G.amin, dim3(256), 0, st, rc, E.T.slots);
+    hipLaunchKernelGGL(k_adv_partition, G.apart, dim3(kPartThreads), 0, st, rc, E.T.slots, r3,
+                       E.gv, E.T.v1, E.fxv, E.loc);
+  }
+  if (e_adv) hipEventRecord(e_adv, st);
+  hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, st, rc, E.dc);
+  const dim3 gf = G.gf, gw = G.gw;
   const PeelArgs base{E.gv, E.T, 0u, 0u, nullptr, E.dc, E.stats, 0u, nullptr};
   if (E.path == 1) {
-    const dim3 ga = blocks_for(2 * m.total, 256, 1024, 8192);
+    const dim3 ga = G.ga;
     switch (E.r) {
       case 2: launch_fast<2>(E, base, gf, gw, ga, e0, e1); break;
       case 3: launch_fast<3>(E, base, gf, gw, ga, e0, e1); break;
@@ -1977,14 +2010,14 @@ void enqueue_round(Engine &E, const RoundCtl &m, bool exact, hipEvent_t e0, hipE
       default: break;
     }
   } else if (E.path == 2) {
-    const dim3 gc = blocks_for(2 * m.total, 256, 1024, 8192);
-    const dim3 ga = blocks_for(2 * m.total3, 256, 1024, 8192);
+    const dim3 gc = G.gc, ga = G.ga;
     switch (E.r * 16 + E.s) {
       ND_GEN(1, 3) ND_GEN(1, 4) ND_GEN(1, 5) ND_GEN(1, 6) ND_GEN(1, 7)
       ND_GEN(2, 4) ND_GEN(2, 5) ND_GEN(2, 6) ND_GEN(2, 7)
       ND_GEN(3, 5) ND_GEN(3, 6) ND_GEN(3, 7)
       ND_GEN(4, 6) ND_GEN(4, 7)
       ND_GEN(5, 7)
+      ND_GEN(1, 8) ND_GEN(2, 8) ND_GEN(3, 8) ND_GEN(4, 8) ND_GEN(5, 8) ND_GEN(6, 8)
       default: break;
     }
   } else {
@@ -1995,10 +2028,62 @@ void enqueue_round(Engine &E, const RoundCtl &m, bool exact, hipEvent_t e0, hipE
       ND_WALK(4, 5) ND_WALK(4, 6) ND_WALK(4, 7)
       ND_WALK(5, 6) ND_WALK(5, 7)
       ND_WALK(6, 7)
+      ND_WALK(1, 8) ND_WALK(2, 8) ND_WALK(3, 8) ND_WALK(4, 8) ND_WALK(5, 8) ND_WALK(6, 8)
+      ND_WALK(7, 8)
       default: break;
     }
   }
   hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, st, rc, E.dc);
+}
+
+// Instantiated graphs of `rest` queued rounds (one run's cache: the graphs
+// hold the run's workspace pointers), keyed by the round count and the
+// quantized grids.  Rounds queued past the first of a batch are captured
+// once per key on a private stream and then replayed with one launch.
+struct GraphCache {
+  struct Entry {
+    uint64_t key;
+    hipGraphExec_t exec;
+  };
+  std::vector<Entry> v;
+  ~GraphCache() {
+    for (auto &e : v) hipGraphExecDestroy(e.exec);
+  }
+};
+
+uint64_t graph_key(int rest, const RoundGrids &G, bool timing) {
+  auto lg = [](uint32_t x) {
+    uint64_t l = 0;
+    while ((1u << l) < x) l++;
+    return l;
+  };
+  return (uint64_t)rest | lg(G.amin.x) << 8 | lg(G.apart.x) << 14 | lg(G.ga.x) << 20 |
+         lg(G.gc.x) << 26 | (uint64_t)timing << 32;
+}
+
+// Queue rounds 1..rest of a batch (the first one is queued by the caller) as
+// one graph launch; returns false if capture or instantiation failed.
+bool launch_rounds_graph(Engine &E, GraphCache &gc, hipStream_t cap, int rest,
+                         const RoundGrids &G, hipEvent_t *ev) {
+  const uint64_t key = graph_key(rest, G, ev != nullptr);
+  hipGraphExec_t exec = nullptr;
+  for (auto &e : gc.v)
+    if (e.key == key) exec = e.exec;
+  if (!exec) {
+    const hipStream_t st = E.st;
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+    E.st = cap;
+    for (int d = 1; d <= rest; d++)
+      launch_round(E, G, ev ? ev[2 * d] : nullptr, ev ? ev[2 * d + 1] : nullptr, nullptr);
+    E.st = st;
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(cap, &g) != hipSuccess || !g) return false;
+    const hipError_t ie = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (ie != hipSuccess) return false;
+    gc.v.push_back({key, exec});
+  }
+  return hipGraphLaunch(exec, E.st) == hipSuccess;
 }
 
 void alloc_records(Engine &E, uint64_t cap) {
@@ -2014,13 +2099,6 @@ void alloc_records(Engine &E, uint64_t cap) {
   E.cap = cap;
 }
 
-// Most rounds queued between two reads of the round state (ND_PEEL_DEPTH,
-// 1..32, default 32).
-int max_depth() {
-  const char *e = getenv("ND_PEEL_DEPTH");
-  const int d = e ? atoi(e) : kPeelMaxDepth;
-  return d < 1 ? 1 : (d > kPeelMaxDepth ? kPeelMaxDepth : d);
-}
 
 }  // namespace
 
@@ -2125,13 +2203,26 @@ uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableVie
   uint32_t status = 0;
   RoundCtl m = h;
   int depth = 1;
-  const int dmax = max_depth();
+  const int dmax = ps.queue_depth >= 1 && ps.queue_depth <= kPeelMaxDepth ? ps.queue_depth
+                                                                          : kPeelMaxDepth;
   bool first = true;
+  GraphCache gcache;
   for (;;) {
     const auto t0 = std::chrono::steady_clock::now();
-    for (int d = 0; d < depth; d++) {
-      enqueue_round(E, m, d == 0, timing ? ev[2 * d] : nullptr, timing ? ev[2 * d + 1] : nullptr,
-                    first && d == 0 ? ev_first : nullptr);
+    launch_round(E, round_grids(E, m, true, false), timing ? ev[0] : nullptr,
+                 timing ? ev[1] : nullptr, first ? ev_first : nullptr);
+    if (depth > 1 && ps.graph_stream) {
+      if (!launch_rounds_graph(E, gcache, ps.graph_stream, depth - 1,
+                               round_grids(E, m, false, true), timing ? ev : nullptr)) {
+        hipGetLastError();
+        status = kErrRuntime;
+        break;
+      }
+    } else {
+      const RoundGrids G = round_grids(E, m, false, false);
+      for (int d = 1; d < depth; d++)
+        launch_round(E, G, timing ? ev[2 * d] : nullptr, timing ? ev[2 * d + 1] : nullptr,
+                     nullptr);
     }
     first = false;
     if (hipMemcpyAsync(mirror, E.rc, sizeof(RoundCtl), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -2263,6 +2354,7 @@ void emit(int r, const uint32_t *occ, uint64_t n_r, const TableView &T, const in
     case 4: hipLaunchKernelGGL(k_emit<4>, grid, blk, 0, st, occ, n_r, T, new2old, kround, nrounds, rcl_out, kappa_out); break;
     case 5: hipLaunchKernelGGL(k_emit<5>, grid, blk, 0, st, occ, n_r, T, new2old, kround, nrounds, rcl_out, kappa_out); break;
     case 6: hipLaunchKernelGGL(k_emit<6>, grid, blk, 0, st, occ, n_r, T, new2old, kround, nrounds, rcl_out, kappa_out); break;
+    case 7: hipLaunchKernelGGL(k_emit<7>, grid, blk, 0, st, occ, n_r, T, new2old, kround, nrounds, rcl_out, kappa_out); break;
     default: break;
   }
 }

@@ -299,8 +299,11 @@ void radix_sort(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t
     uint32_t *tv = vs; vs = vd; vd = tv;
   }
   if (ks != keys) {
-    hipMemcpyAsync(keys, ks, sizeof(uint64_t) * (size_t)n, hipMemcpyDeviceToDevice, st);
-    if (vals) hipMemcpyAsync(vals, vs, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToDevice, st);
+    hip_ok(hipMemcpyAsync(keys, ks, sizeof(uint64_t) * (size_t)n, hipMemcpyDeviceToDevice, st),
+           "copy sorted keys");
+    if (vals)
+      hip_ok(hipMemcpyAsync(vals, vs, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToDevice, st),
+             "copy sorted values");
   }
 }
 
@@ -317,8 +320,7 @@ uint32_t max_u32_host(const uint32_t *p, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_max_u32, dim3((unsigned)blocks_for(n, 256 * 16, 4096)), dim3(256), 0, st,
                      p, n, m.get());
   uint32_t h = 0;
-  hipMemcpyAsync(&h, m.get(), sizeof(uint32_t), hipMemcpyDeviceToHost, st);
-  hipStreamSynchronize(st);
+  read_back(&h, m.get(), sizeof(uint32_t), st);
   return h;
 }
 

@@ -78,6 +78,14 @@ def test_planted_small_all_rs(r, s):
     check_against_oracle(g, r, s)
 
 
+@pytest.mark.parametrize("r", [1, 2, 3, 4, 5, 6, 7])
+def test_s_equals_8(r):
+    """s = 8 (ND_MAX_S) for every r: planted cliques of 9-12 vertices hold
+    8-cliques; (7,8) keys need 6 * ceil(log2 n) <= 63, so n <= 1024."""
+    g = inputs.planted_er(110, 5.0, 3, 9, 12, 80 + r)
+    check_against_oracle(g, r, 8)
+
+
 @pytest.mark.parametrize("r,s", [(2, 3), (3, 4), (4, 5), (5, 6), (6, 7)])
 def test_generic_path_for_s_eq_r_plus_1(r, s):
     """The generic path (Count-Func atomics, intersection by edge tests) on
@@ -268,12 +276,15 @@ def test_malformed_graph_rejected(rows):
 def test_bad_arguments():
     nd = _nd()
     rp, col = nd.to_device(inputs.complete_graph(5))
-    for r, s in [(0, 2), (2, 2), (3, 1), (1, 8)]:
+    for r, s in [(0, 2), (2, 2), (3, 1), (1, 9), (8, 9)]:
         with pytest.raises(nd.NdError) as e:
             nd.decompose(rp, col, r, s)
         assert e.value.name == "ND_EINVAL"
     with pytest.raises(nd.NdError) as e:
         nd.decompose(rp, col, 2, 3, load_factor=0.95)
+    assert e.value.name == "ND_EINVAL"
+    with pytest.raises(nd.NdError) as e:
+        nd.decompose(rp, col, 2, 3, queue_depth=33)
     assert e.value.name == "ND_EINVAL"
 
 
@@ -422,12 +433,23 @@ def test_count_bias_overflow():
     assert e.value.name == "ND_EOVERFLOW"
 
 
-@pytest.mark.parametrize("depth", ["1", "4"])
-def test_round_queue_depth(depth, monkeypatch):
+@pytest.mark.parametrize("depth", [1, 4])
+def test_round_queue_depth(depth):
     """Results do not depend on how many rounds are queued between reads of
     the device round state."""
-    monkeypatch.setenv("ND_PEEL_DEPTH", depth)
-    check_against_oracle(inputs.rmat(10, 8, 55), 2, 4)
+    check_against_oracle(inputs.rmat(10, 8, 55), 2, 4, queue_depth=depth)
+
+
+@pytest.mark.parametrize("r,s", [(3, 4), (2, 4), (2, 3), (4, 5), (1, 2), (3, 5)])
+@pytest.mark.parametrize("timing", [False, True])  # timed runs fall back to plain launches
+def test_graph_replayed_rounds(r, s, timing):
+    """options.graph_rounds: the rounds queued after the first of every batch
+    run from captured HIP graphs, each replayed many times within the peel
+    (with the host's reads of the round state between replays); every round
+    and the final result equal the oracle's."""
+    g = inputs.rmat(10, 10, 300 + r)
+    d = check_against_oracle(g, r, s, graph_rounds=True, timing=timing, queue_depth=4)
+    assert d.stats["rounds"] > 12  # several batches of 4, so graphs are replayed
 
 
 def _random_case(seed):
