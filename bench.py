@@ -116,6 +116,10 @@ def main():
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--orient", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched: default schedules instead of the autotuner's choice")
+    ap.add_argument("--tune-sample", type=int, default=256,
+                    help="batched: graphs in the autotuner's held-out sample")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -286,24 +290,38 @@ def bench_batch(args):
     torch.cuda.set_device(0)
     dev = [nd.to_device(g, "cuda:0") for g in gs]
     torch.cuda.synchronize()
+    # schedules: the autotuner times each candidate on a held-out sample
+    tune = None
+    opts = {}
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        best, rep = nd.nd_batch_autotune(dev, r, s, sample_count=args.tune_sample)
+        opts = {"orient": best["orient"], "queue_depth": best["queue_depth"],
+                "graph_rounds": bool(best["graph_rounds"])}
+        tune = {"sample_graphs": rep["sample_graphs"], "chosen": opts,
+                "seconds": round(time.perf_counter() - t0, 2),
+                "candidates": [{k: c[k] for k in ("orient", "queue_depth", "graph_rounds", "ms")}
+                               for c in rep["candidates"]]}
+        log(f"[bench] autotune: {tune}")
     for _ in range(args.warmup):
-        res = nd.decompose_batch(dev, r, s)
+        res = nd.decompose_batch(dev, r, s, **opts)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        res = nd.decompose_batch(dev, r, s, timing=True)
+        res = nd.decompose_batch(dev, r, s, **opts)
     torch.cuda.synchronize()
     batched_s = (time.perf_counter() - t0) / max(1, args.steps)
     st = res.stats
     log(f"[bench] batched: {batched_s * 1000:.1f} ms per batch, rounds {st['rounds']}, "
         f"n_r {st['n_r']}, n_s {st['n_s']}")
-    # the same graphs, one decomposition (plan, run, destroy) after another
-    nd.decompose(*dev[0], r, s)
+    # the same graphs, one decomposition (plan, run, destroy) after another,
+    # with the same schedule options
+    nd.decompose(*dev[0], r, s, **opts)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     singles = []
     for i, (rp, col) in enumerate(dev):
-        d = nd.decompose(rp, col, r, s)
+        d = nd.decompose(rp, col, r, s, **opts)
         if i % 257 == 0:
             singles.append((i, d))
     torch.cuda.synchronize()
@@ -333,6 +351,7 @@ def bench_batch(args):
         "data": "synthetic",
         "serial_graphs_per_s": count / serial_s,
         "speedup_vs_serial": serial_s / batched_s,
+        "autotune": tune,
         "config": {"workload": BATCH_WORKLOAD, "graphs": count, "r": r, "s": s,
                    "sum_n": int(sum(g.n for g in gs)), "sum_m": int(sum(g.m for g in gs)),
                    "n_r": st["n_r"], "n_s": st["n_s"], "rounds": st["rounds"],

@@ -218,6 +218,30 @@ nd_status nd_batch_round_trace(nd_batch b, uint64_t *sizes_host, uint32_t *level
 
 nd_status nd_batch_destroy(nd_batch b);
 
+/* Schedule autotuner for batched decompositions.  Decomposes a held-out
+ * sample of the graphs -- at most sample_count of them, spread evenly over
+ * the input -- as one batch under each candidate setting and returns the
+ * fastest setting in *best (base's other fields are kept; base may be NULL).
+ * Candidates: orientation (degree order, core order) x queue depth (8, 32)
+ * x replay of queued rounds from captured graphs (off, on).  Each candidate
+ * is timed, host clock around plan creation and run, as the better of two
+ * runs after a warm-up.  report (nullable) receives every candidate with its
+ * time and the index of the best.  Graphs as in nd_batch_create; device
+ * memory comes from the library's pool and is returned; the sample's
+ * results are discarded. */
+#define ND_TUNE_MAX 16
+typedef struct {
+  int32_t candidates;
+  int32_t best;
+  int32_t sample_graphs;
+  nd_options opt[ND_TUNE_MAX];
+  float ms[ND_TUNE_MAX];
+} nd_tune_report;
+
+nd_status nd_batch_autotune(const nd_csr *graphs, int32_t count, int r, int s,
+                            const nd_options *base, int32_t sample_count, void *hip_stream,
+                            nd_options *best, nd_tune_report *report);
+
 /* ---- Serving: continuous batching of (graph, r, s) jobs ----------------
  * A pool of `workers` threads, each with its own HIP stream on the device
  * current at creation, takes jobs from one FIFO queue.  Admission is by

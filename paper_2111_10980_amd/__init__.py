@@ -43,6 +43,15 @@ class nd_options(ctypes.Structure):
                 ("queue_depth", ctypes.c_int32), ("graph_rounds", ctypes.c_int32)]
 
 
+ND_TUNE_MAX = 16
+
+
+class nd_tune_report(ctypes.Structure):
+    _fields_ = [("candidates", ctypes.c_int32), ("best", ctypes.c_int32),
+                ("sample_graphs", ctypes.c_int32), ("opt", nd_options * ND_TUNE_MAX),
+                ("ms", ctypes.c_float * ND_TUNE_MAX)]
+
+
 class nd_roofline(ctypes.Structure):
     _fields_ = [("copy_gbs", ctypes.c_double), ("gather16_gops", ctypes.c_double),
                 ("atomic_ret_gops", ctypes.c_double), ("atomic_noret_gops", ctypes.c_double)]
@@ -88,8 +97,12 @@ def _load():
     lib.nd_batch_round_trace.argtypes = [P, P, P, ctypes.c_uint64,
                                          ctypes.POINTER(ctypes.c_uint64)]
     lib.nd_batch_destroy.argtypes = [P]
+    lib.nd_batch_autotune.argtypes = [ctypes.POINTER(nd_csr), ctypes.c_int32, ctypes.c_int,
+                                      ctypes.c_int, ctypes.POINTER(nd_options), ctypes.c_int32,
+                                      P, ctypes.POINTER(nd_options),
+                                      ctypes.POINTER(nd_tune_report)]
     for name in ("nd_batch_create", "nd_batch_sizes", "nd_batch_run", "nd_batch_round_trace",
-                 "nd_batch_destroy"):
+                 "nd_batch_destroy", "nd_batch_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     lib.nd_server_create.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(P)]
     lib.nd_server_submit.argtypes = [P, ctypes.POINTER(nd_csr), ctypes.c_int, ctypes.c_int,
@@ -141,7 +154,7 @@ EXPORTED = ("nd_plan_create", "nd_plan_sizes", "nd_run", "nd_run_noalloc", "nd_r
             "nd_plan_destroy",
             "nd_release_cached", "nd_status_str", "nd_last_error", "nd_roofline_measure",
             "nd_batch_create", "nd_batch_sizes", "nd_batch_run", "nd_batch_round_trace",
-            "nd_batch_destroy", "nd_server_create", "nd_server_submit", "nd_server_wait",
+            "nd_batch_destroy", "nd_batch_autotune", "nd_server_create", "nd_server_submit", "nd_server_wait",
             "nd_server_result", "nd_server_copy", "nd_server_release", "nd_server_destroy")
 
 
@@ -305,6 +318,33 @@ def nd_batch_round_trace(batch):
 
 def nd_batch_destroy(batch):
     _check(_lib.nd_batch_destroy(batch))
+
+
+def _options_dict(o: nd_options) -> dict:
+    return {name: getattr(o, name) for name, _ in nd_options._fields_}
+
+
+def nd_batch_autotune(graphs, r: int, s: int, sample_count: int = 256, stream=None, **base):
+    """Tunes orientation, queue depth and graph replay on a held-out sample of
+    the graphs; returns (best options dict, report dict)."""
+    arr = (nd_csr * max(1, len(graphs)))()
+    keep = []
+    for i, (rp, col) in enumerate(graphs):
+        rp = rp.contiguous()
+        col = col.contiguous()
+        keep.append((rp, col))
+        arr[i] = nd_csr(int(rp.numel() - 1), int(col.numel()), rp.data_ptr(),
+                        col.data_ptr() if col.numel() else None)
+    b = make_options(**base)
+    best = nd_options()
+    rep = nd_tune_report()
+    _check(_lib.nd_batch_autotune(arr, len(graphs), int(r), int(s), ctypes.byref(b),
+                                  int(sample_count), _stream_handle(stream), ctypes.byref(best),
+                                  ctypes.byref(rep)))
+    cands = [dict(_options_dict(rep.opt[i]), ms=float(rep.ms[i]))
+             for i in range(rep.candidates)]
+    return _options_dict(best), {"sample_graphs": int(rep.sample_graphs), "best": int(rep.best),
+                                 "candidates": cands}
 
 
 def nd_server_create(workers: int, hbm_budget_bytes: int = 0):

@@ -1190,6 +1190,74 @@ nd_status nd_batch_destroy(nd_batch b) {
   return ND_OK;
 }
 
+nd_status nd_batch_autotune(const nd_csr *graphs, int32_t count, int r, int s,
+                            const nd_options *base, int32_t sample_count, void *hip_stream,
+                            nd_options *best, nd_tune_report *report) {
+  if (!best || (count > 0 && !graphs) || count < 0 || sample_count < 1) {
+    g_last_error = "bad autotune arguments";
+    return ND_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  return guarded(st, [&] {
+    // held-out sample: graphs spread evenly over the input
+    const int32_t m = std::min(count, sample_count);
+    std::vector<nd_csr> sample((size_t)std::max(m, 1));
+    for (int32_t k = 0; k < m; k++) sample[k] = graphs[(int64_t)k * count / m];
+    nd_options b0{};
+    if (base) b0 = *base;
+    b0.timing = 0;
+    std::vector<nd_options> cand;
+    for (int orient = 0; orient < 2; orient++)
+      for (int depth : {8, 32})
+        for (int graph = 0; graph < 2; graph++) {
+          nd_options o = b0;
+          o.orient = orient;
+          o.queue_depth = depth;
+          o.graph_rounds = graph;
+          cand.push_back(o);
+        }
+    std::vector<float> ms(cand.size(), 0.f);
+    auto one = [&](const nd_options &o) -> double {
+      nd_batch b = nullptr;
+      const auto t0 = std::chrono::steady_clock::now();
+      nd_status rc = nd_batch_create(sample.data(), m, r, s, &o, 0, hip_stream, &b);
+      if (rc != ND_OK) throw Failure{rc};
+      uint64_t n_r = 0, wsb = 0;
+      int32_t cnt = 0;
+      nd_batch_sizes(b, &n_r, &cnt, &wsb);
+      DevBuf<unsigned char> ws(wsb + kWsAlign);
+      DevBuf<int32_t> rcl(n_r ? n_r * (uint64_t)r : 1);
+      DevBuf<uint32_t> kap(n_r ? n_r : 1);
+      std::vector<uint64_t> off((size_t)cnt + 1);
+      char *wp = (char *)ws.get();
+      wp += (kWsAlign - ((uintptr_t)wp & (kWsAlign - 1))) & (kWsAlign - 1);
+      rc = nd_batch_run(b, wp, wsb, rcl.get(), kap.get(), nullptr, off.data(), nullptr);
+      const auto t1 = std::chrono::steady_clock::now();
+      nd_batch_destroy(b);
+      if (rc != ND_OK) throw Failure{rc};
+      return std::chrono::duration<double, std::milli>(t1 - t0).count();
+    };
+    one(cand[0]);  // warm-up: code objects, pool
+    size_t bi = 0;
+    for (size_t i = 0; i < cand.size(); i++) {
+      ms[i] = (float)std::min(one(cand[i]), one(cand[i]));
+      if (ms[i] < ms[bi]) bi = i;
+    }
+    *best = cand[bi];
+    if (base) best->timing = base->timing;
+    if (report) {
+      memset(report, 0, sizeof(*report));
+      report->candidates = (int32_t)std::min<size_t>(cand.size(), ND_TUNE_MAX);
+      report->best = (int32_t)bi;
+      report->sample_graphs = m;
+      for (int32_t i = 0; i < report->candidates; i++) {
+        report->opt[i] = cand[i];
+        report->ms[i] = ms[i];
+      }
+    }
+  });
+}
+
 nd_status nd_release_cached(void) {
   return guarded(nullptr, [&] {
     hip_check(hipDeviceSynchronize(), "synchronize");

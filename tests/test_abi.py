@@ -61,7 +61,7 @@ def test_struct_layouts_match_c(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     structs = {"nd_csr": nd.nd_csr, "nd_options": nd.nd_options, "nd_stats": nd.nd_stats,
-               "nd_roofline": nd.nd_roofline}
+               "nd_roofline": nd.nd_roofline, "nd_tune_report": nd.nd_tune_report}
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "nd.h"',
              '#include "nd_roofline.h"', "int main(void) {"]
     for sname, cls in structs.items():

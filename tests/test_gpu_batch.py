@@ -96,3 +96,46 @@ def test_batch_empty_and_errors():
     with pytest.raises(nd.NdError) as e:
         nd.decompose_batch([good, (rp, col)], 2, 3)
     assert e.value.name == "ND_EGRAPH"
+
+
+def test_batch_canonical_rows():
+    """options.canonical on a batch: each graph's rows come out in
+    lexicographic order (graph-local ids), equal to the oracle's table."""
+    nd = _nd()
+    gs = mixed_graphs(seed=5, count=24)
+    dev = [nd.to_device(g) for g in gs]
+    res = nd.decompose_batch(dev, 3, 4, with_counts=True, canonical=True)
+    rcl = res.rcliques.cpu().numpy()
+    kap = res.kappa.cpu().numpy().view(np.uint32)
+    off = res.row_offsets
+    for gi, g in enumerate(gs):
+        a, b = int(off[gi]), int(off[gi + 1])
+        ref = oracle.decompose(g.n, g.row_ptr, g.col, 3, 4)
+        np.testing.assert_array_equal(rcl[a:b], ref.rcliques)
+        np.testing.assert_array_equal(kap[a:b].astype(np.uint64), ref.kappa)
+
+
+def test_autotuned_batch():
+    """The schedule autotuner times every candidate on a held-out sample and
+    returns the fastest; the batch decomposed with it matches the oracle."""
+    nd = _nd()
+    gs = mixed_graphs(seed=11, count=40)
+    dev = [nd.to_device(g) for g in gs]
+    best, rep = nd.nd_batch_autotune(dev, 3, 4, sample_count=12)
+    assert rep["sample_graphs"] == 12 and len(rep["candidates"]) == 8
+    times = [c["ms"] for c in rep["candidates"]]
+    assert all(t > 0 for t in times)
+    assert rep["candidates"][rep["best"]]["ms"] == min(times)
+    for k in ("orient", "queue_depth", "graph_rounds"):
+        assert best[k] == rep["candidates"][rep["best"]][k]
+    res = nd.decompose_batch(dev, 3, 4, orient=best["orient"], queue_depth=best["queue_depth"],
+                             graph_rounds=bool(best["graph_rounds"]))
+    rcl = res.rcliques.cpu().numpy()
+    kap = res.kappa.cpu().numpy().view(np.uint32)
+    off = res.row_offsets
+    for gi, g in enumerate(gs):
+        a, b = int(off[gi]), int(off[gi + 1])
+        ref = oracle.decompose(g.n, g.row_ptr, g.col, 3, 4)
+        grc, gk = _canon(rcl[a:b], kap[a:b])
+        np.testing.assert_array_equal(grc, ref.rcliques)
+        np.testing.assert_array_equal(gk.astype(np.uint64), ref.kappa)
