@@ -83,11 +83,16 @@ typedef struct {
                                 ND_EOVERFLOW; 0 = off (results are never changed) */
   int32_t queue_depth;   /* most peel rounds queued between two reads of the device round
                             state, 1..32; 0 = 32 */
+  int32_t contract_off;  /* (2,3) only: 1 = no graph contraction (Section 4.6: after every
+                            2n peeled edges, the listed adjacency of each vertex that lost
+                            a quarter of its neighbours since its last contraction is
+                            filtered of peeled edges); 0 = contraction on */
   int32_t graph_rounds;  /* 1 = the rounds queued after the first of each batch are
                             captured once into a HIP graph (per queue depth and grid
                             class) and replayed with one launch; 0 = plain launches.
                             Ignored with timing (events recorded by graph nodes cannot
                             be timed) */
+  int32_t pad;           /* reserved, 0 */
 } nd_options;
 
 typedef struct {
@@ -114,6 +119,8 @@ typedef struct {
   uint64_t workspace_bytes;   /* workspace bytes the run carved */
   uint64_t max_round_records; /* largest number of records one peel round wrote */
   uint64_t max_round_arcs;    /* s >= r+2: largest number of out-arcs one round walked */
+  uint32_t contractions;      /* (2,3): graph contraction passes */
+  uint32_t reserved;
 } nd_stats;
 
 typedef struct nd_plan_s *nd_plan; /* opaque, library-owned */

@@ -124,6 +124,26 @@ __global__ __launch_bounds__(256) void k_sum_slot_counts(const Slot *__restrict_
   }
 }
 
+// (2,3) run state: every apex list at its full length, every edge alive; no
+// vertex has lost a neighbour, each at its full degree.
+__global__ void k_r2_init_arcs(const uint64_t *__restrict__ lptr, uint64_t nnz, uint32_t *llen,
+                               uint8_t *arcst) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)nnz;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    llen[e] = (uint32_t)(lptr[e + 1] - lptr[e]);
+    arcst[e] = 0;
+  }
+}
+
+__global__ void k_r2_init_vertices(const int64_t *__restrict__ rp, int32_t n, uint32_t *lost,
+                                   uint32_t *deg_at) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    lost[v] = 0;
+    deg_at[v] = (uint32_t)(rp[v + 1] - rp[v]);
+  }
+}
+
 // A re-run starts from the table as built: counts 0, every r-clique live.
 __global__ void k_reset_slots(Slot *s, uint64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)n;
@@ -614,6 +634,16 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
       build_slot_loc(p->g, r, p->table(), p->n_slots, &p->fx, st);
       p->held += p->fx.bm_words * 8 + p->fx.n_tri * 4 + (uint64_t)(gin->nnz + 1) * 8 +
                  p->n_slots * 8;
+      if (r == 2) {  // (2,3) run state: bitmaps, apex lists, edge states, loss counters
+        p->fx.alive.reset(p->fx.bm_words ? p->fx.bm_words : 1);
+        p->fx.lvr.reset(p->fx.n_tri ? p->fx.n_tri : 1);
+        p->fx.llen.reset((size_t)gin->nnz + 1);
+        p->fx.arcst.reset((size_t)gin->nnz + 1);
+        p->fx.lost.reset(n > 0 ? (size_t)n : 1);
+        p->fx.deg_at.reset(n > 0 ? (size_t)n : 1);
+        p->held += 8 * (p->fx.bm_words + 1) + 4 * (p->fx.n_tri + 1) + 5 * (uint64_t)(gin->nnz + 1) +
+                   8 * (uint64_t)(n + 1);
+      }
       if (r == 3) {  // liveness and frontier bits, reset by every run
         const uint64_t bw = p->fx.bm_words ? p->fx.bm_words : 1;
         const uint64_t aw = (p->fx.n_tri + 63) / 64 ? (p->fx.n_tri + 63) / 64 : 1;
@@ -730,6 +760,23 @@ void run_impl(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *counts
   uint32_t *kap_out = canon ? kap_tmp.get() : kappa_dev;
   uint32_t *cnt_out = canon ? cnt_tmp.get() : counts_dev;
   if (cnt_out) gather_counts(p->occ.get(), p->n_r, p->slots.get(), cnt_out, st);
+  if (p->fast && r == 2) {  // (2,3): the listed adjacency starts as the graph's
+    const uint64_t nnz = (uint64_t)p->g.nnz;
+    if (p->fx.bm_words)
+      hip_check(hipMemcpyAsync(p->fx.alive.get(), p->fx.bm.get(), 8 * p->fx.bm_words,
+                               hipMemcpyDeviceToDevice, st),
+                "copy bitmaps");
+    if (p->fx.n_tri)
+      hip_check(hipMemcpyAsync(p->fx.lvr.get(), p->fx.lval.get(), 4 * p->fx.n_tri,
+                               hipMemcpyDeviceToDevice, st),
+                "copy apex lists");
+    if (nnz)
+      hipLaunchKernelGGL(k_r2_init_arcs, dim3((unsigned)grid_for((int64_t)nnz, 256)), dim3(256), 0,
+                         st, p->fx.lptr.get(), nnz, p->fx.llen.get(), p->fx.arcst.get());
+    if (p->g.n)
+      hipLaunchKernelGGL(k_r2_init_vertices, dim3((unsigned)grid_for(p->g.n, 256)), dim3(256), 0,
+                         st, p->g.rp.get(), p->g.n, p->fx.lost.get(), p->fx.deg_at.get());
+  }
   if (p->fast && r == 3) {  // liveness bitmaps start as the adjacency bitmaps
     if (p->fx.bm_words)
       hip_check(hipMemcpyAsync(p->fx.alive.get(), p->fx.bm.get(), 8 * p->fx.bm_words,
@@ -751,6 +798,8 @@ void run_impl(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *counts
   ps.mirror = p->mirror;
   ps.ev = timing && p->ev_peel.ok && !p->ev_peel.ev.empty() ? p->ev_peel.ev.data() : nullptr;
   ps.queue_depth = p->opt.queue_depth ? p->opt.queue_depth : kPeelMaxDepth;
+  // (2,3) graph contraction after every 2n peeled edges (Section 4.6)
+  ps.contract_every = p->fast && r == 2 && !p->opt.contract_off ? 2ull * (uint64_t)p->g.n : 0;
   // events recorded by graph nodes cannot be timed: timed runs launch plainly
   ps.graph_stream = timing ? nullptr : p->graph_stream;
   const uint32_t perr =
@@ -844,6 +893,7 @@ void run_impl(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *counts
     stats->workspace_bytes = g_ws->used;
     stats->max_round_records = pr.max_rec;
     stats->max_round_arcs = pr.max_arcs;
+    stats->contractions = pr.contractions;
   }
 }
 

@@ -154,17 +154,31 @@ struct FastView {
   uint64_t *front_apex;                 // r = 3: apex-entry bits of the same (else null)
   const uint32_t *__restrict__ rowpre;  // r = 3 ranked table: per out-arc (v, N+(v)[i]) the
                                         // triangles of v's bitmap rows before i (else null)
+  // r = 2 (the (2,3) peel), else null: the run's copy of the apex lists,
+  // compacted by graph contraction, with each list's live length; one state
+  // byte per arc position (alive / in the frontier / peeled); per vertex the
+  // incident edges peeled since its last contraction and its degree then
+  int32_t *lvr;
+  uint32_t *llen;
+  uint8_t *arcst;
+  uint32_t *lost;
+  uint32_t *deg_at;
 };
 struct FastIndex {
   DevBuf<uint64_t> bm_off, bm, lptr, alive, alive_apex, front, front_apex;
   DevBuf<uint32_t> rowpre;
+  DevBuf<int32_t> lvr;                    // r = 2 run state (see FastView)
+  DevBuf<uint32_t> llen, lost, deg_at;
+  DevBuf<uint8_t> arcst;
   DevBuf<uint64_t> loc;  // per slot: local indices of v2..vr in N+(v1), 9 bits each
   DevBuf<int32_t> lval;
   uint64_t bm_words = 0, n_tri = 0;
   FastView view() const {
-    return FastView{bm_off.get(), bm.get(),        lptr.get(),  lval.get(),
-                    alive.get(),  alive_apex.get(), front.get(), front_apex.get(),
-                    rowpre.n ? rowpre.get() : nullptr};
+    return FastView{bm_off.get(),  bm.get(),         lptr.get(),  lval.get(),
+                    alive.get(),   alive_apex.get(), front.get(), front_apex.get(),
+                    rowpre.n ? rowpre.get() : nullptr,
+                    lvr.get(),     llen.get(),       arcst.get(), lost.get(),
+                    deg_at.get()};
   }
 };
 // tri_per_root (nullable, n entries) receives the triangles rooted at each
@@ -199,6 +213,7 @@ struct PeelResult {
   uint64_t need_rec = 0;         // kErrCapacity: record capacity the halted round needs
   uint64_t need_trace = 0;       // kErrCapacity: round-trace capacity needed
   uint64_t max_rec = 0, max_arcs = 0;  // largest per-round record / out-arc totals
+  uint32_t contractions = 0;           // r = 2: graph contraction passes
 };
 constexpr int kPeelMaxDepth = 32;      // rounds queued between two reads of the state
 constexpr uint64_t kArcsPerRecord = 4; // s >= r+2: out-arc capacity per record slot
@@ -207,6 +222,7 @@ constexpr uint64_t kArcsPerRecord = 4; // s >= r+2: out-arc capacity per record 
 // 2 * kPeelMaxDepth events (else null), the queue depth and, for graph
 // replay of queued rounds, the capture stream.
 struct PeelState {
+  uint64_t contract_every = 0;           // r = 2: contract after this many peeled edges (0 = never)
   RoundCtl *rc = nullptr;
   RoundCtl *mirror = nullptr;
   hipEvent_t *ev = nullptr;

@@ -388,6 +388,10 @@ struct RoundCtl {
   uint64_t total3, cap3;   // third list (out-arcs of members) / capacity
   uint64_t need;           // capacity asked for when a round halted (halt 1: total, 4: total3)
   uint64_t max_total, max_total3;  // largest record / out-arc totals of a finished round
+  uint64_t contract_every;  // r = 2 graph contraction: peeled edges between contractions (0 off)
+  uint64_t peeled_since;    // edges peeled since the last contraction
+  uint32_t contract_due;    // set when peeled_since reaches contract_every
+  uint32_t contractions;    // contraction passes done
   uint32_t t, k, kw, nF;   // round, level, window top, |A_t|
   uint32_t nW, nH;         // window list and high list sizes
   uint32_t selF, selW, selH;

@@ -131,6 +131,8 @@ __device__ void round_begin_body(RoundCtl *rc, Counters *dc) {
 // empty round (one that only dropped the window list) is not counted.
 __device__ void round_end_body(RoundCtl *rc, const Counters *dc) {
   if (rc->nF == 0) return;
+  rc->peeled_since += rc->nF;
+  if (rc->contract_every && rc->peeled_since >= rc->contract_every) rc->contract_due = 1;
   if (rc->total > rc->max_total) rc->max_total = rc->total;
   if (rc->total3 > rc->max_total3) rc->max_total3 = rc->total3;
   rc->trace_size[rc->t] = rc->nF;
@@ -381,6 +383,32 @@ __device__ __forceinline__ int64_t lower_pos(const int32_t *__restrict__ a, int6
     else hi = mid;
   }
   return lo;
+}
+
+// r = 2 arc states, one byte per arc position of G' (both directions of an
+// edge carry the same state): alive, in the current round's frontier, or
+// peeled in an earlier round.
+constexpr uint8_t kArcAlive = 0, kArcFront = 1, kArcDead = 2;
+
+__device__ __forceinline__ void set_edge_state(const GraphView &g, int32_t a, int32_t b,
+                                               uint8_t *st, uint8_t v) {
+  const int32_t lo = a < b ? a : b, hi = a < b ? b : a;
+  const int64_t e = arc_pos(g, lo, hi);
+  if (e < 0) return;
+  st[e] = v;
+  const int64_t q = lower_pos(g.col, g.rp[hi], g.up[hi], lo);  // lo sits in hi's lower part
+  if (q < g.up[hi] && g.col[q] == lo) st[q] = v;
+}
+
+// r = 2, R = {u0 < u1}: may R list the s-clique R + x (s = 3)?  Not if one of
+// x's edges to R was peeled earlier (the triangle is gone), nor if one is in
+// the frontier and comes before R in the triangle's subset order ({x,u0}
+// does when x < u1, {x,u1} when x < u0): that edge owns it (Update-Func's
+// owner rule) and R would only probe it to skip it.
+__device__ __forceinline__ bool r2_lists(uint8_t s0, uint8_t s1, int32_t x, int32_t u0,
+                                         int32_t u1) {
+  return s0 != kArcDead && s1 != kArcDead && !(s0 == kArcFront && x < u1) &&
+         !(s1 == kArcFront && x < u0);
 }
 
 // r = 3 liveness bitmaps.  A triangle's bits in its root's alive bitmap are
@@ -877,6 +905,8 @@ __global__ __launch_bounds__(256) void k_expand_bound(PeelArgs base, RoundCtl *r
     decode_key<R>(sl.key, a.T.bits, Rv);
 #pragma unroll
     for (int i = 0; i < R; i++) fv[f * R + i] = Rv[i];
+    if constexpr (R == 2)  // frontier edges are marked for this round's expand pass
+      if (fx.arcst) set_edge_state(a.g, Rv[0], Rv[1], fx.arcst, kArcFront);
     if (sl.cnt != 0) {  // otherwise every s-clique of R is already gone
       const int64_t o = a.g.up[Rv[0]];
       const int d = (int)(a.g.rp[Rv[0] + 1] - o);
@@ -885,7 +915,8 @@ __global__ __launch_bounds__(256) void k_expand_bound(PeelArgs base, RoundCtl *r
         uint64_t total1 = 0;
         if (d <= 512) {
           const int wd = (d + 63) >> 6;
-          const uint64_t *rows = (R == 3 ? fx.alive : fx.bm) + fx.bm_off[Rv[0]];
+          const uint64_t *rows =
+              (R == 3 || (R == 2 && fx.alive) ? fx.alive : fx.bm) + fx.bm_off[Rv[0]];
           for (int w = 0; w < wd; w++) {
             uint64_t x = ~0ull;
 #pragma unroll
@@ -898,7 +929,7 @@ __global__ __launch_bounds__(256) void k_expand_bound(PeelArgs base, RoundCtl *r
           total1 = (uint64_t)d;
         }
         int drv = 1;
-        uint64_t len2 = fx.lptr[e[1] + 1] - fx.lptr[e[1]];
+        uint64_t len2 = (R == 2 && fx.llen) ? fx.llen[e[1]] : fx.lptr[e[1] + 1] - fx.lptr[e[1]];
 #pragma unroll
         for (int i = 2; i < R; i++) {
           const uint64_t len = fx.lptr[e[i] + 1] - fx.lptr[e[i]];
@@ -989,7 +1020,7 @@ __global__ __launch_bounds__(256, 8) void k_expand(PeelArgs base, RoundCtl *rc, 
     uint64_t cw = 0;
     if (has_bm) {
       const int wd = (d + 63) >> 6;
-      const uint64_t *rows = (R == 3 ? fx.alive : fx.bm) + ds.bmo;
+      const uint64_t *rows = (R == 3 || (R == 2 && fx.alive) ? fx.alive : fx.bm) + ds.bmo;
       if (lane < wd) {
         cw = ~0ull;
 #pragma unroll
@@ -1043,12 +1074,28 @@ __global__ __launch_bounds__(256, 8) void k_expand(PeelArgs base, RoundCtl *rc, 
           x = a.g.col[o + lxw];
         } else {
           x = a.g.col[o + (int64_t)k];
+          if constexpr (R != 2) {
 #pragma unroll
-          for (int i = 1; i < R; i++) in = in && adjacent(a.g, x, fv[f * R + i]);
+            for (int i = 1; i < R; i++) in = in && adjacent(a.g, x, fv[f * R + i]);
+          }
+        }
+        if constexpr (R == 2) {  // x > v1: edge {v1,x} at its place in N+(v1)
+          const int32_t v1 = fv[f * 2], v2 = fv[f * 2 + 1];
+          const int64_t e1 = o + (int64_t)(has_bm ? lxw : (uint32_t)k);
+          const int64_t e2 = arc_pos(a.g, v2, x);
+          in = in && e2 >= 0;
+          if (in && fx.arcst) in = r2_lists(fx.arcst[e1], fx.arcst[e2], x, v1, v2);
         }
       } else if (in) {
         const uint64_t q1 = lb + (k - total1);
-        x = fx.lval[q1];
+        x = (R == 2 && fx.lvr) ? fx.lvr[q1] : fx.lval[q1];
+        if constexpr (R == 2) {  // x < v1: both edges sit in N+(x)
+          if (fx.arcst) {
+            const int32_t v1 = fv[f * 2], v2 = fv[f * 2 + 1];
+            const int64_t e1 = arc_pos(a.g, x, v1), e2 = arc_pos(a.g, x, v2);
+            in = e1 >= 0 && e2 >= 0 && r2_lists(fx.arcst[e1], fx.arcst[e2], x, v1, v2);
+          }
+        }
         if constexpr (R == 3) {
           // x < v1: S = {x, v1, v2, v3}; the triangles {x, v1, v2} and {x, v1, v3}
           // are the apex entries at q1 and at x's place in the other list
@@ -1533,20 +1580,6 @@ __global__ void k_emit(const uint32_t *__restrict__ occ, uint64_t n_r, TableView
 //   apply:  the out-arcs (x, y) of 64 members spread over a wave: y in I(R)
 //           closes R + {x, y} (s = r + 2) or starts a deeper extension.
 
-// r = 2 arc states of the s >= r+2 path, one byte per arc position of G'
-// (both directions of an edge carry the same state).
-constexpr uint8_t kArcAlive = 0, kArcFront = 1, kArcDead = 2;
-
-__device__ __forceinline__ void set_edge_state(const GraphView &g, int32_t a, int32_t b,
-                                               uint8_t *st, uint8_t v) {
-  const int32_t lo = a < b ? a : b, hi = a < b ? b : a;
-  const int64_t e = arc_pos(g, lo, hi);
-  if (e < 0) return;
-  st[e] = v;
-  const int64_t q = lower_pos(g.col, g.rp[hi], g.up[hi], lo);  // lo sits in hi's lower part
-  if (q < g.up[hi] && g.col[q] == lo) st[q] = v;
-}
-
 template <int R>
 __global__ __launch_bounds__(256) void k_gen_bound(PeelArgs base, RoundCtl *rc, uint64_t *ioff,
                                                    uint32_t *ilen, int32_t *fv, int32_t *drv,
@@ -1844,6 +1877,104 @@ __global__ __launch_bounds__(256) void k_gen_retire2(GraphView g, const RoundCtl
     set_edge_state(g, fv[f * 2], fv[f * 2 + 1], arcst, kArcDead);
 }
 
+// r = 2 on the s = r+1 path, end of the round's update: the frontier's edges
+// become dead (both arc directions) and count as lost neighbours of both
+// endpoints for graph contraction.
+__global__ __launch_bounds__(256) void k_retire2(GraphView g, const RoundCtl *rc,
+                                                 const int32_t *__restrict__ fv, FastView fx) {
+  if (rc_idle(rc)) return;
+  const uint32_t nF = rc->nF;
+  for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nF;
+       f += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t a = fv[f * 2], b = fv[f * 2 + 1];
+    set_edge_state(g, a, b, fx.arcst, kArcDead);
+    atomicAdd(&fx.lost[a], 1u);
+    atomicAdd(&fx.lost[b], 1u);
+  }
+}
+
+// Graph contraction for (2,3) (Section 4.6): once the peeled edges since the
+// last contraction reach the threshold (twice the vertex count), every
+// vertex v that lost at least a quarter of its neighbours since its last
+// contraction has its adjacency filtered of peeled edges.  Here v's
+// adjacency as the peel lists it is v's bitmap over N+(v) (the rows and
+// columns of dead out-edges and the bits of dead edges between two
+// out-neighbours are cleared) and the apex lists of v's out-arcs (entries
+// whose triangle has a dead edge are compacted away).  A wave per vertex;
+// runs between rounds, when no edge is in a frontier.  Listing stays exact
+// without it (the per-candidate edge states decide); it removes work.
+__global__ __launch_bounds__(256) void k_contract2(GraphView g, FastView fx) {
+  __shared__ uint64_t dead_col[256 / kWave][kMaxBitmapWords];
+  const int wv = threadIdx.x / kWave, lane = lane_id();
+  for (int64_t v = (int64_t)blockIdx.x * (256 / kWave) + wv; v < g.n;
+       v += (int64_t)gridDim.x * (256 / kWave)) {
+    const uint32_t lost = fx.lost[v];
+    if (lost == 0 || 4ull * lost < fx.deg_at[v]) continue;  // wave-uniform
+    const int64_t o = g.up[v];
+    const int d = (int)(g.rp[v + 1] - o);
+    if (d > 0 && d <= 64 * kMaxBitmapWords) {
+      const int wd = (d + 63) >> 6;
+      unsigned long long *rows = (unsigned long long *)(fx.alive + fx.bm_off[v]);
+      if (lane < kMaxBitmapWords) dead_col[wv][lane] = 0;
+      __builtin_amdgcn_wave_barrier();
+      for (int i = lane; i < d; i += kWave)
+        if (fx.arcst[o + i] == kArcDead) atomicOr((unsigned long long *)&dead_col[wv][i >> 6],
+                                                  1ull << (i & 63));
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      for (int i = lane; i < d; i += kWave) {
+        const bool row_dead = (dead_col[wv][i >> 6] >> (i & 63)) & 1ull;
+        const int32_t ai = g.col[o + i];
+        for (int w = 0; w < wd; w++) {
+          uint64_t clear = row_dead ? ~0ull : dead_col[wv][w];
+          if (!row_dead) {  // live bits (i, j), j > i: drop dead edges {a_i, a_j}
+            uint64_t m = rows[(int64_t)i * wd + w] & ~clear & ~below_mask(i + 1, w);
+            while (m) {
+              const int b = __builtin_ctzll(m);
+              m &= m - 1;
+              const int j = w * 64 + b;
+              const int64_t q = arc_pos(g, ai, g.col[o + j]);
+              if (q < 0 || fx.arcst[q] == kArcDead) {
+                clear |= 1ull << b;
+                atomicAnd(&rows[(int64_t)j * wd + (i >> 6)], ~(1ull << (i & 63)));
+              }
+            }
+          }
+          if (clear) atomicAnd(&rows[(int64_t)i * wd + w], ~clear);
+        }
+      }
+    }
+    for (int i = lane; i < d; i += kWave) {  // apex lists of v's out-arcs
+      const int64_t e = o + i;
+      if (fx.arcst[e] == kArcDead) {  // its own edge is gone: never listed again
+        fx.llen[e] = 0;
+        continue;
+      }
+      const int32_t a = g.col[e];
+      const uint64_t b0 = fx.lptr[e];
+      const uint32_t n0 = fx.llen[e];
+      uint32_t keep = 0;
+      for (uint32_t q = 0; q < n0; q++) {
+        const int32_t x = fx.lvr[b0 + q];
+        const int64_t e1 = arc_pos(g, x, (int32_t)v), e2 = arc_pos(g, x, a);
+        if (e1 >= 0 && e2 >= 0 && fx.arcst[e1] != kArcDead && fx.arcst[e2] != kArcDead)
+          fx.lvr[b0 + keep++] = x;
+      }
+      fx.llen[e] = keep;
+    }
+    if (lane == 0) {
+      fx.deg_at[v] -= lost;
+      fx.lost[v] = 0;
+    }
+  }
+}
+
+__global__ void k_contract_done(RoundCtl *rc) {
+  rc->peeled_since = 0;
+  rc->contract_due = 0;
+  rc->contractions++;
+}
+
 dim3 blocks_for(uint64_t n, uint64_t per, uint64_t lo, uint64_t hi) {
   uint64_t b = (n + per - 1) / per;
   b = b < lo ? lo : b;
@@ -1907,6 +2038,9 @@ void launch_fast(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, dim3 ga, hip
     hipLaunchKernelGGL(k_apply<R>, ga, dim3(256), 0, E.st, base, E.rc, E.rec.get(),
                        E.fv.get(), E.fxv, E.loc, E.rloc.get(), E.f23.get());
   if (e1) hipEventRecord(e1, E.st);
+  if constexpr (R == 2)
+    if (E.fxv.arcst)
+      hipLaunchKernelGGL(k_retire2, gf, dim3(256), 0, E.st, E.gv, E.rc, E.fv.get(), E.fxv);
 }
 
 template <int R, int S>
@@ -2192,6 +2326,7 @@ uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableVie
   h.cap = E.cap;
   h.cap3 = E.cap3;
   h.nH = (uint32_t)n_r;
+  h.contract_every = ps.contract_every;
   h.mw = kNone;
   h.mh = kNone;
   RoundCtl *mirror = ps.mirror;
@@ -2259,6 +2394,13 @@ uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableVie
       break;
     }
     if (m.done) break;
+    if (m.contract_due) {  // graph contraction before the next batch of rounds
+      hipLaunchKernelGGL(k_contract2, dim3((unsigned)grid_for(g.n, 256 / kWave, 16384)), dim3(256),
+                         0, st, E.gv, E.fxv);
+      hipLaunchKernelGGL(k_contract_done, dim3(1), dim3(1), 0, st, E.rc);
+      m.contract_due = 0;
+      m.peeled_since = 0;
+    }
     // deepen the queue while rounds are short, back off while they are long
     const double dt =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -2268,6 +2410,7 @@ uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableVie
   }
   if (status) return status;
   res->advances = m.advances;
+  res->contractions = m.contractions;
   res->max_rec = m.max_total;
   res->max_arcs = m.max_total3;
   res->apply_launches = m.t;

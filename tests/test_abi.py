@@ -45,10 +45,10 @@ def test_status_strings_without_gpu():
 def test_struct_layouts():
     import paper_2111_10980_amd as nd
     assert ctypes.sizeof(nd.nd_csr) == 32
-    # 6 x 32-bit + 2 u64 + 2 x 32-bit
-    assert ctypes.sizeof(nd.nd_options) == 6 * 4 + 2 * 8 + 2 * 4
-    # 7 u64 + 2 u32 + 8 floats + 2 floats + 2 u32 + 4 u64
-    assert ctypes.sizeof(nd.nd_stats) == 7 * 8 + 2 * 4 + 8 * 4 + 2 * 4 + 2 * 4 + 4 * 8
+    # 6 x 32-bit + 2 u64 + 4 x 32-bit
+    assert ctypes.sizeof(nd.nd_options) == 6 * 4 + 2 * 8 + 4 * 4
+    # 7 u64 + 2 u32 + 8 floats + 2 floats + 2 u32 + 4 u64 + 2 u32
+    assert ctypes.sizeof(nd.nd_stats) == 7 * 8 + 2 * 4 + 8 * 4 + 2 * 4 + 2 * 4 + 4 * 8 + 2 * 4
 
 
 def test_struct_layouts_match_c(tmp_path):

@@ -86,6 +86,26 @@ def test_s_equals_8(r):
     check_against_oracle(g, r, 8)
 
 
+@pytest.mark.parametrize("contract_off", [False, True])
+@pytest.mark.parametrize("g", ["rmat12", "rmat_paper11", "planted", "er"])
+def test_23_graph_contraction(g, contract_off):
+    """(2,3) with and without graph contraction (Section 4.6): the listed
+    adjacency of vertices that lost a quarter of their neighbours is filtered
+    of peeled edges after every 2n peeled edges; results stay exact and the
+    contraction passes happen when enough edges are peeled."""
+    graph = {"rmat12": lambda: inputs.rmat(12, 16, 71),
+             "rmat_paper11": lambda: inputs.rmat_paper(11, 24, 72),
+             "planted": lambda: inputs.planted_er(1500, 12.0, 6, 10, 40, 73),
+             "er": lambda: inputs.erdos_renyi(800, 12000, 74)}[g]()
+    d = check_against_oracle(graph, 2, 3, contract_off=contract_off)
+    if contract_off:
+        assert d.stats["contractions"] == 0
+    elif d.stats["n_r"] >= 4 * graph.n:
+        assert d.stats["contractions"] > 0
+    # every triangle is listed once, by the edge that owns it
+    assert d.stats["discoveries"] == d.stats["n_s"]
+
+
 @pytest.mark.parametrize("r,s", [(2, 3), (3, 4), (4, 5), (5, 6), (6, 7)])
 def test_generic_path_for_s_eq_r_plus_1(r, s):
     """The generic path (Count-Func atomics, intersection by edge tests) on
