@@ -43,6 +43,8 @@ WORKLOADS = {
     "rmat18_34": ("rmat18", 3, 4, "rMAT scale 18, edge factor 16, a=.57 b=.19 c=.19 d=.05, "
                   "symmetrised, loops/duplicates removed; (3,4) nucleus"),
     "er2000_23": ("er_2000", 2, 3, "Erdos-Renyi G(n=2000, m=10000); (2,3) nucleus"),
+    "rmat18_23": ("rmat18", 2, 3, "rMAT scale 18, edge factor 16, a=.57 b=.19 c=.19 d=.05, "
+                  "symmetrised, loops/duplicates removed; (2,3) nucleus (k-truss)"),
     "chunglu1m_45": ("chung_lu_1m", 4, 5, "Chung-Lu n=1e6, avg degree 20, exponent 2.1, "
                      "200 planted cliques of size 20-60; (4,5) nucleus"),
     "chunglu1m_24": ("chung_lu_1m", 2, 4, "Chung-Lu n=1e6, avg degree 20, exponent 2.1, "
@@ -116,6 +118,8 @@ def main():
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--orient", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--contract", action="store_true",
+                    help="(2,3): graph contraction on (for the before/after comparison)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batched: default schedules instead of the autotuner's choice")
     ap.add_argument("--tune-sample", type=int, default=256,
@@ -146,7 +150,8 @@ def main():
     torch.cuda.synchronize()
 
     def step():
-        return nd.decompose(rp, col, r, s, orient=args.orient, timing=True)
+        return nd.decompose(rp, col, r, s, orient=args.orient, timing=True,
+                            contract=args.contract)
 
     for i in range(args.warmup):
         d = step()
@@ -263,7 +268,8 @@ def main():
                    "max_kappa": st["max_kappa"], "orientation": ["degree", "core"][args.orient],
                    "max_out_degree": st["max_out_degree"], "decrements": st["decrements"],
                    "atomics": st["atomics"], "discoveries": st["discoveries"], "k_advances": st["k_advances"],
-                   "table_slots": st["table_slots"], "phase_ms": st["ms"]},
+                   "table_slots": st["table_slots"], "contractions": st["contractions"],
+                   "contract": bool(args.contract), "phase_ms": st["ms"]},
         "roofline": roofline,
         "cpu_baseline": base,
     }

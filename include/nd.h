@@ -83,10 +83,11 @@ typedef struct {
                                 ND_EOVERFLOW; 0 = off (results are never changed) */
   int32_t queue_depth;   /* most peel rounds queued between two reads of the device round
                             state, 1..32; 0 = 32 */
-  int32_t contract_off;  /* (2,3) only: 1 = no graph contraction (Section 4.6: after every
-                            2n peeled edges, the listed adjacency of each vertex that lost
-                            a quarter of its neighbours since its last contraction is
-                            filtered of peeled edges); 0 = contraction on */
+  int32_t contract;      /* (2,3) only: 1 = graph contraction (Section 4.6: after every 2n
+                            peeled edges, the listed adjacency of each vertex that lost a
+                            quarter of its neighbours since its last contraction is
+                            filtered of its peeled edges); 0 = off (default: measured
+                            slower on rMAT-18, since each triangle is listed once anyway) */
   int32_t graph_rounds;  /* 1 = the rounds queued after the first of each batch are
                             captured once into a HIP graph (per queue depth and grid
                             class) and replayed with one launch; 0 = plain launches.

@@ -526,6 +526,7 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
     if (p->opt.canonical != 0 && p->opt.canonical != 1) fail(ND_EINVAL, "canonical must be 0 or 1");
     if (p->opt.queue_depth < 0 || p->opt.queue_depth > kPeelMaxDepth)
       fail(ND_EINVAL, "queue_depth must be in 0..%d", kPeelMaxDepth);
+    if (p->opt.contract != 0 && p->opt.contract != 1) fail(ND_EINVAL, "contract must be 0 or 1");
     if (p->opt.graph_rounds != 0 && p->opt.graph_rounds != 1)
       fail(ND_EINVAL, "graph_rounds must be 0 or 1");
     p->fast = (s == r + 1) && r >= 2 && r <= 6 && p->opt.path == 0;
@@ -799,7 +800,7 @@ void run_impl(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *counts
   ps.ev = timing && p->ev_peel.ok && !p->ev_peel.ev.empty() ? p->ev_peel.ev.data() : nullptr;
   ps.queue_depth = p->opt.queue_depth ? p->opt.queue_depth : kPeelMaxDepth;
   // (2,3) graph contraction after every 2n peeled edges (Section 4.6)
-  ps.contract_every = p->fast && r == 2 && !p->opt.contract_off ? 2ull * (uint64_t)p->g.n : 0;
+  ps.contract_every = p->fast && r == 2 && p->opt.contract ? 2ull * (uint64_t)p->g.n : 0;
   // events recorded by graph nodes cannot be timed: timed runs launch plainly
   ps.graph_stream = timing ? nullptr : p->graph_stream;
   const uint32_t perr =

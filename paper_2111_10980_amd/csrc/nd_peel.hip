@@ -1896,13 +1896,13 @@ __global__ __launch_bounds__(256) void k_retire2(GraphView g, const RoundCtl *rc
 // Graph contraction for (2,3) (Section 4.6): once the peeled edges since the
 // last contraction reach the threshold (twice the vertex count), every
 // vertex v that lost at least a quarter of its neighbours since its last
-// contraction has its adjacency filtered of peeled edges.  Here v's
-// adjacency as the peel lists it is v's bitmap over N+(v) (the rows and
-// columns of dead out-edges and the bits of dead edges between two
-// out-neighbours are cleared) and the apex lists of v's out-arcs (entries
-// whose triangle has a dead edge are compacted away).  A wave per vertex;
-// runs between rounds, when no edge is in a frontier.  Listing stays exact
-// without it (the per-candidate edge states decide); it removes work.
+// contraction has its adjacency filtered of its peeled edges.  Here v's
+// adjacency as the peel lists it is v's bitmap over N+(v), whose rows and
+// columns of dead out-edges {v, a_i} are cleared, and the apex lists of v's
+// out-arcs, from which the lower neighbours x with a dead edge {x, v} are
+// compacted away.  A wave per vertex; runs between rounds, when no edge is
+// in a frontier.  Listing stays exact without it (the per-candidate edge
+// states decide); it only removes work.
 __global__ __launch_bounds__(256) void k_contract2(GraphView g, FastView fx) {
   __shared__ uint64_t dead_col[256 / kWave][kMaxBitmapWords];
   const int wv = threadIdx.x / kWave, lane = lane_id();
@@ -1914,33 +1914,21 @@ __global__ __launch_bounds__(256) void k_contract2(GraphView g, FastView fx) {
     const int d = (int)(g.rp[v + 1] - o);
     if (d > 0 && d <= 64 * kMaxBitmapWords) {
       const int wd = (d + 63) >> 6;
-      unsigned long long *rows = (unsigned long long *)(fx.alive + fx.bm_off[v]);
+      uint64_t *rows = fx.alive + fx.bm_off[v];
       if (lane < kMaxBitmapWords) dead_col[wv][lane] = 0;
       __builtin_amdgcn_wave_barrier();
       for (int i = lane; i < d; i += kWave)
-        if (fx.arcst[o + i] == kArcDead) atomicOr((unsigned long long *)&dead_col[wv][i >> 6],
-                                                  1ull << (i & 63));
+        if (fx.arcst[o + i] == kArcDead)
+          atomicOr((unsigned long long *)&dead_col[wv][i >> 6], 1ull << (i & 63));
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
+      // each lane owns whole rows: plain stores
       for (int i = lane; i < d; i += kWave) {
         const bool row_dead = (dead_col[wv][i >> 6] >> (i & 63)) & 1ull;
-        const int32_t ai = g.col[o + i];
         for (int w = 0; w < wd; w++) {
-          uint64_t clear = row_dead ? ~0ull : dead_col[wv][w];
-          if (!row_dead) {  // live bits (i, j), j > i: drop dead edges {a_i, a_j}
-            uint64_t m = rows[(int64_t)i * wd + w] & ~clear & ~below_mask(i + 1, w);
-            while (m) {
-              const int b = __builtin_ctzll(m);
-              m &= m - 1;
-              const int j = w * 64 + b;
-              const int64_t q = arc_pos(g, ai, g.col[o + j]);
-              if (q < 0 || fx.arcst[q] == kArcDead) {
-                clear |= 1ull << b;
-                atomicAnd(&rows[(int64_t)j * wd + (i >> 6)], ~(1ull << (i & 63)));
-              }
-            }
-          }
-          if (clear) atomicAnd(&rows[(int64_t)i * wd + w], ~clear);
+          const uint64_t x = rows[(int64_t)i * wd + w];
+          const uint64_t y = row_dead ? 0ull : x & ~dead_col[wv][w];
+          if (y != x) rows[(int64_t)i * wd + w] = y;
         }
       }
     }
@@ -1950,15 +1938,13 @@ __global__ __launch_bounds__(256) void k_contract2(GraphView g, FastView fx) {
         fx.llen[e] = 0;
         continue;
       }
-      const int32_t a = g.col[e];
       const uint64_t b0 = fx.lptr[e];
       const uint32_t n0 = fx.llen[e];
       uint32_t keep = 0;
       for (uint32_t q = 0; q < n0; q++) {
         const int32_t x = fx.lvr[b0 + q];
-        const int64_t e1 = arc_pos(g, x, (int32_t)v), e2 = arc_pos(g, x, a);
-        if (e1 >= 0 && e2 >= 0 && fx.arcst[e1] != kArcDead && fx.arcst[e2] != kArcDead)
-          fx.lvr[b0 + keep++] = x;
+        const int64_t e1 = arc_pos(g, x, (int32_t)v);
+        if (e1 >= 0 && fx.arcst[e1] != kArcDead) fx.lvr[b0 + keep++] = x;
       }
       fx.llen[e] = keep;
     }

@@ -86,9 +86,9 @@ def test_s_equals_8(r):
     check_against_oracle(g, r, 8)
 
 
-@pytest.mark.parametrize("contract_off", [False, True])
+@pytest.mark.parametrize("contract", [False, True])
 @pytest.mark.parametrize("g", ["rmat12", "rmat_paper11", "planted", "er"])
-def test_23_graph_contraction(g, contract_off):
+def test_23_graph_contraction(g, contract):
     """(2,3) with and without graph contraction (Section 4.6): the listed
     adjacency of vertices that lost a quarter of their neighbours is filtered
     of peeled edges after every 2n peeled edges; results stay exact and the
@@ -97,8 +97,8 @@ def test_23_graph_contraction(g, contract_off):
              "rmat_paper11": lambda: inputs.rmat_paper(11, 24, 72),
              "planted": lambda: inputs.planted_er(1500, 12.0, 6, 10, 40, 73),
              "er": lambda: inputs.erdos_renyi(800, 12000, 74)}[g]()
-    d = check_against_oracle(graph, 2, 3, contract_off=contract_off)
-    if contract_off:
+    d = check_against_oracle(graph, 2, 3, contract=contract)
+    if not contract:
         assert d.stats["contractions"] == 0
     elif d.stats["n_r"] >= 4 * graph.n:
         assert d.stats["contractions"] > 0
