@@ -206,14 +206,47 @@ __device__ __forceinline__ void update_func(const PeelArgs &a, const int32_t (&S
     key[q] = make_key<R>(Rv, a.T.bits);
     want[q] = active && cb.mask[q] != rmask;
   }
+  // The other subsets are looked up two at a time, and the lookups stop at
+  // the first one peeled in an earlier round: S is gone then, and the
+  // remaining probes would only confirm it.  (Each s-clique is listed again
+  // from every subset peeled after it was destroyed; with all probes at once
+  // those repeat listings carried most of the update pass's traffic.)
   int64_t pos[N];
   Slot sl[N];
-  table_find_n<N>(a.T, v1, key, want, pos, sl);
+  bool alive = active;
+#pragma unroll
+  for (int g0 = 0; g0 < N; g0 += 2) {
+    int32_t gv[2];
+    uint64_t gk[2];
+    bool gw[2];
+    int64_t gp[2];
+    Slot gs[2];
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+      const int q = g0 + j < N ? g0 + j : N - 1;
+      gv[j] = v1[q];
+      gk[j] = key[q];
+      gw[j] = g0 + j < N && want[q] && alive;
+    }
+    table_find_n<2>(a.T, gv, gk, gw, gp, gs);
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+      if (g0 + j >= N) continue;
+      pos[g0 + j] = gp[j];
+      sl[g0 + j] = gs[j];
+      if (!gw[j]) continue;
+      if (gp[j] < 0) {
+        ls.err |= kErrLookup;
+        alive = false;
+      } else if (gs[j].stamp < a.t) {
+        alive = false;  // S was destroyed in an earlier round
+      }
+    }
+  }
   int self = 0;  // this r-clique's place in the subset order
 #pragma unroll
   for (int q = 0; q < N; q++)
     if (cb.mask[q] == rmask) self = q;
-  bool alive = active;
   bool other_owner = false;
   // hot: live (not peeled) and its count read above the level.  A count read
   // at or below the level has crossed k+1 (and the window level) already:
@@ -224,13 +257,8 @@ __device__ __forceinline__ void update_func(const PeelArgs &a, const int32_t (&S
 #pragma unroll
   for (int q = 0; q < N; q++) {
     hot[q] = false;
-    if (!want[q]) continue;
-    if (pos[q] < 0) {
-      ls.err |= kErrLookup;
-      alive = false;
-    } else if (sl[q].stamp < a.t) {
-      alive = false;  // S was destroyed in an earlier round
-    } else if (sl[q].stamp == a.t) {
+    if (!want[q] || !alive) continue;  // every subset was looked up when S is alive
+    if (sl[q].stamp == a.t) {
       other_owner = other_owner || q < self;  // peeled with R and first in order
     } else {
       n_live++;

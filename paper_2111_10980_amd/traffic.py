@@ -13,6 +13,9 @@ reader can tell whether the numbers still describe the current kernels.
 
 Usage:
   python -m paper_2111_10980_amd.traffic FETCH_CSV WRITE_CSV KERNEL_REGEX OUT_JSON
+  python -m paper_2111_10980_amd.traffic --counters CSV [CSV ...] > table.md
+The second form reduces any counter CSVs to one row per kernel: dispatches
+and the mean value of every counter per dispatch.
 """
 from __future__ import annotations
 
@@ -81,7 +84,37 @@ def traffic(fetch_csv: str, write_csv: str, kernel_re: str) -> dict:
     }
 
 
+def counter_table(paths) -> str:
+    """Markdown table: per kernel, dispatches and each counter's mean per dispatch."""
+    acc = {}
+    names = []
+    for path in paths:
+        for r in csv.DictReader(open(path)):
+            k = re.sub(r"\(.*", "", r["Kernel_Name"].replace("(anonymous namespace)::", ""))
+            k = k.replace("void ", "")
+            c = r["Counter_Name"]
+            if c not in names:
+                names.append(c)
+            d = acc.setdefault(k, {})
+            v = d.setdefault(c, [0.0, 0])
+            v[0] += float(r["Counter_Value"])
+            v[1] += 1
+    lines = ["| kernel | dispatches | " + " | ".join(names) + " |",
+             "|---|---:|" + "---:|" * len(names)]
+    for k, d in sorted(acc.items()):
+        n = max(v[1] for v in d.values())
+        cells = []
+        for c in names:
+            v = d.get(c)
+            cells.append(f"{v[0] / v[1]:.4g}" if v else "")
+        lines.append(f"| {k} | {n} | " + " | ".join(cells) + " |")
+    return "\n".join(lines)
+
+
 if __name__ == "__main__":
+    if len(sys.argv) >= 3 and sys.argv[1] == "--counters":
+        print(counter_table(sys.argv[2:]))
+        sys.exit(0)
     if len(sys.argv) != 5:
         print(__doc__)
         sys.exit(2)
