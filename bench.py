@@ -36,6 +36,7 @@ SLOT_BYTES = 16                # one r-clique table slot {key, count, stamp}
 
 BATCH_WORKLOAD = "batch4096_34"
 SERVE_WORKLOAD = "serve_rmat"
+SERVE_CLASSES_WORKLOAD = "serve_classes"
 SWEEP_WORKLOAD = "rmat_density_sweep"
 
 WORKLOADS = {
@@ -106,7 +107,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat18_34",
-                    choices=sorted(WORKLOADS) + [BATCH_WORKLOAD, SERVE_WORKLOAD, SWEEP_WORKLOAD])
+                    choices=sorted(WORKLOADS) + [BATCH_WORKLOAD, SERVE_WORKLOAD, SWEEP_WORKLOAD,
+                                                 SERVE_CLASSES_WORKLOAD])
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--rates", default="5,10,20,40",
                     help="serving: Poisson arrival rates (jobs/s) to sweep")
@@ -114,6 +116,9 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=30, help="serving: warm-up jobs per rate")
     ap.add_argument("--max-scale", type=int, default=11, help="serving: largest rMAT scale")
     ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--class-cap-s", type=float, default=20.0,
+                    help="serving classes: skip a class at the next scale once one job of it "
+                         "would take longer than this")
     ap.add_argument("--hbm-budget-gb", type=float, default=200.0)
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--orient", type=int, default=0)
@@ -138,6 +143,8 @@ def main():
         return bench_batch(args)
     if args.workload == SERVE_WORKLOAD:
         return bench_serve(args)
+    if args.workload == SERVE_CLASSES_WORKLOAD:
+        return bench_serve_classes(args)
     if args.workload == SWEEP_WORKLOAD:
         return bench_sweep(args)
     gen, r, s, desc = WORKLOADS[args.workload]
@@ -539,6 +546,75 @@ def bench_serve(args):
                    "scales": [10, args.max_scale], "edge_factor": [8, 16], "r": [1, 3],
                    "s": "r+1..r+2", "hbm_budget_gb": args.hbm_budget_gb,
                    "workers": args.serve_workers, "sweep": sweep},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve_classes(args):
+    """Service time of every job class of the serving mix (rMAT, r in 1..3,
+    s in r+1..r+2) alone on the GPU, scale 10 up to 20, at edge factor 16 (the
+    heaviest of the mix's 8..16), one warm-up and one timed decomposition per
+    point.  A class stops growing in scale once its next job would take longer
+    than --class-cap-s (estimated from the growth of the last two scales).  The
+    mix's mean service time over scale ~U{10..20} and (r,s) ~U then bounds the
+    arrival rate one GPU sustains; classes not measured are reported, and the
+    bound is given over the measured scales only."""
+    import numpy as np
+    import torch
+    import paper_2111_10980_amd as nd
+    from paper_2111_10980_amd import inputs
+    torch.cuda.set_device(0)
+    classes = [(r, s) for r in (1, 2, 3) for s in (r + 1, r + 2)]
+    table = {}
+    for r, s in classes:
+        prev = []
+        for scale in range(10, 21):
+            if len(prev) >= 2:
+                growth = prev[-1] / max(prev[-2], 1e-3)
+                if prev[-1] * growth > args.class_cap_s:
+                    log(f"[bench] ({r},{s}) stops before scale {scale}: next job ~"
+                        f"{prev[-1] * growth:.1f} s")
+                    break
+            g = inputs.rmat(scale, 16, 7000 + scale)
+            rp, col = nd.to_device(g, "cuda:0")
+            nd.decompose(rp, col, r, s)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            d = nd.decompose(rp, col, r, s)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            prev.append(dt)
+            table[(r, s, scale)] = {"ms": round(1000 * dt, 2), "n_r": d.stats["n_r"],
+                                    "n_s": d.stats["n_s"], "rounds": d.stats["rounds"]}
+            log(f"[bench] ({r},{s}) scale {scale}: {1000 * dt:.1f} ms, n_r {d.stats['n_r']}, "
+                f"n_s {d.stats['n_s']}")
+            del rp, col, d
+            nd.nd_release_cached()
+            torch.cuda.empty_cache()
+    measured_scales = sorted({k[2] for k in table})
+    full = [sc for sc in measured_scales if all((r, s, sc) in table for r, s in classes)]
+    top = max(full) if full else 10
+    mean_ms = float(np.mean([table[(r, s, sc)]["ms"] for r, s in classes
+                             for sc in range(10, top + 1)]))
+    out = {
+        "metric": "serving: sustainable arrival rate of one GPU (mean service time bound)",
+        "value": 1000.0 / mean_ms,
+        "unit": "jobs/s",
+        "n_gpus": 1,
+        "steps": len(table),
+        "warmup": 1,
+        "ms_per_step": mean_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": SERVE_CLASSES_WORKLOAD, "edge_factor": 16,
+                   "mix_scales_covered": [10, top],
+                   "classes": {f"({r},{s}) s{sc}": v for (r, s, sc), v in sorted(table.items())},
+                   "not_measured": [f"({r},{s}) s{sc}" for r, s in classes
+                                    for sc in range(10, 21) if (r, s, sc) not in table],
+                   "cap_s": args.class_cap_s},
     }
     print(json.dumps(out), flush=True)
 
