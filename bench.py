@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=30, help="serving: warm-up jobs per rate")
     ap.add_argument("--max-scale", type=int, default=11, help="serving: largest rMAT scale")
     ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--classes", default="",
+                    help="serving classes: only these (r,s), e.g. '3,4;3,5' (default all)")
     ap.add_argument("--class-cap-s", type=float, default=20.0,
                     help="serving classes: skip a class at the next scale once one job of it "
                          "would take longer than this")
@@ -565,8 +567,13 @@ def bench_serve_classes(args):
     from paper_2111_10980_amd import inputs
     torch.cuda.set_device(0)
     classes = [(r, s) for r in (1, 2, 3) for s in (r + 1, r + 2)]
+    only = [tuple(int(x) for x in c.split(",")) for c in args.classes.split(";")] \
+        if args.classes else classes
     table = {}
+    failed = {}
     for r, s in classes:
+        if (r, s) not in only:
+            continue
         prev = []
         for scale in range(10, 21):
             if len(prev) >= 2:
@@ -577,12 +584,20 @@ def bench_serve_classes(args):
                     break
             g = inputs.rmat(scale, 16, 7000 + scale)
             rp, col = nd.to_device(g, "cuda:0")
-            nd.decompose(rp, col, r, s)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            d = nd.decompose(rp, col, r, s)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
+            try:
+                nd.decompose(rp, col, r, s)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                d = nd.decompose(rp, col, r, s)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+            except (torch.OutOfMemoryError, nd.NdError) as e:  # does not fit one GPU
+                failed[f"({r},{s}) s{scale}"] = str(e)[:160]
+                log(f"[bench] ({r},{s}) scale {scale}: {str(e)[:160]}")
+                del rp, col
+                nd.nd_release_cached()
+                torch.cuda.empty_cache()
+                break
             prev.append(dt)
             table[(r, s, scale)] = {"ms": round(1000 * dt, 2), "n_r": d.stats["n_r"],
                                     "n_s": d.stats["n_s"], "rounds": d.stats["rounds"]}
@@ -592,10 +607,10 @@ def bench_serve_classes(args):
             nd.nd_release_cached()
             torch.cuda.empty_cache()
     measured_scales = sorted({k[2] for k in table})
-    full = [sc for sc in measured_scales if all((r, s, sc) in table for r, s in classes)]
+    full = [sc for sc in measured_scales if all((r, s, sc) in table for r, s in only)]
     top = max(full) if full else 10
-    mean_ms = float(np.mean([table[(r, s, sc)]["ms"] for r, s in classes
-                             for sc in range(10, top + 1)]))
+    mean_ms = float(np.mean([table[(r, s, sc)]["ms"] for r, s in only
+                             for sc in range(10, top + 1)])) if full else float("nan")
     out = {
         "metric": "serving: sustainable arrival rate of one GPU (mean service time bound)",
         "value": 1000.0 / mean_ms,
@@ -612,8 +627,9 @@ def bench_serve_classes(args):
         "config": {"workload": SERVE_CLASSES_WORKLOAD, "edge_factor": 16,
                    "mix_scales_covered": [10, top],
                    "classes": {f"({r},{s}) s{sc}": v for (r, s, sc), v in sorted(table.items())},
-                   "not_measured": [f"({r},{s}) s{sc}" for r, s in classes
+                   "not_measured": [f"({r},{s}) s{sc}" for r, s in only
                                     for sc in range(10, 21) if (r, s, sc) not in table],
+                   "failed": failed,
                    "cap_s": args.class_cap_s},
     }
     print(json.dumps(out), flush=True)

@@ -809,8 +809,8 @@ void run_impl(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *counts
   if (perr & kErrCapacity) {
     // the workspace was too small for one round: raise the requirement so
     // that nd_plan_sizes reports the size to run again with
-    if (pr.need_rec > rec_cap)  // later rounds may need more: grow at least 8-fold
-      p->rec_need = std::max<uint64_t>(pr.need_rec + pr.need_rec / 4, 8 * rec_cap);
+    if (pr.need_rec > rec_cap)  // later rounds may need more: half again, at least double
+      p->rec_need = std::max<uint64_t>(pr.need_rec + pr.need_rec / 2, 2 * rec_cap);
     if (pr.need_trace > tcap)  // rho is unknown: grow the trace 8-fold, to at least 4096
       p->trace_need = (uint32_t)std::min<uint64_t>(
           std::max<uint64_t>(std::max<uint64_t>(pr.need_trace, 8ull * tcap), 4096),

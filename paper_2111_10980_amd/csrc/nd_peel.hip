@@ -1032,7 +1032,7 @@ __global__ __launch_bounds__(256, 8) void k_expand(PeelArgs base, RoundCtl *rc, 
   const int wpb = blockDim.x / kWave;
   const int wv = threadIdx.x / kWave;
   const int lane = lane_id();
-  __shared__ int32_t lbuf[256 / kWave][R == 3 ? kListCap : 1];
+  __shared__ int32_t lbuf[256 / kWave][R == 3 ? kListCap + 1 : 1];  // padded: see k_count_group
   for (int64_t f = (int64_t)blockIdx.x * wpb + wv; f < nF; f += (int64_t)gridDim.x * wpb) {
     const uint64_t b = off[f];
     const uint64_t total = len[f];
@@ -1279,7 +1279,10 @@ __global__ __launch_bounds__(256) void k_count_group(PeelArgs a, FastView fx,
   const int gpb = blockDim.x / G;
   const int gi = threadIdx.x / G;
   const int gl = threadIdx.x % G;
-  __shared__ int32_t lbuf[256 / G][R == 3 ? kGroupList : 1];
+  // one word of padding per group's share: the groups' binary searches start
+  // at similar midpoints, and unpadded shares 128 words apart put them in the
+  // same LDS bank (2.1 conflict cycles per LDS instruction measured)
+  __shared__ int32_t lbuf[256 / G][R == 3 ? kGroupList + 1 : 1];
   for (int64_t it = (int64_t)blockIdx.x * gpb + gi; it < (int64_t)n_r;
        it += (int64_t)gridDim.x * gpb) {  // group-uniform
     const uint32_t p = occ[it];
@@ -1674,6 +1677,7 @@ __global__ __launch_bounds__(256) void k_gen_spread(RoundCtl *rc, const uint64_t
 
 // A thread per candidate x of the round: flag x when it lies in I(R) and
 // list the members that have out-arcs as (frontier index, x).
+// r = 1 and r = 2 list each s-clique once, from its owner.
 // r = 2: arcst[e] says whether the edge of arc position e was peeled in an
 // earlier round (dead) or is in this round's frontier.  A candidate x joins
 // I(R), R = {u < v}, only if both its edges to R are alive (no s-clique
@@ -1688,7 +1692,8 @@ __global__ __launch_bounds__(256) void k_gen_member(GraphView g, RoundCtl *rc,
                                                     const int32_t *__restrict__ fv,
                                                     const int32_t *__restrict__ drv, uint8_t *flag,
                                                     int2 *mrec, uint64_t *mbeg, uint32_t *aown,
-                                                    const uint8_t *__restrict__ arcst) {
+                                                    const uint8_t *__restrict__ arcst,
+                                                    TableView T) {
   if (rc_idle(rc)) return;
   const uint64_t C = rc->total;
   const uint64_t cap3 = rc->cap3;
@@ -1705,7 +1710,15 @@ __global__ __launch_bounds__(256) void k_gen_member(GraphView g, RoundCtl *rc,
       const int32_t v = drv[f];
       const int64_t ev = g.rp[v] + (int64_t)(k - ioff[f]);
       x = g.col[ev];
-      if constexpr (R == 2) {
+      if constexpr (R == 1) {
+        // r = 1: the r-subsets are the vertices, stamped in their one-slot
+        // segments.  x peeled earlier: every s-clique through it is gone; x
+        // in this round's frontier below v: it owns them (Update-Func's
+        // owner rule).  Either way R = {v} would only probe them to skip them.
+        const uint32_t sx = T.slots[T.seg[x]].stamp;
+        const uint32_t t = rc->t;
+        in = !(sx != kLive && (sx < t || (sx == t && x < v)));
+      } else if constexpr (R == 2) {
         const int32_t u0 = fv[(int64_t)f * 2], u1 = fv[(int64_t)f * 2 + 1];  // u0 < u1
         const int32_t w = u0 == v ? u1 : u0;
         const int64_t ew = arc_pos(g, x, w);
@@ -2066,7 +2079,7 @@ void launch_gen(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, dim3 gc, dim3
                      E.owner.get());
   hipLaunchKernelGGL(k_gen_member<R>, gc, dim3(256), 0, E.st, E.gv, E.rc, E.off.get(),
                      E.owner.get(), E.fv.get(), E.drv.get(), E.flag.get(), E.rec.get(),
-                     E.mbeg.get(), E.aown.get(), E.dead.get());
+                     E.mbeg.get(), E.aown.get(), E.dead.get(), E.T);
   if (e0) hipEventRecord(e0, E.st);
   hipLaunchKernelGGL((k_gen_apply<R, S>), ga, dim3(256), 0, E.st, base, E.rc, E.off.get(),
                      E.fv.get(), E.drv.get(), E.flag.get(), E.rec.get(), E.mbeg.get(),
