@@ -41,7 +41,7 @@ typedef enum {
   ND_OK = 0,
   ND_EINVAL = 1,     /* bad argument: r < 1, s <= r, s > ND_MAX_S, null pointer, ... */
   ND_EGRAPH = 2,     /* CSR is not simple/symmetric/sorted, or ids out of range */
-  ND_EKEYWIDTH = 3,  /* (r-1) * ceil(log2 n) > 63: an r-clique key does not fit 64 bits */
+  ND_EKEYWIDTH = 3,  /* (r-1) * ceil(log2 n) > 126: an r-clique key does not fit two words */
   ND_EOVERFLOW = 4,  /* an s-clique count exceeds UINT32_MAX, the table exceeds 2^32-1 slots,
                         or the graph has more than 2^31-1 r-cliques */
   ND_ENOMEM = 5,     /* device memory budget exceeded or allocation failed */
@@ -121,7 +121,8 @@ typedef struct {
   uint64_t max_round_records; /* largest number of records one peel round wrote */
   uint64_t max_round_arcs;    /* s >= r+2: largest number of out-arcs one round walked */
   uint32_t contractions;      /* (2,3): graph contraction passes */
-  uint32_t reserved;
+  uint32_t key_words;         /* 64-bit words per r-clique key: 1, or 2 when the r-1
+                                 vertex fields of ceil(log2 n) bits need more than 63 */
 } nd_stats;
 
 typedef struct nd_plan_s *nd_plan; /* opaque, library-owned */
@@ -129,7 +130,9 @@ typedef struct nd_plan_s *nd_plan; /* opaque, library-owned */
 /* Validate the graph (a1), orient and relabel it (a2: Section 2
  * "O(alpha)-Orientation", Section 4.4 "Graph Relabeling") and build the
  * two-level r-clique table (a3: Sections 4.1-4.3, contiguous last-level
- * tables, slot position = r-clique index).  hbm_budget_bytes bounds the
+ * tables, slot position = r-clique index).  A last-level key packs the
+ * r-clique's other r-1 vertices, ceil(log2 n) bits each, into one 64-bit word,
+ * or into two when they need more than 63 bits (ND_EKEYWIDTH beyond 126).  hbm_budget_bytes bounds the
  * plan's device memory plus the workspace its run needs (0 = no budget): a
  * plan that would exceed it fails with ND_ENOMEM once n_r is known, before
  * the table is allocated.  On success *out owns device memory until

@@ -68,7 +68,7 @@ class nd_stats(ctypes.Structure):
                 ("peel_launches", ctypes.c_uint32), ("atomics", ctypes.c_uint64),
                 ("workspace_bytes", ctypes.c_uint64), ("max_round_records", ctypes.c_uint64),
                 ("max_round_arcs", ctypes.c_uint64), ("contractions", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("key_words", ctypes.c_uint32)]
 
 
 def _load():

@@ -382,6 +382,7 @@ struct nd_plan_s {
   DevBuf<uint64_t> seg;
   DevBuf<Slot> slots;
   DevBuf<int32_t> v1;
+  DevBuf<uint64_t> khi;  // second key words, when (r-1) * bits > 63
   DevBuf<uint32_t> occ;
   DevBuf<Counters> ctr;
   DevBuf<unsigned long long> stats;  // kStatLines x kStatStride statistic lines
@@ -393,6 +394,7 @@ struct nd_plan_s {
   int path = 0;       // peel path: 0 walker, 1 s = r+1 passes, 2 s >= r+2 passes
   uint64_t n_r = 0, n_slots = 0, held = 0;
   int bits = 1;
+  bool wide = false;  // two-word r-clique keys
   int runs = 0;
   bool traced = false;
   uint64_t rec_need = 0;     // record capacity the next run's workspace provides at least
@@ -405,7 +407,9 @@ struct nd_plan_s {
   EventSet ev_run;     // 5: run phases, 2: count kernels
   EventSet ev_peel;    // timing: 2 * kPeelMaxDepth around the update passes
   hipStream_t graph_stream = nullptr;  // graph_rounds: capture stream of queued rounds
-  TableView table() const { return TableView{bits, seg.get(), slots.get(), v1.get()}; }
+  TableView table() const {
+    return TableView{bits, seg.get(), slots.get(), v1.get(), wide ? khi.get() : nullptr};
+  }
   ~nd_plan_s() {
     if (mirror) hipHostFree(mirror);
     if (graph_stream) hipStreamDestroy(graph_stream);
@@ -479,7 +483,7 @@ const char *nd_status_str(nd_status st) {
     case ND_OK: return "ok";
     case ND_EINVAL: return "invalid argument";
     case ND_EGRAPH: return "malformed graph";
-    case ND_EKEYWIDTH: return "r-clique key does not fit 64 bits";
+    case ND_EKEYWIDTH: return "r-clique key does not fit two 64-bit words";
     case ND_EOVERFLOW: return "count or size overflow";
     case ND_ENOMEM: return "out of device memory or budget";
     case ND_EHIP: return "HIP runtime error";
@@ -558,8 +562,11 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
     tm.mark(1, st);
     int vb = bits_for(n > 1 ? (uint64_t)(n - 1) : 1);
     p->bits = vb < 1 ? 1 : vb;
-    if ((r - 1) * p->bits > 63)
-      fail(ND_EKEYWIDTH, "(r-1)*ceil(log2 n) = %d exceeds 63", (r - 1) * p->bits);
+    // r-clique keys: (r-1) fields of `bits` in one word, or in two when they
+    // need more than 63 bits
+    if ((r - 1) * p->bits > 126)
+      fail(ND_EKEYWIDTH, "(r-1)*ceil(log2 n) = %d exceeds 126", (r - 1) * p->bits);
+    p->wide = (r - 1) * p->bits > 63;
     const uint64_t fixed_bytes = ws_buf<Counters>(1) + ws_buf<unsigned long long>(
                                      (uint64_t)kStatLines * kStatStride) +
                                  ws_buf<unsigned long long>(2) + ws_buf<RoundCtl>(1);
@@ -608,7 +615,8 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
     p->trace_need = p->opt.trace_cap
                         ? p->opt.trace_cap
                         : (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(p->n_r, 1u << 20));
-    uint64_t table_bytes = p->n_slots * (sizeof(Slot) + 4) + p->n_r * 4 * 5;
+    uint64_t table_bytes =
+        p->n_slots * (sizeof(Slot) + 4 + (p->wide ? 8 : 0)) + p->n_r * 4 * 5;
     p->held = graph_bytes + table_bytes + (uint64_t)(n + 1) * 8 + fixed_bytes;
     // the budget covers the plan and the workspace of its run; checked before
     // the table is allocated
@@ -618,6 +626,7 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
            (unsigned long long)p->budget);
     p->slots.reset(p->n_slots ? p->n_slots : 1);
     p->v1.reset(p->n_slots ? p->n_slots : 1);
+    if (p->wide) p->khi.reset(p->n_slots ? p->n_slots : 1);
     fill_slots(p->slots.get(), (int64_t)p->n_slots, st);
     fill_u32(&p->ctr.get()->err, 0, 1, st);
     if (ranked) {
@@ -895,6 +904,7 @@ void run_impl(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *counts
     stats->max_round_records = pr.max_rec;
     stats->max_round_arcs = pr.max_arcs;
     stats->contractions = pr.contractions;
+    stats->key_words = p->wide ? 2 : 1;
   }
 }
 

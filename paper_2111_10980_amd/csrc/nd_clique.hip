@@ -228,7 +228,7 @@ struct CountOp {
     constexpr int N = cb.N;
     l.ns++;
     int32_t v1[N];
-    uint64_t key[N];
+    Key key[N];
     bool want[N];
 #pragma unroll
     for (int q = 0; q < N; q++) {

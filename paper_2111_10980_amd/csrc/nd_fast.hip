@@ -218,7 +218,7 @@ __global__ __launch_bounds__(256) void k_insert_ranked(GraphView g, const uint64
           const int j = w * 64 + __ffsll((unsigned long long)m) - 1;
           m &= m - 1;
           const int32_t Rv[3] = {(int32_t)v, a, g.col[o + j]};
-          T.slots[pos].key = make_key<3>(Rv, T.bits);
+          T.slots[pos].key = make_key<3>(Rv, T.bits).lo;  // one word for r = 3
           T.v1[pos] = (int32_t)v;
           pos++;
         }

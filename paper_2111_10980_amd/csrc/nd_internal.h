@@ -26,7 +26,7 @@ constexpr int kMaxS = 8;
 constexpr int kMaxBitmapWords = 8;           // 8 x 64 = 512 out-neighbours per root
 
 struct alignas(16) Slot {
-  uint64_t key;    // kOcc | v2 | v3 << b | ... ; 0 = empty
+  uint64_t key;    // kOcc | low 63 bits of the packed (v2, v3, ...); 0 = empty
   uint32_t cnt;    // s-clique count, decremented while peeling
   uint32_t stamp;  // round in which the r-clique was peeled, or kLive
 };
@@ -44,6 +44,16 @@ struct TableView {
   const uint64_t *__restrict__ seg;    // n+1
   Slot *__restrict__ slots;
   int32_t *__restrict__ v1;            // first vertex of each occupied slot
+  uint64_t *__restrict__ khi;          // second key word per slot, or null (keys fit 63 bits)
+};
+
+// Key of a sorted r-tuple (v1 < ... < vR) within v1's segment: the fields
+// v2..vR, `bits` each, packed from bit 0 up into at most 126 bits.  Its low
+// 63 bits plus the occupied bit form the slot's key word; its high 63 bits
+// are the second word, zero unless (R-1) * bits exceeds 63 (then the table
+// keeps them in TableView::khi).
+struct Key {
+  uint64_t lo, hi;
 };
 
 // Device-side error flags (bit set in a device word, read by the host).
@@ -115,30 +125,69 @@ __device__ __forceinline__ int64_t arc_pos(const GraphView &g, int32_t x, int32_
   return -1;
 }
 
-// Key of a sorted r-tuple: fields v[1..R-1], bits each, plus the occupied bit.
 template <int R>
-__device__ __forceinline__ uint64_t make_key(const int32_t *v, int bits) {
-  uint64_t k = kOcc;
+__device__ __forceinline__ Key make_key(const int32_t *v, int bits) {
+  uint64_t lo = 0, hi = 0;
+  if constexpr (R <= 3) {  // at most two fields of <= 31 bits: one word
 #pragma unroll
-  for (int i = 1; i < R; i++) k |= (uint64_t)(uint32_t)v[i] << (bits * (i - 1));
-  return k;
+    for (int i = 1; i < R; i++) lo |= (uint64_t)(uint32_t)v[i] << (bits * (i - 1));
+    return Key{lo | kOcc, 0ull};
+  }
+#pragma unroll
+  for (int i = 1; i < R; i++) {
+    const int o = bits * (i - 1);
+    const uint64_t f = (uint32_t)v[i];
+    if (o < 63) {
+      lo |= f << o;
+      if (o + bits > 63) hi |= f >> (63 - o);  // the field straddles the two words
+    } else {
+      hi |= f << (o - 63);
+    }
+  }
+  return Key{(lo & (kOcc - 1)) | kOcc, hi};
 }
 
+// v2..vR of the r-clique in slot p (v[0] is the caller's).
 template <int R>
-__device__ __forceinline__ void decode_key(uint64_t key, int bits, int32_t *v) {
-  uint64_t mask = (bits >= 63) ? ~0ull : ((1ull << bits) - 1ull);
+__device__ __forceinline__ void decode_key(const TableView &T, uint64_t p, uint64_t key_lo,
+                                           int32_t *v) {
+  const int bits = T.bits;  // <= 31
+  const uint64_t mask = (1ull << bits) - 1ull;
+  if constexpr (R <= 3) {  // one word
 #pragma unroll
-  for (int i = 1; i < R; i++) v[i] = (int32_t)((key >> (bits * (i - 1))) & mask);
+    for (int i = 1; i < R; i++) v[i] = (int32_t)((key_lo >> (bits * (i - 1))) & mask);
+    return;
+  }
+  const uint64_t lo = key_lo & (kOcc - 1);
+  const uint64_t hi = T.khi ? T.khi[p] : 0ull;
+#pragma unroll
+  for (int i = 1; i < R; i++) {
+    const int o = bits * (i - 1);
+    uint64_t f;
+    if (o >= 63) {
+      f = hi >> (o - 63);
+    } else {
+      f = lo >> o;
+      if (o + bits > 63) f |= hi << (63 - o);
+    }
+    v[i] = (int32_t)(f & mask);
+  }
 }
 
-__device__ __forceinline__ uint64_t home_slot(uint64_t key, uint64_t cap) {
+__device__ __forceinline__ uint64_t home_slot(const Key &key, uint64_t cap) {
   // fastrange: maps the high 32 hash bits onto [0, cap) without a division
-  return ((mix64(key) >> 32) * cap) >> 32;
+  return ((mix64(key.lo ^ (key.hi * 0x9E3779B97F4A7C15ull)) >> 32) * cap) >> 32;
+}
+
+// Does slot i (whose key word is `lo`) hold `key`?
+__device__ __forceinline__ bool key_eq(const TableView &T, uint64_t i, uint64_t lo,
+                                       const Key &key) {
+  return lo == key.lo && (!T.khi || T.khi[i] == key.hi);
 }
 
 // Linear probe of the last-level table of vertex v1.  Returns the slot
 // index, or -1 when absent; *out receives the slot's contents.
-__device__ __forceinline__ int64_t table_find(const TableView &T, int32_t v1, uint64_t key,
+__device__ __forceinline__ int64_t table_find(const TableView &T, int32_t v1, const Key &key,
                                               Slot *out) {
   uint64_t base = T.seg[v1];
   uint64_t cap = T.seg[v1 + 1] - base;
@@ -146,7 +195,7 @@ __device__ __forceinline__ int64_t table_find(const TableView &T, int32_t v1, ui
   uint64_t i = home_slot(key, cap);
   for (uint64_t probe = 0; probe < cap; probe++) {
     Slot s = T.slots[base + i];
-    if (s.key == key) {
+    if (key_eq(T, base + i, s.key, key)) {
       *out = s;
       return (int64_t)(base + i);
     }
@@ -156,15 +205,20 @@ __device__ __forceinline__ int64_t table_find(const TableView &T, int32_t v1, ui
   return -1;
 }
 
-__device__ __forceinline__ int64_t table_insert(const TableView &T, int32_t v1, uint64_t key) {
+// Every r-clique is inserted once (the listing meets each exactly once), so
+// claiming an empty slot is enough.  With two-word keys a slot whose first
+// word equals this key's holds another r-clique (or one whose second word is
+// still being written): probing goes on.
+__device__ __forceinline__ int64_t table_insert(const TableView &T, int32_t v1, const Key &key) {
   uint64_t base = T.seg[v1];
   uint64_t cap = T.seg[v1 + 1] - base;
   if (cap == 0) return -1;
   uint64_t i = home_slot(key, cap);
   for (uint64_t probe = 0; probe < cap; probe++) {
     unsigned long long *kp = (unsigned long long *)&T.slots[base + i].key;
-    unsigned long long prev = atomicCAS(kp, 0ull, (unsigned long long)key);
-    if (prev == 0ull || prev == key) {
+    unsigned long long prev = atomicCAS(kp, 0ull, (unsigned long long)key.lo);
+    if (prev == 0ull || (prev == key.lo && !T.khi)) {
+      if (T.khi) T.khi[base + i] = key.hi;
       T.v1[base + i] = v1;
       return (int64_t)(base + i);
     }
@@ -203,7 +257,7 @@ __device__ __forceinline__ void lower_bounds(const int32_t *__restrict__ a, int6
 // lookup q (pos[q] = -1).
 template <int N>
 __device__ __forceinline__ void table_find_n(const TableView &T, const int32_t (&v1)[N],
-                                             const uint64_t (&key)[N], const bool (&want)[N],
+                                             const Key (&key)[N], const bool (&want)[N],
                                              int64_t (&pos)[N], Slot (&out)[N]) {
   uint64_t base[N], cap[N], i[N];
 #pragma unroll
@@ -225,7 +279,7 @@ __device__ __forceinline__ void table_find_n(const TableView &T, const int32_t (
   for (int q = 0; q < N; q++) {
     if (!want[q] || !cap[q]) continue;
     for (uint64_t probe = 0; probe < cap[q]; probe++) {
-      if (out[q].key == key[q]) {
+      if (key_eq(T, base[q] + i[q], out[q].key, key[q])) {
         pos[q] = (int64_t)(base[q] + i[q]);
         break;
       }

@@ -195,7 +195,7 @@ __device__ __forceinline__ void update_func(const PeelArgs &a, const int32_t (&S
   constexpr Combos<S, R> cb{};
   constexpr int N = cb.N;
   int32_t v1[N];
-  uint64_t key[N];
+  Key key[N];
   bool want[N];
 #pragma unroll
   for (int q = 0; q < N; q++) {
@@ -217,7 +217,7 @@ __device__ __forceinline__ void update_func(const PeelArgs &a, const int32_t (&S
 #pragma unroll
   for (int g0 = 0; g0 < N; g0 += 2) {
     int32_t gv[2];
-    uint64_t gk[2];
+    Key gk[2];
     bool gw[2];
     int64_t gp[2];
     Slot gs[2];
@@ -344,7 +344,7 @@ __global__ __launch_bounds__(256) void k_peel(PeelArgs base, const RoundCtl *__r
     if (sl.cnt == 0) continue;  // every s-clique of R is already gone
     int32_t Rv[R];
     Rv[0] = a.T.v1[p];
-    decode_key<R>(sl.key, a.T.bits, Rv);
+    decode_key<R>(a.T, p, sl.key, Rv);
     // drive the intersection from the member of R with the smallest degree
     int drv = 0;
     int64_t best = a.g.rp[Rv[0] + 1] - a.g.rp[Rv[0]];
@@ -554,7 +554,7 @@ __global__ __launch_bounds__(256) void k_count_direct(GraphView g, TableView T, 
     const Slot sl = T.slots[p];
     int32_t Rv[R];
     Rv[0] = T.v1[p];
-    decode_key<R>(sl.key, T.bits, Rv);
+    decode_key<R>(T, p, sl.key, Rv);
     const int32_t v1 = Rv[0];
     const int64_t o = g.up[v1];
     const int d = (int)(g.rp[v1 + 1] - o);
@@ -798,7 +798,7 @@ __device__ __forceinline__ void update_r3_ranked(const PeelArgs &a, const FastVi
     }
     sl[q] = a.T.slots[pos[q]];
     const int32_t Tv[3] = {Sv[cb.idx[q][0]], Sv[cb.idx[q][1]], Sv[cb.idx[q][2]]};
-    if (sl[q].key != make_key<3>(Tv, a.T.bits)) {  // the rank must land on the triangle
+    if (sl[q].key != make_key<3>(Tv, a.T.bits).lo) {  // the rank must land on the triangle
       ls.err |= kErrLookup;
       alive = false;
     } else if (sl[q].stamp < a.t) {
@@ -930,7 +930,7 @@ __global__ __launch_bounds__(256) void k_expand_bound(PeelArgs base, RoundCtl *r
     a.T.slots[p].stamp = a.t;
     int32_t Rv[R];
     Rv[0] = a.T.v1[p];
-    decode_key<R>(sl.key, a.T.bits, Rv);
+    decode_key<R>(a.T, p, sl.key, Rv);
 #pragma unroll
     for (int i = 0; i < R; i++) fv[f * R + i] = Rv[i];
     if constexpr (R == 2)  // frontier edges are marked for this round's expand pass
@@ -1289,7 +1289,7 @@ __global__ __launch_bounds__(256) void k_count_group(PeelArgs a, FastView fx,
     const Slot sl = a.T.slots[p];
     int32_t Rv[R];
     Rv[0] = a.T.v1[p];
-    decode_key<R>(sl.key, a.T.bits, Rv);
+    decode_key<R>(a.T, p, sl.key, Rv);
     const int64_t o = a.g.up[Rv[0]];
     const int d = (int)(a.g.rp[Rv[0] + 1] - o);
     int64_t e[R];
@@ -1375,7 +1375,7 @@ __global__ void k_make_loc(GraphView g, TableView T, FastView fx, uint64_t n_slo
     if (sl.key != 0) {
       int32_t Rv[R];
       Rv[0] = T.v1[p];
-      decode_key<R>(sl.key, T.bits, Rv);
+      decode_key<R>(T, p, sl.key, Rv);
       const int64_t o = g.up[Rv[0]];
       const int d = (int)(g.rp[Rv[0] + 1] - o);
       if (d <= 512) {
@@ -1576,7 +1576,7 @@ __global__ void k_emit(const uint32_t *__restrict__ occ, uint64_t n_r, TableView
     const Slot s = T.slots[p];
     int32_t v[R];
     v[0] = T.v1[p];
-    decode_key<R>(s.key, T.bits, v);
+    decode_key<R>(T, p, s.key, v);
 #pragma unroll
     for (int j = 0; j < R; j++) v[j] = new2old[v[j]];
     // insertion sort into ascending original ids
@@ -1628,7 +1628,7 @@ __global__ __launch_bounds__(256) void k_gen_bound(PeelArgs base, RoundCtl *rc, 
       a.T.slots[p].stamp = a.t;
       int32_t Rv[R];
       Rv[0] = a.T.v1[p];
-      decode_key<R>(sl.key, a.T.bits, Rv);
+      decode_key<R>(a.T, p, sl.key, Rv);
       int32_t best_v = Rv[0];
       int64_t best = a.g.rp[Rv[0] + 1] - a.g.rp[Rv[0]];
 #pragma unroll

@@ -197,6 +197,29 @@ def planted_er(n: int, avg_deg: float, n_cliques: int, kmin: int, kmax: int,
     return csr_from_edges(n, np.concatenate(us), np.concatenate(vs))
 
 
+def sparse_with_dense_block(n: int, avg_deg: float, block: int, p: float,
+                            n_cliques: int, kmin: int, kmax: int, seed: int) -> CSR:
+    """A sparse ER graph G(n, round(n*d/2)) with a dense part: ``block`` vertex
+    ids drawn uniformly from [0, n) carry G(block, p) among themselves plus
+    ``n_cliques`` overlapping cliques of size uniform in [kmin, kmax] on
+    random subsets of the block.  Large n with the cliques concentrated on a
+    few hundred vertices (which get the top ranks of a degree order)."""
+    rng = np.random.default_rng(seed)
+    base = erdos_renyi(n, int(round(n * avg_deg / 2)), int(rng.integers(0, 2**62)))
+    bu, bv = edges_of(base)
+    ids = rng.choice(n, size=block, replace=False).astype(np.int64)
+    iu, iv = np.triu_indices(block, 1)
+    keep = rng.random(iu.size) < p
+    us, vs = [bu, ids[iu[keep]]], [bv, ids[iv[keep]]]
+    for _ in range(n_cliques):
+        k = min(int(rng.integers(kmin, kmax + 1)), block)
+        verts = ids[rng.choice(block, size=k, replace=False)]
+        cu, cv = np.triu_indices(k, 1)
+        us.append(verts[cu])
+        vs.append(verts[cv])
+    return csr_from_edges(n, np.concatenate(us), np.concatenate(vs))
+
+
 def complete_graph(n: int) -> CSR:
     iu, iv = np.triu_indices(n, 1)
     return csr_from_edges(n, iu, iv)

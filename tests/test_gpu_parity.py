@@ -75,7 +75,8 @@ def test_worked_example(r, s, generic):
 @pytest.mark.parametrize("r,s", RS_ALL)
 def test_planted_small_all_rs(r, s):
     g = inputs.planted_er(120, 6.0, 3, 6, 11, 31)
-    check_against_oracle(g, r, s)
+    d = check_against_oracle(g, r, s)
+    assert d.stats["key_words"] == 1
 
 
 @pytest.mark.parametrize("r", [1, 2, 3, 4, 5, 6, 7])
@@ -309,12 +310,44 @@ def test_bad_arguments():
 
 
 def test_key_width_rejected():
+    """Six 22-bit fields (r = 7, n > 2^21) need 132 bits: more than two words."""
     nd = _nd()
     g = inputs.csr_from_edges((1 << 21) + 2, [0, 1], [1, 2])
     rp, col = nd.to_device(g)
     with pytest.raises(nd.NdError) as e:
-        nd.decompose(rp, col, 4, 5)
+        nd.decompose(rp, col, 7, 8)
     assert e.value.name == "ND_EKEYWIDTH"
+
+
+_WIDE = {}
+
+
+def _wide_graph(n):
+    if n not in _WIDE:
+        _WIDE.clear()
+        _WIDE[n] = inputs.sparse_with_dense_block(n, 2.0, 200, 0.3, 8, 8, 14, n % 1000)
+    return _WIDE[n]
+
+
+@pytest.mark.parametrize("n,r,s,kw", [
+    # n > 2^21: 22-bit fields; r = 4 keys take 66 bits, r = 6 keys 110
+    ((1 << 21) + 4096, 4, 5, {}),
+    ((1 << 21) + 4096, 4, 5, {"generic": True}),
+    ((1 << 21) + 4096, 4, 6, {}),
+    ((1 << 21) + 4096, 5, 6, {}),
+    ((1 << 21) + 4096, 5, 7, {}),
+    ((1 << 21) + 4096, 6, 7, {}),
+    # 18-bit fields: r = 7 keys take 108 bits
+    ((1 << 17) + 100, 7, 8, {}),
+    ((1 << 17) + 100, 5, 6, {"load_factor": 0.9}),
+])
+def test_two_word_keys(n, r, s, kw):
+    """Keys of (r-1) vertex fields wider than 63 bits take a second word.  The
+    dense block's vertices get the top ranks (the highest degrees), so their
+    fields straddle the two words and fill the second."""
+    d = check_against_oracle(_wide_graph(n), r, s, **kw)
+    assert d.stats["key_words"] == 2
+    assert d.stats["n_s"] > 0
 
 
 def test_budget_rejected():
