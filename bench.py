@@ -127,6 +127,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--contract", action="store_true",
                     help="(2,3): graph contraction on (for the before/after comparison)")
+    ap.add_argument("--levels", type=int, default=0, choices=[0, 2, 3],
+                    help="r-clique table levels (3: three-level table, r >= 4)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batched: default schedules instead of the autotuner's choice")
     ap.add_argument("--tune-sample", type=int, default=256,
@@ -160,7 +162,7 @@ def main():
 
     def step():
         return nd.decompose(rp, col, r, s, orient=args.orient, timing=True,
-                            contract=args.contract)
+                            contract=args.contract, levels=args.levels)
 
     for i in range(args.warmup):
         d = step()
@@ -278,7 +280,8 @@ def main():
                    "max_out_degree": st["max_out_degree"], "decrements": st["decrements"],
                    "atomics": st["atomics"], "discoveries": st["discoveries"], "k_advances": st["k_advances"],
                    "table_slots": st["table_slots"], "contractions": st["contractions"],
-                   "contract": bool(args.contract), "phase_ms": st["ms"]},
+                   "contract": bool(args.contract), "table_levels": args.levels or 2,
+                   "key_words": st["key_words"], "phase_ms": st["ms"]},
         "roofline": roofline,
         "cpu_baseline": base,
     }

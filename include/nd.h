@@ -93,7 +93,11 @@ typedef struct {
                             class) and replayed with one launch; 0 = plain launches.
                             Ignored with timing (events recorded by graph nodes cannot
                             be timed) */
-  int32_t pad;           /* reserved, 0 */
+  int32_t levels;        /* r-clique table levels (Section 4.1): 0 or 2 = two (an array over
+                            the first vertex v1, hashed last-level tables keyed by the other
+                            r-1 vertices); 3 = three, r >= 4 only (v1, then its out-arc to v2
+                            found in v1's sorted row, hashed last-level tables per arc keyed
+                            by the other r-2 vertices) */
 } nd_options;
 
 typedef struct {

@@ -41,7 +41,7 @@ class nd_options(ctypes.Structure):
                 ("canonical", ctypes.c_int32), ("trace_cap", ctypes.c_uint32),
                 ("record_cap", ctypes.c_uint64), ("debug_count_bias", ctypes.c_uint64),
                 ("queue_depth", ctypes.c_int32), ("contract", ctypes.c_int32),
-                ("graph_rounds", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("graph_rounds", ctypes.c_int32), ("levels", ctypes.c_int32)]
 
 
 ND_TUNE_MAX = 16
@@ -177,18 +177,19 @@ def _stream_handle(stream):
 def make_options(orient: int = 0, timing: bool = False, load_factor: float = 0.0,
                  generic: bool = False, canonical: bool = False, trace_cap: int = 0,
                  record_cap: int = 0, debug_count_bias: int = 0, queue_depth: int = 0,
-                 graph_rounds: bool = False, contract: bool = False) -> nd_options:
+                 graph_rounds: bool = False, contract: bool = False,
+                 levels: int = 0) -> nd_options:
     return nd_options(int(orient), int(bool(timing)), float(load_factor), int(bool(generic)),
                       int(bool(canonical)), int(trace_cap), int(record_cap),
                       int(debug_count_bias), int(queue_depth), int(bool(contract)),
-                      int(bool(graph_rounds)), 0)
+                      int(bool(graph_rounds)), int(levels))
 
 
 def nd_plan_create(row_ptr, col, r: int, s: int, orient: int = 0, load_factor: float = 0.0,
                    hbm_budget_bytes: int = 0, stream=None, timing: bool = False,
                    generic: bool = False, canonical: bool = False, trace_cap: int = 0,
                    record_cap: int = 0, debug_count_bias: int = 0, queue_depth: int = 0,
-                   graph_rounds: bool = False, contract: bool = False):
+                   graph_rounds: bool = False, contract: bool = False, levels: int = 0):
     """row_ptr (int64, n+1) and col (int32) are CUDA tensors; returns a plan handle."""
     import torch
     if row_ptr.dtype != torch.int64 or col.dtype != torch.int32:
@@ -200,7 +201,7 @@ def nd_plan_create(row_ptr, col, r: int, s: int, orient: int = 0, load_factor: f
     g = nd_csr(int(row_ptr.numel() - 1), int(col.numel()), row_ptr.data_ptr(),
                col.data_ptr() if col.numel() else None)
     opt = make_options(orient, timing, load_factor, generic, canonical, trace_cap, record_cap,
-                       debug_count_bias, queue_depth, graph_rounds, contract)
+                       debug_count_bias, queue_depth, graph_rounds, contract, levels)
     h = ctypes.c_void_p()
     _check(_lib.nd_plan_create(ctypes.byref(g), int(r), int(s), ctypes.byref(opt),
                                int(hbm_budget_bytes), _stream_handle(stream), ctypes.byref(h)))
@@ -479,14 +480,14 @@ def decompose(row_ptr, col, r: int, s: int, with_counts: bool = False, orient: i
               timing: bool = False, generic: bool = False, canonical: bool = False,
               trace_cap: int = 0, record_cap: int = 0, debug_count_bias: int = 0,
               queue_depth: int = 0, graph_rounds: bool = False, contract: bool = False,
-              requery: bool = True) -> Decomposition:
+              requery: bool = True, levels: int = 0) -> Decomposition:
     """Whole hot path on the current device: plan, workspace, run, round
     trace, destroy.  With requery a run whose round outgrew the workspace is
     repeated with the larger workspace the plan then reports."""
     import torch
     plan = nd_plan_create(row_ptr, col, r, s, orient, load_factor, hbm_budget_bytes, stream,
                           timing, generic, canonical, trace_cap, record_cap, debug_count_bias,
-                          queue_depth, graph_rounds, contract)
+                          queue_depth, graph_rounds, contract, levels)
     try:
         n_r, ws_bytes, _ = nd_plan_sizes(plan)
         dev = row_ptr.device

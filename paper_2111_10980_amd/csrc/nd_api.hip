@@ -85,7 +85,7 @@ int64_t grid_for(int64_t n, int threads, int64_t cap = 65536) {
   return b < cap ? b : cap;
 }
 
-__global__ void k_caps(int32_t n, int r, float lf, const uint32_t *__restrict__ cnt,
+__global__ void k_caps(int64_t n, int r, float lf, const uint32_t *__restrict__ cnt,
                        uint64_t *cap) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * blockDim.x) {
@@ -382,7 +382,9 @@ struct nd_plan_s {
   DevBuf<uint64_t> seg;
   DevBuf<Slot> slots;
   DevBuf<int32_t> v1;
-  DevBuf<uint64_t> khi;  // second key words, when (r-1) * bits > 63
+  DevBuf<uint64_t> khi;  // second key words, when the key fields need more than 63 bits
+  DevBuf<uint64_t> aseg;  // three levels: last-level table of each arc position
+  DevBuf<int32_t> v2s;    // three levels: second vertex of each slot
   DevBuf<uint32_t> occ;
   DevBuf<Counters> ctr;
   DevBuf<unsigned long long> stats;  // kStatLines x kStatStride statistic lines
@@ -395,6 +397,7 @@ struct nd_plan_s {
   uint64_t n_r = 0, n_slots = 0, held = 0;
   int bits = 1;
   bool wide = false;  // two-word r-clique keys
+  int levels = 2;     // r-clique table levels: 2, or 3 (r >= 4)
   int runs = 0;
   bool traced = false;
   uint64_t rec_need = 0;     // record capacity the next run's workspace provides at least
@@ -408,7 +411,15 @@ struct nd_plan_s {
   EventSet ev_peel;    // timing: 2 * kPeelMaxDepth around the update passes
   hipStream_t graph_stream = nullptr;  // graph_rounds: capture stream of queued rounds
   TableView table() const {
-    return TableView{bits, seg.get(), slots.get(), v1.get(), wide ? khi.get() : nullptr};
+    const bool three = levels == 3;
+    return TableView{bits,
+                     seg.get(),
+                     slots.get(),
+                     v1.get(),
+                     wide ? khi.get() : nullptr,
+                     three ? aseg.get() : nullptr,
+                     three ? v2s.get() : nullptr,
+                     g.view()};
   }
   ~nd_plan_s() {
     if (mirror) hipHostFree(mirror);
@@ -533,6 +544,10 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
     if (p->opt.contract != 0 && p->opt.contract != 1) fail(ND_EINVAL, "contract must be 0 or 1");
     if (p->opt.graph_rounds != 0 && p->opt.graph_rounds != 1)
       fail(ND_EINVAL, "graph_rounds must be 0 or 1");
+    if (p->opt.levels != 0 && p->opt.levels != 2 && p->opt.levels != 3)
+      fail(ND_EINVAL, "levels must be 0, 2 or 3");
+    if (p->opt.levels == 3 && r < 4) fail(ND_EINVAL, "three-level tables need r >= 4");
+    p->levels = p->opt.levels == 3 ? 3 : 2;
     p->fast = (s == r + 1) && r >= 2 && r <= 6 && p->opt.path == 0;
     p->path = p->fast ? 1 : (s >= r + 2 && p->opt.path == 0 ? 2 : 0);
     p->budget = hbm_budget_bytes;
@@ -562,11 +577,12 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
     tm.mark(1, st);
     int vb = bits_for(n > 1 ? (uint64_t)(n - 1) : 1);
     p->bits = vb < 1 ? 1 : vb;
-    // r-clique keys: (r-1) fields of `bits` in one word, or in two when they
+    // r-clique keys: the vertices after the levels' own (r-1 with two
+    // levels, r-2 with three), `bits` each, in one word, or in two when they
     // need more than 63 bits
-    if ((r - 1) * p->bits > 126)
-      fail(ND_EKEYWIDTH, "(r-1)*ceil(log2 n) = %d exceeds 126", (r - 1) * p->bits);
-    p->wide = (r - 1) * p->bits > 63;
+    const int key_bits = (r - (p->levels - 1)) * p->bits;
+    if (key_bits > 126) fail(ND_EKEYWIDTH, "r-clique key needs %d bits (limit 126)", key_bits);
+    p->wide = key_bits > 63;
     const uint64_t fixed_bytes = ws_buf<Counters>(1) + ws_buf<unsigned long long>(
                                      (uint64_t)kStatLines * kStatStride) +
                                  ws_buf<unsigned long long>(2) + ws_buf<RoundCtl>(1);
@@ -576,24 +592,38 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
     tm.mark(2, st);
     // r-clique table: count per first vertex, capacities, prefix sum.  For
     // (3,4)-type plans the triangles of bitmap roots are placed by rank
-    // (ordered within a root), so the bitmaps are built first.
+    // (ordered within a root), so the bitmaps are built first.  Three-level
+    // tables count per out-arc (v1, v2) instead and give each arc position
+    // its own last-level table.
     const bool ranked = p->fast && r == 3;
-    DevBuf<uint32_t> cnt(n > 0 ? (size_t)n : 1);
+    const bool three = p->levels == 3;
+    const int64_t n_units = three ? p->g.nnz : (int64_t)n;  // last-level tables
+    DevBuf<uint32_t> cnt(n_units + 1);
+    uint64_t *useg = nullptr;
     if (ranked)  // the index counts the triangles per root on the way
       build_fast_index(p->g, &p->fx, p->ctr.get(), st, cnt.get());
+    else if (three)
+      count_rcliques_arcs(p->g, r, cnt.get(), st);
     else
       count_rcliques(p->g, r, cnt.get(), st);
-    p->seg.reset((size_t)n + 1);
-    fill_u64(p->seg.get() + n, 0, 1, st);
+    if (three) {
+      p->seg.reset(1);  // the middle level is the CSR row itself
+      p->aseg.reset((size_t)n_units + 1);
+      useg = p->aseg.get();
+    } else {
+      p->seg.reset((size_t)n + 1);
+      useg = p->seg.get();
+    }
+    fill_u64(useg + n_units, 0, 1, st);
     if (ranked)
-      ranked_caps(p->g, &p->fx, cnt.get(), p->opt.load_factor, p->seg.get(), st);
-    else if (n > 0)
-      hipLaunchKernelGGL(k_caps, dim3((unsigned)grid_for(n, 256)), dim3(256), 0, st, n, r,
-                         p->opt.load_factor, cnt.get(), p->seg.get());
-    scan_exclusive_u64(p->seg.get(), p->seg.get(), (int64_t)n + 1, st);
+      ranked_caps(p->g, &p->fx, cnt.get(), p->opt.load_factor, useg, st);
+    else if (n_units > 0)
+      hipLaunchKernelGGL(k_caps, dim3((unsigned)grid_for(n_units, 256)), dim3(256), 0, st,
+                         n_units, r, p->opt.load_factor, cnt.get(), useg);
+    scan_exclusive_u64(useg, useg, n_units + 1, st);
     fill_u64((uint64_t *)&p->ctr.get()->n_s, 0, 1, st);
-    sum_u32(cnt.get(), n, (uint64_t *)&p->ctr.get()->n_s, st);
-    p->n_slots = read_dev(p->seg.get() + n, st);
+    sum_u32(cnt.get(), n_units, (uint64_t *)&p->ctr.get()->n_s, st);
+    p->n_slots = read_dev(useg + n_units, st);
     p->n_r = read_dev((uint64_t *)&p->ctr.get()->n_s, st);
     if (p->n_slots >= (1ull << 32) - 1)
       fail(ND_EOVERFLOW, "table needs %llu slots (limit 2^32-1)", (unsigned long long)p->n_slots);
@@ -616,7 +646,8 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
                         ? p->opt.trace_cap
                         : (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(p->n_r, 1u << 20));
     uint64_t table_bytes =
-        p->n_slots * (sizeof(Slot) + 4 + (p->wide ? 8 : 0)) + p->n_r * 4 * 5;
+        p->n_slots * (sizeof(Slot) + 4 + (p->wide ? 8 : 0) + (three ? 4 : 0)) +
+        p->n_r * 4 * 5 + (three ? ((uint64_t)n_units + 1) * 8 : 0);
     p->held = graph_bytes + table_bytes + (uint64_t)(n + 1) * 8 + fixed_bytes;
     // the budget covers the plan and the workspace of its run; checked before
     // the table is allocated
@@ -627,6 +658,7 @@ nd_status nd_plan_create(const nd_csr *gin, int r, int s, const nd_options *opt,
     p->slots.reset(p->n_slots ? p->n_slots : 1);
     p->v1.reset(p->n_slots ? p->n_slots : 1);
     if (p->wide) p->khi.reset(p->n_slots ? p->n_slots : 1);
+    if (three) p->v2s.reset(p->n_slots ? p->n_slots : 1);
     fill_slots(p->slots.get(), (int64_t)p->n_slots, st);
     fill_u32(&p->ctr.get()->err, 0, 1, st);
     if (ranked) {

@@ -227,7 +227,7 @@ struct CountOp {
     constexpr Combos<S, R> cb{};
     constexpr int N = cb.N;
     l.ns++;
-    int32_t v1[N];
+    int32_t v1[N], v2[N];
     Key key[N];
     bool want[N];
 #pragma unroll
@@ -236,12 +236,13 @@ struct CountOp {
 #pragma unroll
       for (int i = 0; i < R; i++) Rv[i] = Sv[cb.idx[q][i]];
       v1[q] = Rv[0];
-      key[q] = make_key<R>(Rv, T.bits);
+      v2[q] = R > 1 ? Sv[cb.idx[q][R > 1 ? 1 : 0]] : 0;
+      key[q] = rkey<R>(T, Rv);
       want[q] = true;
     }
     int64_t pos[N];
     Slot sl[N];
-    table_find_n<N>(T, v1, key, want, pos, sl);
+    table_find_n<N>(T, v1, v2, key, want, pos, sl);
 #pragma unroll
     for (int q = 0; q < N; q++) {
       if (pos[q] < 0) {
@@ -275,6 +276,23 @@ struct CountROp {
   __device__ void lane_finish(Lane &) const {}
 };
 
+// Number of r-cliques on each out-arc (v1, v2) of the oriented graph, by arc
+// position (three-level tables).
+template <int R>
+struct CountArcOp {
+  GraphView g;
+  uint32_t *cnt;
+  struct Lane {};
+  __device__ void lane_init(Lane &) const {}
+  __device__ void root_begin(Lane &, int32_t) const {}
+  __device__ void root_end(Lane &, int32_t) const {}
+  __device__ void operator()(Lane &, const int32_t (&Sv)[R]) const {
+    const int64_t e = arc_pos(g, Sv[0], Sv[1]);
+    if (e >= 0) atomicAdd(&cnt[e], 1u);
+  }
+  __device__ void lane_finish(Lane &) const {}
+};
+
 template <int R>
 struct InsertOp {
   TableView T;
@@ -286,7 +304,8 @@ struct InsertOp {
   __device__ void root_begin(Lane &, int32_t) const {}
   __device__ void root_end(Lane &, int32_t) const {}
   __device__ void operator()(Lane &l, const int32_t (&Sv)[R]) const {
-    if (table_insert(T, Sv[0], make_key<R>(Sv, T.bits)) < 0) l.err |= kErrTable;
+    if (table_insert(T, Sv[0], R > 1 ? Sv[R > 1 ? 1 : 0] : 0, rkey<R>(T, Sv)) < 0)
+      l.err |= kErrTable;
   }
   __device__ void lane_finish(Lane &l) const {
     if (l.err) atomicOr(&ctr->err, l.err);
@@ -409,6 +428,14 @@ void count_r_impl(const OrientedGraph &g, uint32_t *cnt, Counters *dctr, hipStre
 }
 
 template <int R>
+void count_arc_impl(const OrientedGraph &g, uint32_t *cnt, Counters *dctr, hipStream_t st) {
+  Bins b;
+  bin_roots(g, R - 1, dctr, &b, st);
+  fill_u32(cnt, 0, g.nnz + 1, st);
+  launch_listing<R>(g, b, CountArcOp<R>{g.view(), cnt}, st);
+}
+
+template <int R>
 void insert_r_impl(const OrientedGraph &g, const TableView &T, Counters *dctr, hipStream_t st) {
   Bins b;
   bin_roots(g, R - 1, dctr, &b, st);
@@ -441,6 +468,18 @@ void count_rcliques(const OrientedGraph &g, int r, uint32_t *cnt, hipStream_t st
     case 5: count_r_impl<5>(g, cnt, tmp.get(), st); break;
     case 6: count_r_impl<6>(g, cnt, tmp.get(), st); break;
     case 7: count_r_impl<7>(g, cnt, tmp.get(), st); break;
+    default: break;
+  }
+}
+
+void count_rcliques_arcs(const OrientedGraph &g, int r, uint32_t *cnt, hipStream_t st) {
+  if (g.n == 0) return;
+  DevBuf<Counters> tmp(1);
+  switch (r) {
+    case 4: count_arc_impl<4>(g, cnt, tmp.get(), st); break;
+    case 5: count_arc_impl<5>(g, cnt, tmp.get(), st); break;
+    case 6: count_arc_impl<6>(g, cnt, tmp.get(), st); break;
+    case 7: count_arc_impl<7>(g, cnt, tmp.get(), st); break;
     default: break;
   }
 }

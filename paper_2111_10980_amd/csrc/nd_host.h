@@ -124,6 +124,8 @@ void orient_relabel(int32_t n, int64_t nnz, const int64_t *rp, const int32_t *co
 // ---- cliques (nd_clique.hip)
 // count the r-cliques rooted at each vertex (lowest rank), into cnt[n]
 void count_rcliques(const OrientedGraph &g, int r, uint32_t *cnt, hipStream_t st);
+// r >= 4: r-cliques per out-arc (v1, v2), indexed by arc position (nnz + 1 entries)
+void count_rcliques_arcs(const OrientedGraph &g, int r, uint32_t *cnt, hipStream_t st);
 void insert_rcliques(const OrientedGraph &g, int r, const TableView &T, Counters *dctr,
                      hipStream_t st);
 // ev0/ev1 (nullable) are recorded around the listing kernels only

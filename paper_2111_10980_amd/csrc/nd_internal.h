@@ -45,13 +45,20 @@ struct TableView {
   Slot *__restrict__ slots;
   int32_t *__restrict__ v1;            // first vertex of each occupied slot
   uint64_t *__restrict__ khi;          // second key word per slot, or null (keys fit 63 bits)
+  // Three levels (aseg non-null; Section 4.1, l = 3): the middle level is
+  // v1's out-row of the oriented CSR, searched for v2; the arc at position e
+  // owns the last-level table [aseg[e], aseg[e+1]), keyed by v3..vr.
+  const uint64_t *__restrict__ aseg;   // per arc position (2m+1), or null: two levels
+  int32_t *__restrict__ v2;            // second vertex of each occupied slot (three levels)
+  GraphView arcs;                      // the oriented CSR (three levels)
 };
 
-// Key of a sorted r-tuple (v1 < ... < vR) within v1's segment: the fields
-// v2..vR, `bits` each, packed from bit 0 up into at most 126 bits.  Its low
-// 63 bits plus the occupied bit form the slot's key word; its high 63 bits
-// are the second word, zero unless (R-1) * bits exceeds 63 (then the table
-// keeps them in TableView::khi).
+// Key of a sorted r-tuple (v1 < ... < vR) within its last-level table: the
+// fields v2..vR (two levels) or v3..vR (three levels), `bits` each, packed
+// from bit 0 up into at most 126 bits.  Its low 63 bits plus the occupied bit
+// form the slot's key word; its high 63 bits are the second word, zero
+// unless the fields need more than 63 bits (then the table keeps them in
+// TableView::khi).
 struct Key {
   uint64_t lo, hi;
 };
@@ -125,8 +132,9 @@ __device__ __forceinline__ int64_t arc_pos(const GraphView &g, int32_t x, int32_
   return -1;
 }
 
+// first: index of the first key field (1: two levels, 2: three levels, R >= 4)
 template <int R>
-__device__ __forceinline__ Key make_key(const int32_t *v, int bits) {
+__device__ __forceinline__ Key make_key(const int32_t *v, int bits, int first = 1) {
   uint64_t lo = 0, hi = 0;
   if constexpr (R <= 3) {  // at most two fields of <= 31 bits: one word
 #pragma unroll
@@ -135,7 +143,8 @@ __device__ __forceinline__ Key make_key(const int32_t *v, int bits) {
   }
 #pragma unroll
   for (int i = 1; i < R; i++) {
-    const int o = bits * (i - 1);
+    if (i < first) continue;
+    const int o = bits * (i - first);
     const uint64_t f = (uint32_t)v[i];
     if (o < 63) {
       lo |= f << o;
@@ -145,6 +154,14 @@ __device__ __forceinline__ Key make_key(const int32_t *v, int bits) {
     }
   }
   return Key{(lo & (kOcc - 1)) | kOcc, hi};
+}
+
+__device__ __forceinline__ int key_first(const TableView &T) { return T.aseg ? 2 : 1; }
+
+// The key of a sorted r-tuple in table T.
+template <int R>
+__device__ __forceinline__ Key rkey(const TableView &T, const int32_t *v) {
+  return make_key<R>(v, T.bits, key_first(T));
 }
 
 // v2..vR of the r-clique in slot p (v[0] is the caller's).
@@ -160,9 +177,12 @@ __device__ __forceinline__ void decode_key(const TableView &T, uint64_t p, uint6
   }
   const uint64_t lo = key_lo & (kOcc - 1);
   const uint64_t hi = T.khi ? T.khi[p] : 0ull;
+  const int first = key_first(T);
+  if (first == 2) v[1] = T.v2[p];
 #pragma unroll
   for (int i = 1; i < R; i++) {
-    const int o = bits * (i - 1);
+    if (i < first) continue;
+    const int o = bits * (i - first);
     uint64_t f;
     if (o >= 63) {
       f = hi >> (o - 63);
@@ -185,12 +205,56 @@ __device__ __forceinline__ bool key_eq(const TableView &T, uint64_t i, uint64_t 
   return lo == key.lo && (!T.khi || T.khi[i] == key.hi);
 }
 
-// Linear probe of the last-level table of vertex v1.  Returns the slot
-// index, or -1 when absent; *out receives the slot's contents.
-__device__ __forceinline__ int64_t table_find(const TableView &T, int32_t v1, const Key &key,
-                                              Slot *out) {
-  uint64_t base = T.seg[v1];
-  uint64_t cap = T.seg[v1 + 1] - base;
+// The last-level table of an r-clique with first vertices v1 < v2:
+// [base, base + cap).  cap = 0 when there is none (no such r-clique).
+__device__ __forceinline__ void last_level(const TableView &T, int32_t v1, int32_t v2,
+                                           uint64_t &base, uint64_t &cap) {
+  if (!T.aseg) {
+    base = T.seg[v1];
+    cap = T.seg[v1 + 1] - base;
+    return;
+  }
+  const int64_t e = arc_pos(T.arcs, v1, v2);
+  base = e >= 0 ? T.aseg[e] : 0;
+  cap = e >= 0 ? T.aseg[e + 1] - base : 0;
+}
+
+// Positions of N arcs (a[q] < b[q]) in the rows of a[q], searched in
+// lock-step so their loads overlap; -1 when absent or not wanted.
+template <int N>
+__device__ __forceinline__ void arc_pos_n(const GraphView &g, const int32_t (&a)[N],
+                                          const int32_t (&b)[N], const bool (&want)[N],
+                                          int64_t (&e)[N]) {
+  int64_t base[N], len[N];
+#pragma unroll
+  for (int q = 0; q < N; q++) {
+    base[q] = want[q] ? g.up[a[q]] : 0;
+    len[q] = want[q] ? g.rp[a[q] + 1] - base[q] : 0;
+  }
+  // invariant: b[q], when present, lies in [base, base + len)
+  bool more = true;
+  while (more) {
+    more = false;
+#pragma unroll
+    for (int q = 0; q < N; q++) {
+      if (len[q] > 1) {
+        const int64_t half = len[q] >> 1;
+        if (g.col[base[q] + half] <= b[q]) base[q] += half;
+        len[q] -= half;
+        more = more || len[q] > 1;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < N; q++) e[q] = len[q] == 1 && g.col[base[q]] == b[q] ? base[q] : -1;
+}
+
+// Linear probe of the last-level table of the r-clique starting v1 < v2.
+// Returns the slot index, or -1 when absent; *out receives the slot.
+__device__ __forceinline__ int64_t table_find(const TableView &T, int32_t v1, int32_t v2,
+                                              const Key &key, Slot *out) {
+  uint64_t base, cap;
+  last_level(T, v1, v2, base, cap);
   if (cap == 0) return -1;
   uint64_t i = home_slot(key, cap);
   for (uint64_t probe = 0; probe < cap; probe++) {
@@ -209,9 +273,10 @@ __device__ __forceinline__ int64_t table_find(const TableView &T, int32_t v1, co
 // claiming an empty slot is enough.  With two-word keys a slot whose first
 // word equals this key's holds another r-clique (or one whose second word is
 // still being written): probing goes on.
-__device__ __forceinline__ int64_t table_insert(const TableView &T, int32_t v1, const Key &key) {
-  uint64_t base = T.seg[v1];
-  uint64_t cap = T.seg[v1 + 1] - base;
+__device__ __forceinline__ int64_t table_insert(const TableView &T, int32_t v1, int32_t v2,
+                                               const Key &key) {
+  uint64_t base, cap;
+  last_level(T, v1, v2, base, cap);
   if (cap == 0) return -1;
   uint64_t i = home_slot(key, cap);
   for (uint64_t probe = 0; probe < cap; probe++) {
@@ -219,6 +284,7 @@ __device__ __forceinline__ int64_t table_insert(const TableView &T, int32_t v1, 
     unsigned long long prev = atomicCAS(kp, 0ull, (unsigned long long)key.lo);
     if (prev == 0ull || (prev == key.lo && !T.khi)) {
       if (T.khi) T.khi[base + i] = key.hi;
+      if (T.v2) T.v2[base + i] = v2;
       T.v1[base + i] = v1;
       return (int64_t)(base + i);
     }
@@ -257,9 +323,12 @@ __device__ __forceinline__ void lower_bounds(const int32_t *__restrict__ a, int6
 // lookup q (pos[q] = -1).
 template <int N>
 __device__ __forceinline__ void table_find_n(const TableView &T, const int32_t (&v1)[N],
-                                             const Key (&key)[N], const bool (&want)[N],
-                                             int64_t (&pos)[N], Slot (&out)[N]) {
+                                             const int32_t (&v2)[N], const Key (&key)[N],
+                                             const bool (&want)[N], int64_t (&pos)[N],
+                                             Slot (&out)[N]) {
   uint64_t base[N], cap[N], i[N];
+  int64_t e[N];
+  if (T.aseg) arc_pos_n<N>(T.arcs, v1, v2, want, e);
 #pragma unroll
   for (int q = 0; q < N; q++) {
     pos[q] = -1;
@@ -267,8 +336,13 @@ __device__ __forceinline__ void table_find_n(const TableView &T, const int32_t (
     cap[q] = 0;
     i[q] = 0;
     if (want[q]) {
-      base[q] = T.seg[v1[q]];
-      cap[q] = T.seg[v1[q] + 1] - base[q];
+      if (T.aseg) {
+        base[q] = e[q] >= 0 ? T.aseg[e[q]] : 0;
+        cap[q] = e[q] >= 0 ? T.aseg[e[q] + 1] - base[q] : 0;
+      } else {
+        base[q] = T.seg[v1[q]];
+        cap[q] = T.seg[v1[q] + 1] - base[q];
+      }
       if (cap[q]) i[q] = home_slot(key[q], cap[q]);
     }
   }

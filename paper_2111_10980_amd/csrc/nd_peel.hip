@@ -194,7 +194,7 @@ __device__ __forceinline__ void update_func(const PeelArgs &a, const int32_t (&S
                                             LaneStats &ls, Appender *ap) {
   constexpr Combos<S, R> cb{};
   constexpr int N = cb.N;
-  int32_t v1[N];
+  int32_t v1[N], v2[N];
   Key key[N];
   bool want[N];
 #pragma unroll
@@ -203,7 +203,8 @@ __device__ __forceinline__ void update_func(const PeelArgs &a, const int32_t (&S
 #pragma unroll
     for (int i = 0; i < R; i++) Rv[i] = Sv[cb.idx[q][i]];
     v1[q] = Rv[0];
-    key[q] = make_key<R>(Rv, a.T.bits);
+    v2[q] = R > 1 ? Sv[cb.idx[q][R > 1 ? 1 : 0]] : 0;
+    key[q] = rkey<R>(a.T, Rv);
     want[q] = active && cb.mask[q] != rmask;
   }
   // The other subsets are looked up two at a time, and the lookups stop at
@@ -216,7 +217,7 @@ __device__ __forceinline__ void update_func(const PeelArgs &a, const int32_t (&S
   bool alive = active;
 #pragma unroll
   for (int g0 = 0; g0 < N; g0 += 2) {
-    int32_t gv[2];
+    int32_t gv[2], gv2[2];
     Key gk[2];
     bool gw[2];
     int64_t gp[2];
@@ -225,10 +226,11 @@ __device__ __forceinline__ void update_func(const PeelArgs &a, const int32_t (&S
     for (int j = 0; j < 2; j++) {
       const int q = g0 + j < N ? g0 + j : N - 1;
       gv[j] = v1[q];
+      gv2[j] = v2[q];
       gk[j] = key[q];
       gw[j] = g0 + j < N && want[q] && alive;
     }
-    table_find_n<2>(a.T, gv, gk, gw, gp, gs);
+    table_find_n<2>(a.T, gv, gv2, gk, gw, gp, gs);
 #pragma unroll
     for (int j = 0; j < 2; j++) {
       if (g0 + j >= N) continue;
@@ -696,7 +698,7 @@ __device__ __forceinline__ int64_t tri_slot(const PeelArgs &a, const FastView &f
   if (rr.d > 512) {
     const int32_t Tv[3] = {x0, x1, x2};
     Slot tmp;
-    return table_find(a.T, x0, make_key<3>(Tv, a.T.bits), &tmp);
+    return table_find(a.T, x0, x1, make_key<3>(Tv, a.T.bits), &tmp);
   }
   if (l1 < 0 && l2 < 0) {
     const int32_t ys[2] = {x1, x2};
@@ -1217,10 +1219,11 @@ __device__ __forceinline__ void apply_body(const PeelArgs &base, const RoundCtl 
   if (ls.err) atomicOr(&a.ctr->err, ls.err);
 }
 
-// r = 4: at least 4 waves per SIMD (128 registers, a few spilled; without
-// the bound the compiler takes 133 and 3 waves, ~60 ms slower per Chung-Lu
-// 1M (4,5) decomposition).  r = 5, 6 keep the default (the bound spills
-// their larger subset arrays).
+// r = 4: at least 4 waves per SIMD.  (Before the paired early-exit lookups
+// the compiler took 133 registers and 3 waves without the bound, ~60 ms
+// slower per Chung-Lu 1M (4,5) decomposition; the pass now fits 92 registers
+// and 5 waves.)  r = 5, 6 keep the default (the bound spilled their larger
+// subset arrays).
 template <int R>
 __global__ __launch_bounds__(256, R == 4 ? 4 : 1) void k_apply(PeelArgs base, const RoundCtl *__restrict__ rc,
                                                const int2 *__restrict__ rec,

@@ -350,6 +350,40 @@ def test_two_word_keys(n, r, s, kw):
     assert d.stats["n_s"] > 0
 
 
+@pytest.mark.parametrize("r,s,kw", [
+    (4, 5, {}), (4, 6, {}), (5, 6, {}), (5, 7, {}), (6, 7, {}), (4, 7, {}), (7, 8, {}),
+    (4, 5, {"generic": True}), (5, 6, {"generic": True}), (4, 5, {"load_factor": 0.9}),
+])
+def test_three_level_table(r, s, kw):
+    """Three-level r-clique tables (Section 4.1, l = 3): the out-arc (v1, v2)
+    selects the last-level table; results identical to the oracle's."""
+    g = inputs.sparse_with_dense_block(400, 3.0, 120, 0.35, 10, 8, 13, 77)
+    d = check_against_oracle(g, r, s, levels=3, **kw)
+    assert d.stats["n_s"] > 0
+
+
+@pytest.mark.parametrize("n,r,s,words", [
+    ((1 << 21) + 4096, 4, 5, 1),  # v3, v4: 44 bits (66 with two levels)
+    ((1 << 21) + 4096, 4, 6, 1),
+    ((1 << 21) + 4096, 5, 7, 2),  # v3..v5: 66 bits
+    ((1 << 21) + 4096, 6, 7, 2),  # v3..v6: 88 bits
+])
+def test_three_level_key_width(n, r, s, words):
+    """With three levels a key carries r-2 vertices, so n > 2^21 keeps (4,*)
+    keys in one word."""
+    d = check_against_oracle(_wide_graph(n), r, s, levels=3)
+    assert d.stats["key_words"] == words
+
+
+def test_three_level_rejected_below_r4():
+    nd = _nd()
+    rp, col = nd.to_device(inputs.planted_er(60, 5.0, 2, 5, 8, 3))
+    for r, s, lv in [(3, 4, 3), (2, 4, 3), (4, 5, 1), (4, 5, 4)]:
+        with pytest.raises(nd.NdError) as e:
+            nd.decompose(rp, col, r, s, levels=lv)
+        assert e.value.name == "ND_EINVAL"
+
+
 def test_budget_rejected():
     """A budget below what the plan and its run's workspace need fails at plan
     creation, once n_r is known and before the table is allocated."""
