@@ -651,6 +651,13 @@ __device__ __forceinline__ void peel_candidate(const PeelArgs &a, const int32_t 
 // row-major order, i and j the local indices of b and c in N+(a).  Roots
 // without a bitmap are hashed.
 
+// r = 3 record word (rloc): the local index of x in N+(v1) (bitmap part), or
+// 0xFFFF; with an index, bits 14 and 15 flag {v1, v2, x} and {v1, v3, x} as
+// frontier triangles (alive is implied: the expand pass listed x from the
+// alive rows).
+constexpr int kRlocFront2 = 14, kRlocFront3 = 15;
+constexpr uint32_t kRlocIndex = 0x3FFFu;
+
 struct RootRow {
   int64_t o;      // up[a]
   int d;          // |N+(a)|
@@ -722,8 +729,14 @@ __device__ __forceinline__ int64_t tri_slot(const PeelArgs &a, const FastView &f
 // decisions as update_func, with the three other triangles located by rank
 // (local indices of v2, v3 in N+(v1) come from R's loc word).  Called by every
 // lane of the wave together.
-// lxh: local index of x in N+(v1) when the expand pass had it (else 0xFFFF);
-// l23: local index of v3 in N+(v2) (else 0xFFFFFFFF).
+// lxh: the record word (local index of x in N+(v1) and frontier flags when
+// the expand pass had them, else 0xFFFF); l23: local index of v3 in N+(v2)
+// (else 0xFFFFFFFF).
+// The expand pass already decided the two triangles through v1 and x
+// (omitting v2 or v3) whenever x came from v1's alive rows (x > v1, flags in
+// lxh) or from the apex lists (x < v1: both alive and outside the frontier):
+// their slots are not read, and a live one takes its decrement without the
+// count check.  Only the triangle omitting v1 is read.
 __device__ __forceinline__ void update_r3_ranked(const PeelArgs &a, const FastView &fx,
                                                  const int32_t (&Rv)[3], int32_t x, uint64_t lc,
                                                  uint32_t lxh, uint32_t l23, bool active,
@@ -756,7 +769,7 @@ __device__ __forceinline__ void update_r3_ranked(const PeelArgs &a, const FastVi
       l3 = (int64_t)((lc >> 9) & 511u);
       if (x > v1) {
         if (lxh != 0xFFFFu) {
-          lx = (int64_t)lxh;
+          lx = (int64_t)(lxh & kRlocIndex);
         } else {
           lx = lower_pos(a.g.col, r1.o, r1.o + r1.d, x) - r1.o;
           if (lx >= r1.d || a.g.col[r1.o + lx] != x) lx = -1;  // tri_slot searches again
@@ -786,6 +799,20 @@ __device__ __forceinline__ void update_r3_ranked(const PeelArgs &a, const FastVi
       pos[q] = tri_slot(a, fx, rr, t0, t1, t2, h1, h2);
     }
   }
+  // known[q]: 0 read the slot, 1 live, 2 in the frontier after R
+  int known[4];
+  const bool apex = x < v1;
+  const bool flagged = !apex && lxh != 0xFFFFu;
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    known[q] = 0;
+    const uint32_t omit = rmask & ~(uint32_t)cb.mask[q];  // R's vertex missing from q
+    const bool omits_v2 = omit != 0 && Sv[__builtin_ctz(omit)] == Rv[1];
+    const bool omits_v3 = omit != 0 && Sv[__builtin_ctz(omit)] == Rv[2];
+    if (apex && (omits_v2 || omits_v3)) known[q] = 1;
+    if (flagged && omits_v3) known[q] = (lxh >> kRlocFront2) & 1u ? 2 : 1;  // {v1, v2, x}
+    if (flagged && omits_v2) known[q] = (lxh >> kRlocFront3) & 1u ? 2 : 1;  // {v1, v3, x}
+  }
   Slot sl[4];
   bool alive = active, other_owner = false, hot[4];  // as in update_func
   uint32_t n_live = 0;
@@ -798,6 +825,12 @@ __device__ __forceinline__ void update_r3_ranked(const PeelArgs &a, const FastVi
       alive = false;
       continue;
     }
+    if (known[q] == 1) {
+      n_live++;
+      hot[q] = true;
+      continue;
+    }
+    if (known[q] == 2) continue;
     sl[q] = a.T.slots[pos[q]];
     const int32_t Tv[3] = {Sv[cb.idx[q][0]], Sv[cb.idx[q][1]], Sv[cb.idx[q][2]]};
     if (sl[q].key != make_key<3>(Tv, a.T.bits).lo) {  // the rank must land on the triangle
@@ -1048,6 +1081,7 @@ __global__ __launch_bounds__(256, 8) void k_expand(PeelArgs base, RoundCtl *rc, 
     const bool has_bm = d <= 512;
     uint32_t total1, iw[8];
     uint64_t cw = 0;
+    uint64_t fw2 = 0, fw3 = 0;  // r = 3: frontier marks of rows v2, v3 (this lane's word)
     if (has_bm) {
       const int wd = (d + 63) >> 6;
       const uint64_t *rows = (R == 3 || (R == 2 && fx.alive) ? fx.alive : fx.bm) + ds.bmo;
@@ -1055,8 +1089,13 @@ __global__ __launch_bounds__(256, 8) void k_expand(PeelArgs base, RoundCtl *rc, 
         cw = ~0ull;
 #pragma unroll
         for (int i = 1; i < R; i++) cw &= rows[(e[i] - o) * wd + lane];
-        if constexpr (R == 3)
-          cw &= ~owned_elsewhere(fx.front + ds.bmo, e[1] - o, e[2] - o, wd, lane);
+        if constexpr (R == 3) {
+          const int64_t l2 = e[1] - o, l3 = e[2] - o;
+          fw2 = fx.front[ds.bmo + l2 * wd + lane];
+          fw3 = fx.front[ds.bmo + l3 * wd + lane];
+          // a frontier triangle {v1, v2, x} or {v1, v3, x} before R owns R + x
+          cw &= ~((fw2 & below_mask(l3, lane)) | (fw3 & below_mask(l2, lane)));
+        }
       }
       const uint32_t incl = wave_incl_scan((uint32_t)__popcll(cw));
       total1 = __shfl(incl, kWave - 1);
@@ -1097,11 +1136,23 @@ __global__ __launch_bounds__(256, 8) void k_expand(PeelArgs base, RoundCtl *rc, 
         }
       }
       const uint64_t wordw = __shfl(cw, w);
+      uint64_t fr2 = 0, fr3 = 0;
+      if constexpr (R == 3) {
+        fr2 = __shfl(fw2, w);
+        fr3 = __shfl(fw3, w);
+      }
       uint32_t lxw = 0xFFFFu;  // local index of x in N+(v1), bitmap part only
       if (in && k < total1) {
         if (has_bm) {
-          lxw = (uint32_t)w * 64u + select_bit(wordw, kk - before);
+          const uint32_t bit = select_bit(wordw, kk - before);
+          lxw = (uint32_t)w * 64u + bit;
           x = a.g.col[o + lxw];
+          // r = 3: {v1, v2, x} and {v1, v3, x} are alive (the alive rows); a
+          // frontier one comes after R and owns nothing: its flag tells the
+          // update pass, which then needs neither triangle's slot
+          if constexpr (R == 3)
+            lxw |= (uint32_t)((fr2 >> bit) & 1u) << kRlocFront2 |
+                   (uint32_t)((fr3 >> bit) & 1u) << kRlocFront3;
         } else {
           x = a.g.col[o + (int64_t)k];
           if constexpr (R != 2) {
