@@ -242,7 +242,7 @@ struct CountOp {
     }
     int64_t pos[N];
     Slot sl[N];
-    table_find_n<N>(T, v1, v2, key, want, pos, sl);
+    table_find_n<N, (R >= 4)>(T, v1, v2, key, want, pos, sl);
 #pragma unroll
     for (int q = 0; q < N; q++) {
       if (pos[q] < 0) {
@@ -304,7 +304,7 @@ struct InsertOp {
   __device__ void root_begin(Lane &, int32_t) const {}
   __device__ void root_end(Lane &, int32_t) const {}
   __device__ void operator()(Lane &l, const int32_t (&Sv)[R]) const {
-    if (table_insert(T, Sv[0], R > 1 ? Sv[R > 1 ? 1 : 0] : 0, rkey<R>(T, Sv)) < 0)
+    if (table_insert<(R >= 4)>(T, Sv[0], R > 1 ? Sv[R > 1 ? 1 : 0] : 0, rkey<R>(T, Sv)) < 0)
       l.err |= kErrTable;
   }
   __device__ void lane_finish(Lane &l) const {

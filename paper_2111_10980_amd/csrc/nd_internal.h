@@ -161,7 +161,7 @@ __device__ __forceinline__ int key_first(const TableView &T) { return T.aseg ? 2
 // The key of a sorted r-tuple in table T.
 template <int R>
 __device__ __forceinline__ Key rkey(const TableView &T, const int32_t *v) {
-  return make_key<R>(v, T.bits, key_first(T));
+  return make_key<R>(v, T.bits, R >= 4 ? key_first(T) : 1);
 }
 
 // v2..vR of the r-clique in slot p (v[0] is the caller's).
@@ -199,7 +199,11 @@ __device__ __forceinline__ uint64_t home_slot(const Key &key, uint64_t cap) {
   return ((mix64(key.lo ^ (key.hi * 0x9E3779B97F4A7C15ull)) >> 32) * cap) >> 32;
 }
 
-// Does slot i (whose key word is `lo`) hold `key`?
+// Does slot i (whose key word is `lo`) hold `key`?  The second word is
+// tested at run time for every r: compiled out for r < 4, the listing
+// kernels of the count phase took 16 more registers per lane (the probe
+// loops were laid out differently) and spilled at 8 bitmap words.
+template <bool kR4>
 __device__ __forceinline__ bool key_eq(const TableView &T, uint64_t i, uint64_t lo,
                                        const Key &key) {
   return lo == key.lo && (!T.khi || T.khi[i] == key.hi);
@@ -207,9 +211,12 @@ __device__ __forceinline__ bool key_eq(const TableView &T, uint64_t i, uint64_t 
 
 // The last-level table of an r-clique with first vertices v1 < v2:
 // [base, base + cap).  cap = 0 when there is none (no such r-clique).
+// kR4 = false: the caller's r is below 4, so its table has two levels and
+// one-word keys, and the code for the others is compiled out.
+template <bool kR4>
 __device__ __forceinline__ void last_level(const TableView &T, int32_t v1, int32_t v2,
                                            uint64_t &base, uint64_t &cap) {
-  if (!T.aseg) {
+  if (!kR4 || !T.aseg) {
     base = T.seg[v1];
     cap = T.seg[v1 + 1] - base;
     return;
@@ -251,15 +258,16 @@ __device__ __forceinline__ void arc_pos_n(const GraphView &g, const int32_t (&a)
 
 // Linear probe of the last-level table of the r-clique starting v1 < v2.
 // Returns the slot index, or -1 when absent; *out receives the slot.
+template <bool kR4>
 __device__ __forceinline__ int64_t table_find(const TableView &T, int32_t v1, int32_t v2,
                                               const Key &key, Slot *out) {
   uint64_t base, cap;
-  last_level(T, v1, v2, base, cap);
+  last_level<kR4>(T, v1, v2, base, cap);
   if (cap == 0) return -1;
   uint64_t i = home_slot(key, cap);
   for (uint64_t probe = 0; probe < cap; probe++) {
     Slot s = T.slots[base + i];
-    if (key_eq(T, base + i, s.key, key)) {
+    if (key_eq<kR4>(T, base + i, s.key, key)) {
       *out = s;
       return (int64_t)(base + i);
     }
@@ -273,18 +281,20 @@ __device__ __forceinline__ int64_t table_find(const TableView &T, int32_t v1, in
 // claiming an empty slot is enough.  With two-word keys a slot whose first
 // word equals this key's holds another r-clique (or one whose second word is
 // still being written): probing goes on.
+template <bool kR4>
 __device__ __forceinline__ int64_t table_insert(const TableView &T, int32_t v1, int32_t v2,
                                                const Key &key) {
   uint64_t base, cap;
-  last_level(T, v1, v2, base, cap);
+  last_level<kR4>(T, v1, v2, base, cap);
   if (cap == 0) return -1;
   uint64_t i = home_slot(key, cap);
   for (uint64_t probe = 0; probe < cap; probe++) {
     unsigned long long *kp = (unsigned long long *)&T.slots[base + i].key;
     unsigned long long prev = atomicCAS(kp, 0ull, (unsigned long long)key.lo);
-    if (prev == 0ull || (prev == key.lo && !T.khi)) {
-      if (T.khi) T.khi[base + i] = key.hi;
-      if (T.v2) T.v2[base + i] = v2;
+    const bool wide = kR4 && T.khi;
+    if (prev == 0ull || (prev == key.lo && !wide)) {
+      if (wide) T.khi[base + i] = key.hi;
+      if (kR4 && T.v2) T.v2[base + i] = v2;
       T.v1[base + i] = v1;
       return (int64_t)(base + i);
     }
@@ -321,14 +331,15 @@ __device__ __forceinline__ void lower_bounds(const int32_t *__restrict__ a, int6
 // N independent table lookups issued together: the home slots of all keys
 // are loaded before any collision chain is followed.  want[q] = false skips
 // lookup q (pos[q] = -1).
-template <int N>
+template <int N, bool kR4>
 __device__ __forceinline__ void table_find_n(const TableView &T, const int32_t (&v1)[N],
                                              const int32_t (&v2)[N], const Key (&key)[N],
                                              const bool (&want)[N], int64_t (&pos)[N],
                                              Slot (&out)[N]) {
   uint64_t base[N], cap[N], i[N];
   int64_t e[N];
-  if (T.aseg) arc_pos_n<N>(T.arcs, v1, v2, want, e);
+  const bool arcs = kR4 && T.aseg;
+  if (arcs) arc_pos_n<N>(T.arcs, v1, v2, want, e);
 #pragma unroll
   for (int q = 0; q < N; q++) {
     pos[q] = -1;
@@ -336,7 +347,7 @@ __device__ __forceinline__ void table_find_n(const TableView &T, const int32_t (
     cap[q] = 0;
     i[q] = 0;
     if (want[q]) {
-      if (T.aseg) {
+      if (arcs) {
         base[q] = e[q] >= 0 ? T.aseg[e[q]] : 0;
         cap[q] = e[q] >= 0 ? T.aseg[e[q] + 1] - base[q] : 0;
       } else {
@@ -353,7 +364,7 @@ __device__ __forceinline__ void table_find_n(const TableView &T, const int32_t (
   for (int q = 0; q < N; q++) {
     if (!want[q] || !cap[q]) continue;
     for (uint64_t probe = 0; probe < cap[q]; probe++) {
-      if (key_eq(T, base[q] + i[q], out[q].key, key[q])) {
+      if (key_eq<kR4>(T, base[q] + i[q], out[q].key, key[q])) {
         pos[q] = (int64_t)(base[q] + i[q]);
         break;
       }
@@ -521,6 +532,7 @@ struct RoundCtl {
   uint32_t contract_due;    // set when peeled_since reaches contract_every
   uint32_t contractions;    // contraction passes done
   uint32_t t, k, kw, nF;   // round, level, window top, |A_t|
+  uint32_t nA;             // |A_t| of the round under way (set by begin, kept by end)
   uint32_t nW, nH;         // window list and high list sizes
   uint32_t selF, selW, selH;
   uint32_t done;           // every r-clique peeled

@@ -123,6 +123,7 @@ __device__ void round_begin_body(RoundCtl *rc, Counters *dc) {
   rc->total = 0;
   rc->total2 = 0;
   rc->total3 = 0;
+  rc->nA = rc->nF;
   dc->next_size = 0;
   dc->low_size = rc->nW;  // window appends continue after the live entries
 }
@@ -230,7 +231,7 @@ __device__ __forceinline__ void update_func(const PeelArgs &a, const int32_t (&S
       gk[j] = key[q];
       gw[j] = g0 + j < N && want[q] && alive;
     }
-    table_find_n<2>(a.T, gv, gv2, gk, gw, gp, gs);
+    table_find_n<2, (R >= 4)>(a.T, gv, gv2, gk, gw, gp, gs);
 #pragma unroll
     for (int j = 0; j < 2; j++) {
       if (g0 + j >= N) continue;
@@ -705,7 +706,7 @@ __device__ __forceinline__ int64_t tri_slot(const PeelArgs &a, const FastView &f
   if (rr.d > 512) {
     const int32_t Tv[3] = {x0, x1, x2};
     Slot tmp;
-    return table_find(a.T, x0, x1, make_key<3>(Tv, a.T.bits), &tmp);
+    return table_find<false>(a.T, x0, x1, make_key<3>(Tv, a.T.bits), &tmp);
   }
   if (l1 < 0 && l2 < 0) {
     const int32_t ys[2] = {x1, x2};
@@ -1600,6 +1601,29 @@ __global__ void k_round_end(RoundCtl *rc, const Counters *dc) {
   round_end_body(rc, dc);
 }
 
+// r = 2, end of a round: the bookkeeping of k_round_end (one thread) and,
+// over the grid, the frontier's edges becoming dead for the candidate tests
+// of later rounds (both arc directions), counted as lost neighbours of both
+// endpoints when graph contraction is on (lost non-null).  The retirement
+// reads the round's |A_t| from nA, which the bookkeeping leaves alone.
+__global__ __launch_bounds__(256) void k_round_end_r2(RoundCtl *rc, const Counters *dc,
+                                                      GraphView g,
+                                                      const int32_t *__restrict__ fv,
+                                                      uint8_t *arcst, uint32_t *lost) {
+  if (rc_idle(rc)) return;
+  const uint32_t nA = rc->nA;
+  if (blockIdx.x == 0 && threadIdx.x == 0) round_end_body(rc, dc);
+  for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nA;
+       f += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t a = fv[f * 2], b = fv[f * 2 + 1];
+    set_edge_state(g, a, b, arcst, kArcDead);
+    if (lost) {
+      atomicAdd(&lost[a], 1u);
+      atomicAdd(&lost[b], 1u);
+    }
+  }
+}
+
 __global__ void k_occ_flags(const Slot *__restrict__ slots, uint64_t n, uint32_t *flags) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -1660,7 +1684,8 @@ __global__ void k_emit(const uint32_t *__restrict__ occ, uint64_t n_r, TableView
 // x along the out-arcs of x, so each s-clique of R is met exactly once.
 //   bound:  thread per peeled R: stamp it, pick the driver, allocate one
 //           flag per position of the driver's row;
-//   member: wave per peeled R: flag the positions in I(R), list the
+//   spread: wave per peeled R: its index over its candidate range;
+//   member: thread per candidate: flag the positions in I(R), list the
 //           members that have out-arcs;
 //   apply:  the out-arcs (x, y) of 64 members spread over a wave: y in I(R)
 //           closes R + {x, y} (s = r + 2) or starts a deeper extension.
@@ -1707,7 +1732,10 @@ __global__ __launch_bounds__(256) void k_gen_bound(PeelArgs base, RoundCtl *rc, 
 }
 
 // One wave per peeled r-clique writes its index over its candidate range, so
-// the member pass can be flattened over all candidates of the round.
+// the member pass can be flattened over all candidates of the round.  (Done
+// by the bound pass's own blocks instead, the writes of a round with a few
+// hundred r-cliques fell to four waves: the Chung-Lu 1M (2,4) peel took 15%
+// longer.)
 __global__ __launch_bounds__(256) void k_gen_spread(RoundCtl *rc, const uint64_t *__restrict__ ioff,
                                                     const uint32_t *__restrict__ ilen,
                                                     uint32_t *owner) {
@@ -1960,34 +1988,6 @@ __global__ __launch_bounds__(256) void k_gen_apply(PeelArgs base, RoundCtl *rc,
   if (ls.err) atomicOr(&a.ctr->err, ls.err);
 }
 
-// r = 2, end of the round's update: the frontier's edges become dead for
-// the candidate tests of later rounds (both arc directions).
-__global__ __launch_bounds__(256) void k_gen_retire2(GraphView g, const RoundCtl *rc,
-                                                     const int32_t *__restrict__ fv,
-                                                     uint8_t *arcst) {
-  if (rc_idle(rc)) return;
-  const uint32_t nF = rc->nF;
-  for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nF;
-       f += (int64_t)gridDim.x * blockDim.x)
-    set_edge_state(g, fv[f * 2], fv[f * 2 + 1], arcst, kArcDead);
-}
-
-// r = 2 on the s = r+1 path, end of the round's update: the frontier's edges
-// become dead (both arc directions) and count as lost neighbours of both
-// endpoints for graph contraction.
-__global__ __launch_bounds__(256) void k_retire2(GraphView g, const RoundCtl *rc,
-                                                 const int32_t *__restrict__ fv, FastView fx) {
-  if (rc_idle(rc)) return;
-  const uint32_t nF = rc->nF;
-  for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nF;
-       f += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t a = fv[f * 2], b = fv[f * 2 + 1];
-    set_edge_state(g, a, b, fx.arcst, kArcDead);
-    atomicAdd(&fx.lost[a], 1u);
-    atomicAdd(&fx.lost[b], 1u);
-  }
-}
-
 // Graph contraction for (2,3) (Section 4.6): once the peeled edges since the
 // last contraction reach the threshold (twice the vertex count), every
 // vertex v that lost at least a quarter of its neighbours since its last
@@ -2089,6 +2089,7 @@ struct Engine {
   DevBuf<uint64_t> mbeg;   // s >= r+2: first out-arc of each member
   DevBuf<uint32_t> aown;   // s >= r+2: member of each out-arc
   DevBuf<uint8_t> dead;    // s >= r+2, r = 2: per arc position, alive / frontier / dead
+  bool track_lost = false; // (2,3) with graph contraction: count lost neighbours
   uint64_t cap3 = 0;
   DevBuf<uint32_t> tsize, tk;
   uint64_t cap = 0;
@@ -2119,9 +2120,6 @@ void launch_fast(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, dim3 ga, hip
     hipLaunchKernelGGL(k_apply<R>, ga, dim3(256), 0, E.st, base, E.rc, E.rec.get(),
                        E.fv.get(), E.fxv, E.loc, E.rloc.get(), E.f23.get());
   if (e1) hipEventRecord(e1, E.st);
-  if constexpr (R == 2)
-    if (E.fxv.arcst)
-      hipLaunchKernelGGL(k_retire2, gf, dim3(256), 0, E.st, E.gv, E.rc, E.fv.get(), E.fxv);
 }
 
 template <int R, int S>
@@ -2139,9 +2137,6 @@ void launch_gen(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, dim3 gc, dim3
                      E.fv.get(), E.drv.get(), E.flag.get(), E.rec.get(), E.mbeg.get(),
                      E.aown.get(), E.dead.get());
   if (e1) hipEventRecord(e1, E.st);
-  if constexpr (R == 2)
-    hipLaunchKernelGGL(k_gen_retire2, gf, dim3(256), 0, E.st, E.gv, E.rc, E.fv.get(),
-                       E.dead.get());
 }
 
 #define ND_WALK(R_, S_) \
@@ -2248,7 +2243,13 @@ void launch_round(Engine &E, const RoundGrids &G, hipEvent_t e0, hipEvent_t e1,
       default: break;
     }
   }
-  hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, st, rc, E.dc);
+  // r = 2 keeps per-arc edge states: the round's end also retires its edges
+  uint8_t *arcst = E.r != 2 ? nullptr : (E.path == 2 ? E.dead.get() : E.fxv.arcst);
+  if (arcst)
+    hipLaunchKernelGGL(k_round_end_r2, gf, dim3(256), 0, st, rc, E.dc, E.gv, E.fv.get(), arcst,
+                       E.track_lost ? E.fxv.lost : nullptr);
+  else
+    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, st, rc, E.dc);
 }
 
 // Instantiated graphs of `rest` queued rounds (one run's cache: the graphs
@@ -2368,6 +2369,7 @@ uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableVie
   E.stats = stats;
   E.st = st;
   E.rc = ps.rc;
+  E.track_lost = ps.contract_every != 0 && fx && fx->lost.get();
   E.lists.reset(6 * n_r);
   uint32_t *L = E.lists.get();
   // H = every r-clique
