@@ -1759,7 +1759,9 @@ __global__ __launch_bounds__(256) void k_gen_spread(RoundCtl *rc, const uint64_t
 
 // A thread per candidate x of the round: flag x when it lies in I(R) and
 // list the members that have out-arcs as (frontier index, x).
-// r = 1 and r = 2 list each s-clique once, from its owner.
+// Candidates whose s-cliques with R are all gone or all owned by another
+// frontier r-clique are left out: r = 1 by vertex stamps, r = 2 by edge
+// states, r >= 3 by looking up the r-subsets of R + x through x.
 // r = 2: arcst[e] says whether the edge of arc position e was peeled in an
 // earlier round (dead) or is in this round's frontier.  A candidate x joins
 // I(R), R = {u < v}, only if both its edges to R are alive (no s-clique
@@ -1817,6 +1819,53 @@ __global__ __launch_bounds__(256) void k_gen_member(GraphView g, RoundCtl *rc,
         for (int i = 0; i < R; i++) {
           const int32_t u = fv[(int64_t)f * R + i];
           if (in && u != v) in = adjacent(g, x, u);
+        }
+        // r >= 3: the other r-subsets of R + x are R minus one vertex plus x.
+        // One peeled earlier: every s-clique through R + x is gone.  One in
+        // this round's frontier that precedes R lexicographically: it owns
+        // each of them (Update-Func's owner rule: subsets of a sorted s-clique
+        // compare by position as they compare by vertex).  Either way R
+        // would only list them to skip them.
+        if (in) {
+          int32_t Rv[R], v1s[R], v2s[R];
+          Key keys[R];
+          bool want[R], before[R];
+#pragma unroll
+          for (int i = 0; i < R; i++) Rv[i] = fv[(int64_t)f * R + i];
+#pragma unroll
+          for (int a = 0; a < R; a++) {
+            int32_t Tv[R];  // R without Rv[a], with x, ascending
+            int o = 0;
+            bool placed = false;
+#pragma unroll
+            for (int i = 0; i < R; i++) {
+              if (i == a) continue;
+              if (!placed && x < Rv[i]) {
+                Tv[o++] = x;
+                placed = true;
+              }
+              Tv[o++] = Rv[i];
+            }
+            if (!placed) Tv[R - 1] = x;
+            int d = 0;  // first place where Tv and R differ (they differ somewhere)
+#pragma unroll
+            for (int i = R - 1; i >= 0; i--)
+              if (Tv[i] != Rv[i]) d = i;
+            before[a] = Tv[d] < Rv[d];
+            v1s[a] = Tv[0];
+            v2s[a] = Tv[1];
+            keys[a] = rkey<R>(T, Tv);
+            want[a] = true;
+          }
+          int64_t pos[R];
+          Slot sl[R];
+          table_find_n<R, (R >= 4)>(T, v1s, v2s, keys, want, pos, sl);
+          const uint32_t t = rc->t;
+#pragma unroll
+          for (int a = 0; a < R; a++) {
+            const uint32_t st = sl[a].stamp;
+            if (pos[a] >= 0 && st != kLive && (st < t || (st == t && before[a]))) in = false;
+          }
         }
       }
       flag[k] = in ? 1 : 0;
