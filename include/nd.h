@@ -111,7 +111,9 @@ typedef struct {
   uint32_t max_kappa;
   uint32_t max_out_degree; /* of the orientation */
   float ms[8];           /* phase times: 0 validate, 1 orient+relabel, 2 table,
-                            3 count, 4 bucket init, 5 peel loop, 6 emit, 7 total */
+                            3 count, 4 bucket init, 5 peel loop, 6 emit, 7 total (of this
+                            call: a run that resumed a stopped peel counts no count phase
+                            and only its own rounds) */
   float count_kernel_ms; /* with options.timing: time of the s-clique count kernels */
   float peel_kernel_ms;  /* with options.timing: summed time of every round's update
                             (apply) kernel -- k_apply3 / k_apply / k_gen_apply / k_peel --
@@ -166,8 +168,13 @@ nd_status nd_plan_sizes(nd_plan p, uint64_t *n_r, uint64_t *workspace_bytes,
  * ND_ENOMEM after the peel started when one round needs more records (or
  * round-trace entries) than the workspace holds -- the plan then reports
  * the larger requirement through nd_plan_sizes and may be run again;
- * ND_EOVERFLOW when a count does not fit 32 bits.  A plan may be run any
- * number of times; each run starts again from the table. */
+ * ND_EOVERFLOW when a count does not fit 32 bits.  After ND_ENOMEM for
+ * records or out-arcs the plan keeps the peel's state (in host memory),
+ * and the next nd_run on it goes on from the round that stopped; the rows,
+ * kappa and counts of the whole peel are written by the run that finishes
+ * (initial counts as the stopped run took them; a resumed run that asks
+ * for counts the stopped run did not take starts again).  Otherwise a plan
+ * may be run any number of times; each run starts again from the table. */
 nd_status nd_run(nd_plan p, void *workspace_dev, uint64_t workspace_bytes, int32_t *rcliques_dev,
                  uint32_t *kappa_dev, uint32_t *counts_dev, nd_stats *stats);
 

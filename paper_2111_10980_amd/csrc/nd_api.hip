@@ -400,6 +400,10 @@ struct nd_plan_s {
   int levels = 2;     // r-clique table levels: 2, or 3 (r >= 4)
   int runs = 0;
   bool traced = false;
+  PeelSuspend susp;          // a peel stopped by a round that outgrew the workspace
+  uint64_t susp_n_s = 0;     // its s-clique count
+  bool susp_counts = false;  // its initial counts are kept (susp_cnt)
+  std::vector<uint32_t> susp_cnt;
   uint64_t rec_need = 0;     // record capacity the next run's workspace provides at least
   uint32_t trace_need = 0;   // round-trace capacity likewise
   std::vector<uint64_t> round_sizes;
@@ -748,49 +752,20 @@ void run_impl(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *counts
   // what is left of the workspace (a batch run carves its own buffers first)
   const uint64_t rec_cap = rec_cap_for(p, g_ws->size - g_ws->used);
   const uint32_t tcap = p->trace_need;
+  const bool canon = p->opt.canonical && p->n_r > 1;
+  // A peel that stopped at a round the last workspace could not hold goes on
+  // from that round: the slots, statistics and round control are the plan's,
+  // the rest of its state was kept in host memory.  (Not when this run asks
+  // for initial counts that run did not take.)
+  const bool want_counts = counts_dev != nullptr;
+  if (p->susp.on && want_counts && !p->susp_counts) p->susp.on = false;
+  const bool resume = p->susp.on;
   tm.mark(0, st);
-  if (p->runs > 0 && p->n_slots)  // a re-run starts from the table as built
+  if (!resume && p->runs > 0 && p->n_slots)  // a re-run starts from the table as built
     hipLaunchKernelGGL(k_reset_slots, dim3((unsigned)grid_for(p->n_slots, 256, 16384)),
                        dim3(256), 0, st, p->slots.get(), p->n_slots);
   p->runs++;
   p->traced = false;
-  // ---- count (Count-Func)
-  fill_u32((uint32_t *)dc, 0, sizeof(Counters) / 4, st);
-  fill_u64((uint64_t *)p->stats.get(), 0, (int64_t)kStatLines * kStatStride, st);
-  if (p->fast) {
-    if (timing) tm.mark(5, st);
-    count_direct(p->g, r, p->table(), p->fx, p->occ.get(), p->n_r, dc, st);
-    if (timing) tm.mark(6, st);
-  } else {
-    count_scliques(p->g, r, s, p->table(), dc, p->stats.get(), st,
-                   timing ? tm.at(5) : nullptr, timing ? tm.at(6) : nullptr);
-    stats_collect(p->stats.get(), dc, st);
-    fill_u64((uint64_t *)p->stats.get(), 0, (int64_t)kStatLines * kStatStride, st);
-  }
-  unsigned long long *total = p->total.get();
-  fill_u64((uint64_t *)total, 0, 2, st);
-  if (p->n_slots)
-    hipLaunchKernelGGL(k_sum_slot_counts, dim3((unsigned)grid_for(p->n_slots, 256 * 16, 4096)),
-                       dim3(256), 0, st, p->slots.get(), p->n_slots, total);
-  Counters hc = read_dev(dc, st);
-  if (hc.err) fail(ND_EHIP, "s-clique count failed (flags %u)", hc.err);
-  if (timing) {
-    count_kernel_ms = tm.between(5, 6);
-    count_launches = 1;
-  }
-  const uint64_t sum = read_dev((uint64_t *)total, st);
-  const uint64_t maxc = read_dev((uint64_t *)total + 1, st);
-  const uint64_t per = binom_u64(s, r);
-  // direct counting: every s-clique is counted once by each of its r-subsets
-  const uint64_t n_s = p->fast ? sum / per : hc.n_s;
-  if (p->fast && sum % per != 0) fail(ND_EHIP, "direct counts are inconsistent");
-  if (sum != per * n_s) fail(ND_EOVERFLOW, "an s-clique count exceeds 32 bits");
-  if (maxc + p->opt.debug_count_bias > 0xFFFFFFFFull)
-    fail(ND_EOVERFLOW, "an s-clique count (%llu + bias %llu) exceeds 32 bits",
-         (unsigned long long)maxc, (unsigned long long)p->opt.debug_count_bias);
-  const bool canon = p->opt.canonical && p->n_r > 1;
-  // outputs are staged for the canonical row order; the initial counts are
-  // taken now, before the peel decrements them
   DevBuf<int32_t> rows_tmp;
   DevBuf<uint32_t> kap_tmp, cnt_tmp;
   if (canon) {
@@ -801,36 +776,83 @@ void run_impl(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *counts
   int32_t *rows_out = canon ? rows_tmp.get() : rcl_dev;
   uint32_t *kap_out = canon ? kap_tmp.get() : kappa_dev;
   uint32_t *cnt_out = canon ? cnt_tmp.get() : counts_dev;
-  if (cnt_out) gather_counts(p->occ.get(), p->n_r, p->slots.get(), cnt_out, st);
-  if (p->fast && r == 2) {  // (2,3): the listed adjacency starts as the graph's
-    const uint64_t nnz = (uint64_t)p->g.nnz;
-    if (p->fx.bm_words)
-      hip_check(hipMemcpyAsync(p->fx.alive.get(), p->fx.bm.get(), 8 * p->fx.bm_words,
-                               hipMemcpyDeviceToDevice, st),
-                "copy bitmaps");
-    if (p->fx.n_tri)
-      hip_check(hipMemcpyAsync(p->fx.lvr.get(), p->fx.lval.get(), 4 * p->fx.n_tri,
-                               hipMemcpyDeviceToDevice, st),
-                "copy apex lists");
-    if (nnz)
-      hipLaunchKernelGGL(k_r2_init_arcs, dim3((unsigned)grid_for((int64_t)nnz, 256)), dim3(256), 0,
-                         st, p->fx.lptr.get(), nnz, p->fx.llen.get(), p->fx.arcst.get());
-    if (p->g.n)
-      hipLaunchKernelGGL(k_r2_init_vertices, dim3((unsigned)grid_for(p->g.n, 256)), dim3(256), 0,
-                         st, p->g.rp.get(), p->g.n, p->fx.lost.get(), p->fx.deg_at.get());
-  }
-  if (p->fast && r == 3) {  // liveness bitmaps start as the adjacency bitmaps
-    if (p->fx.bm_words)
-      hip_check(hipMemcpyAsync(p->fx.alive.get(), p->fx.bm.get(), 8 * p->fx.bm_words,
-                               hipMemcpyDeviceToDevice, st),
-                "copy bitmaps");
-    const uint64_t bw = p->fx.bm_words ? p->fx.bm_words : 1;
-    const uint64_t aw = (p->fx.n_tri + 63) / 64 ? (p->fx.n_tri + 63) / 64 : 1;
-    fill_u64(p->fx.alive_apex.get(), ~0ull, (int64_t)aw, st);  // every triangle alive
-    fill_u64(p->fx.front.get(), 0, (int64_t)bw, st);            // no triangle in a frontier yet
-    fill_u64(p->fx.front_apex.get(), 0, (int64_t)aw, st);
-  }
-  tm.mark(1, st);
+  uint64_t n_s = p->susp_n_s;
+  Counters hc{};
+  if (resume) {
+    if (cnt_out &&
+        hipMemcpyAsync(cnt_out, p->susp_cnt.data(), 4 * p->n_r, hipMemcpyHostToDevice, st) !=
+            hipSuccess)
+      fail(ND_EHIP, "restore the initial counts");
+    tm.mark(1, st);
+  } else {
+    // ---- count (Count-Func)
+    fill_u32((uint32_t *)dc, 0, sizeof(Counters) / 4, st);
+    fill_u64((uint64_t *)p->stats.get(), 0, (int64_t)kStatLines * kStatStride, st);
+    if (p->fast) {
+      if (timing) tm.mark(5, st);
+      count_direct(p->g, r, p->table(), p->fx, p->occ.get(), p->n_r, dc, st);
+      if (timing) tm.mark(6, st);
+    } else {
+      count_scliques(p->g, r, s, p->table(), dc, p->stats.get(), st,
+                     timing ? tm.at(5) : nullptr, timing ? tm.at(6) : nullptr);
+      stats_collect(p->stats.get(), dc, st);
+      fill_u64((uint64_t *)p->stats.get(), 0, (int64_t)kStatLines * kStatStride, st);
+    }
+    unsigned long long *total = p->total.get();
+    fill_u64((uint64_t *)total, 0, 2, st);
+    if (p->n_slots)
+      hipLaunchKernelGGL(k_sum_slot_counts, dim3((unsigned)grid_for(p->n_slots, 256 * 16, 4096)),
+                         dim3(256), 0, st, p->slots.get(), p->n_slots, total);
+    hc = read_dev(dc, st);
+    if (hc.err) fail(ND_EHIP, "s-clique count failed (flags %u)", hc.err);
+    if (timing) {
+      count_kernel_ms = tm.between(5, 6);
+      count_launches = 1;
+    }
+    const uint64_t sum = read_dev((uint64_t *)total, st);
+    const uint64_t maxc = read_dev((uint64_t *)total + 1, st);
+    const uint64_t per = binom_u64(s, r);
+    // direct counting: every s-clique is counted once by each of its r-subsets
+    n_s = p->fast ? sum / per : hc.n_s;
+    if (p->fast && sum % per != 0) fail(ND_EHIP, "direct counts are inconsistent");
+    if (sum != per * n_s) fail(ND_EOVERFLOW, "an s-clique count exceeds 32 bits");
+    if (maxc + p->opt.debug_count_bias > 0xFFFFFFFFull)
+      fail(ND_EOVERFLOW, "an s-clique count (%llu + bias %llu) exceeds 32 bits",
+           (unsigned long long)maxc, (unsigned long long)p->opt.debug_count_bias);
+    // outputs are staged for the canonical row order; the initial counts are
+    // taken now, before the peel decrements them
+    if (cnt_out) gather_counts(p->occ.get(), p->n_r, p->slots.get(), cnt_out, st);
+    if (p->fast && r == 2) {  // (2,3): the listed adjacency starts as the graph's
+      const uint64_t nnz = (uint64_t)p->g.nnz;
+      if (p->fx.bm_words)
+        hip_check(hipMemcpyAsync(p->fx.alive.get(), p->fx.bm.get(), 8 * p->fx.bm_words,
+                                 hipMemcpyDeviceToDevice, st),
+                  "copy bitmaps");
+      if (p->fx.n_tri)
+        hip_check(hipMemcpyAsync(p->fx.lvr.get(), p->fx.lval.get(), 4 * p->fx.n_tri,
+                                 hipMemcpyDeviceToDevice, st),
+                  "copy apex lists");
+      if (nnz)
+        hipLaunchKernelGGL(k_r2_init_arcs, dim3((unsigned)grid_for((int64_t)nnz, 256)),
+                           dim3(256), 0, st, p->fx.lptr.get(), nnz, p->fx.llen.get(),
+                           p->fx.arcst.get());
+      if (p->g.n)
+        hipLaunchKernelGGL(k_r2_init_vertices, dim3((unsigned)grid_for(p->g.n, 256)), dim3(256), 0,
+                           st, p->g.rp.get(), p->g.n, p->fx.lost.get(), p->fx.deg_at.get());
+    }
+    if (p->fast && r == 3) {  // liveness bitmaps start as the adjacency bitmaps
+      if (p->fx.bm_words)
+        hip_check(hipMemcpyAsync(p->fx.alive.get(), p->fx.bm.get(), 8 * p->fx.bm_words,
+                                 hipMemcpyDeviceToDevice, st),
+                  "copy bitmaps");
+      const uint64_t bw = p->fx.bm_words ? p->fx.bm_words : 1;
+      const uint64_t aw = (p->fx.n_tri + 63) / 64 ? (p->fx.n_tri + 63) / 64 : 1;
+      fill_u64(p->fx.alive_apex.get(), ~0ull, (int64_t)aw, st);  // every triangle alive
+      fill_u64(p->fx.front.get(), 0, (int64_t)bw, st);            // no triangle in a frontier yet
+      fill_u64(p->fx.front_apex.get(), 0, (int64_t)aw, st);
+    }
+    tm.mark(1, st);
+  }  // fresh run
   // ---- bucket init + peel, driven by the device (the host polls the
   // round state every few rounds)
   PeelResult pr;
@@ -846,8 +868,20 @@ void run_impl(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *counts
   ps.graph_stream = timing ? nullptr : p->graph_stream;
   const uint32_t perr =
       peel_all(p->g, r, s, p->path, p->table(), p->fast ? &p->fx : nullptr, p->occ.get(), p->n_r,
-               dc, p->stats.get(), ps, rec_cap, tcap, st, tm.at(2), &kround, &pr);
+               dc, p->stats.get(), ps, rec_cap, tcap, st, tm.at(2), &kround, &pr, &p->susp);
   if (perr & kErrCapacity) {
+    if (p->susp.on && !resume) {  // keep what the next run needs besides the peel state
+      p->susp_n_s = n_s;
+      p->susp_counts = cnt_out != nullptr;
+      p->susp_cnt.clear();
+      if (cnt_out) {
+        p->susp_cnt.resize(p->n_r);
+        if (hipMemcpyAsync(p->susp_cnt.data(), cnt_out, 4 * p->n_r, hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+          p->susp.on = false;
+      }
+    }
     // the workspace was too small for one round: raise the requirement so
     // that nd_plan_sizes reports the size to run again with
     if (pr.need_rec > rec_cap)  // later rounds may need more: half again, at least double

@@ -18,7 +18,10 @@
 // a wave prefix sum of the row popcounts, and lane p takes pair p.  Roots are
 // binned by d into W = 1, 2, 4, 8 words so the LDS footprint follows the
 // root.  Roots with d > 512 go to a wave-per-root kernel whose lanes extend
-// cliques with binary-search edge tests instead of bitmaps.
+// cliques with binary-search edge tests instead of bitmaps.  For s-clique
+// counting with s >= 4 the pairs of a root are split over `split` waves (each
+// stages the root itself): the few roots of the wide bins hold most of the
+// deep listing work, and one wave each left most of the chip idle.
 #include "nd_host.h"
 
 namespace nd {
@@ -76,7 +79,7 @@ __device__ void bitmap_dfs(const uint64_t *rows, const int32_t *nb, int32_t (&S)
 
 template <int C, int W, class Op>
 __global__ __launch_bounds__(kWave) void k_list_bitmap(GraphView g, const uint32_t *__restrict__ roots,
-                                                       uint32_t nroots, Op op) {
+                                                       uint32_t nroots, Op op, uint32_t split) {
   constexpr int D = 64 * W;
   __shared__ int32_t nb[D];
   __shared__ uint64_t rows[C >= 3 ? D * W : 1];
@@ -84,7 +87,10 @@ __global__ __launch_bounds__(kWave) void k_list_bitmap(GraphView g, const uint32
   const int lane = threadIdx.x;
   typename Op::Lane ls;
   op.lane_init(ls);
-  for (uint32_t ri = blockIdx.x; ri < nroots; ri += gridDim.x) {
+  // item = (root, part): the part-th of the root's `split` waves
+  const uint64_t items = (uint64_t)nroots * split;
+  for (uint64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const uint32_t ri = (uint32_t)(it / split), part = (uint32_t)(it % split);
     const int32_t v = (int32_t)roots[ri];
     const int64_t o = g.up[v];
     const int d = (int)(g.rp[v + 1] - o);
@@ -92,7 +98,7 @@ __global__ __launch_bounds__(kWave) void k_list_bitmap(GraphView g, const uint32
     __syncthreads();
     op.root_begin(ls, v);
     if constexpr (C == 2) {
-      for (int i = lane; i < d; i += kWave) {
+      for (int i = (int)(part * kWave) + lane; i < d; i += (int)(split * kWave)) {
         int32_t S[2] = {v, nb[i]};
         op(ls, S);
       }
@@ -133,7 +139,7 @@ __global__ __launch_bounds__(kWave) void k_list_bitmap(GraphView g, const uint32
       if (lane == 0) pre[d] = carry;
       __syncthreads();
       const uint32_t P = pre[d];
-      for (uint32_t p = lane; p < P; p += kWave) {
+      for (uint32_t p = part * kWave + lane; p < P; p += split * kWave) {
         int lo = 0, hi = d - 1;
         while (lo < hi) {
           int mid = (lo + hi + 1) >> 1;
@@ -211,6 +217,7 @@ __global__ __launch_bounds__(kWave) void k_list_heavy(GraphView g, const uint32_
 // Count-Func: +1 on the count of every r-subset of the s-clique.
 template <int R, int S>
 struct CountOp {
+  static constexpr bool kSplit = true;  // no per-root state: a root may span waves
   TableView T;
   Counters *ctr;
   unsigned long long *stats;
@@ -262,6 +269,7 @@ struct CountOp {
 // Number of r-cliques whose lowest-ranked vertex is the root.
 template <int R>
 struct CountROp {
+  static constexpr bool kSplit = false;  // root_end writes the root's total
   uint32_t *cnt;
   struct Lane {
     uint32_t c;
@@ -280,6 +288,7 @@ struct CountROp {
 // position (three-level tables).
 template <int R>
 struct CountArcOp {
+  static constexpr bool kSplit = false;
   GraphView g;
   uint32_t *cnt;
   struct Lane {};
@@ -295,6 +304,7 @@ struct CountArcOp {
 
 template <int R>
 struct InsertOp {
+  static constexpr bool kSplit = false;
   TableView T;
   Counters *ctr;
   struct Lane {
@@ -317,6 +327,7 @@ struct InsertOp {
 // of the relabeled CSR.  Keys are (arc << xbits) | x, written at per-root
 // cursors so no two lanes contend on one counter.
 struct ApexOp {
+  static constexpr bool kSplit = false;
   GraphView g;
   unsigned long long *cursor;
   uint64_t *keys;
@@ -387,19 +398,22 @@ void bin_roots(const OrientedGraph &g, int minout, Counters *dctr, Bins *b, hipS
 template <int C, class Op>
 void launch_listing(const OrientedGraph &g, const Bins &b, const Op &op, hipStream_t st) {
   const GraphView gv = g.view();
-  auto grid = [](uint32_t n) { return dim3(n < 262144u ? n : 262144u); };
+  auto grid = [](uint64_t n) { return dim3((unsigned)(n < 262144u ? n : 262144u)); };
+  // waves per root of bins 0..3 (d <= 64, 128, 256, 512)
+  const bool deep = Op::kSplit && C >= 4;
+  const uint32_t sp[4] = {deep ? 2u : 1u, deep ? 8u : 1u, deep ? 16u : 1u, deep ? 32u : 1u};
   if (b.size[0])
-    hipLaunchKernelGGL((k_list_bitmap<C, 1, Op>), grid(b.size[0]), dim3(kWave), 0, st, gv,
-                       b.list(0), b.size[0], op);
+    hipLaunchKernelGGL((k_list_bitmap<C, 1, Op>), grid((uint64_t)b.size[0] * sp[0]), dim3(kWave),
+                       0, st, gv, b.list(0), b.size[0], op, sp[0]);
   if (b.size[1])
-    hipLaunchKernelGGL((k_list_bitmap<C, 2, Op>), grid(b.size[1]), dim3(kWave), 0, st, gv,
-                       b.list(1), b.size[1], op);
+    hipLaunchKernelGGL((k_list_bitmap<C, 2, Op>), grid((uint64_t)b.size[1] * sp[1]), dim3(kWave),
+                       0, st, gv, b.list(1), b.size[1], op, sp[1]);
   if (b.size[2])
-    hipLaunchKernelGGL((k_list_bitmap<C, 4, Op>), grid(b.size[2]), dim3(kWave), 0, st, gv,
-                       b.list(2), b.size[2], op);
+    hipLaunchKernelGGL((k_list_bitmap<C, 4, Op>), grid((uint64_t)b.size[2] * sp[2]), dim3(kWave),
+                       0, st, gv, b.list(2), b.size[2], op, sp[2]);
   if (b.size[3])
-    hipLaunchKernelGGL((k_list_bitmap<C, 8, Op>), grid(b.size[3]), dim3(kWave), 0, st, gv,
-                       b.list(3), b.size[3], op);
+    hipLaunchKernelGGL((k_list_bitmap<C, 8, Op>), grid((uint64_t)b.size[3] * sp[3]), dim3(kWave),
+                       0, st, gv, b.list(3), b.size[3], op, sp[3]);
   if (b.size[4])
     hipLaunchKernelGGL((k_list_heavy<C, Op>), grid(b.size[4]), dim3(kWave), 0, st, gv,
                        b.list(4), b.size[4], op);

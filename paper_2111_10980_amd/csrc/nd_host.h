@@ -235,17 +235,33 @@ struct PeelState {
 // Workspace bytes peel_all allocates with the given capacities.
 uint64_t peel_ws_bytes(int r, int path, uint64_t n_r, uint64_t nnz, uint64_t rec_cap,
                        uint32_t trace_cap);
+// The peel's state between rounds that lives in the workspace (bucket
+// lists, round trace, r = 2 edge states), kept in host memory when a round
+// outgrew the workspace, together with the round control block as it
+// stopped.  Everything else the peel carries from round to round is
+// plan-owned (slot counts and stamps, liveness bits, statistics), so a run
+// with a larger workspace continues at the round that stopped.
+struct PeelSuspend {
+  bool on = false;
+  RoundCtl rc{};
+  std::vector<uint32_t> lists;       // 6 n_r
+  std::vector<uint32_t> tsize, tk;   // the rounds done
+  std::vector<uint8_t> dead;         // s >= r+2, r = 2: per-arc edge states
+};
+
 // Whole bucketed peel (Algorithm 2 after the count) on the device.  path: 0
 // the one-wave walker, 1 the s = r+1 expand/apply passes (needs fx), 2 the
 // flattened s >= r+2 passes.  rec_cap records (and kArcsPerRecord * rec_cap
 // out-arcs) per round and trace_cap rounds; a round that needs more stops the
-// peel with kErrCapacity and the capacity it needs in res.  kround receives
-// the level of every round (for emit).  Returns 0 or kErr* bits.
+// peel with kErrCapacity and the capacity it needs in res.  With sus, a round
+// that outgrew the records or out-arcs leaves the state in *sus, and a call
+// with sus->on continues from it instead of starting the peel.  kround
+// receives the level of every round (for emit).  Returns 0 or kErr* bits.
 uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableView &T,
                   const FastIndex *fx, const uint32_t *occ, uint64_t n_r, Counters *dc,
                   unsigned long long *stats, const PeelState &ps, uint64_t rec_cap,
                   uint32_t trace_cap, hipStream_t st, hipEvent_t ev_first,
-                  DevBuf<uint32_t> *kround, PeelResult *res);
+                  DevBuf<uint32_t> *kround, PeelResult *res, PeelSuspend *sus);
 void occupied_list(const Slot *slots, uint64_t n_slots, uint32_t *occ, hipStream_t st);
 void gather_counts(const uint32_t *occ, uint64_t n_r, const Slot *slots, uint32_t *out,
                    hipStream_t st);

@@ -2388,7 +2388,7 @@ uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableVie
                   const FastIndex *fx, const uint32_t *occ, uint64_t n_r, Counters *dc,
                   unsigned long long *stats, const PeelState &ps, uint64_t rec_cap,
                   uint32_t trace_cap, hipStream_t st, hipEvent_t ev_first,
-                  DevBuf<uint32_t> *kround, PeelResult *res) {
+                  DevBuf<uint32_t> *kround, PeelResult *res, PeelSuspend *sus) {
   res->sizes.clear();
   res->levels.clear();
   res->advances = 0;
@@ -2419,19 +2419,34 @@ uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableVie
   E.st = st;
   E.rc = ps.rc;
   E.track_lost = ps.contract_every != 0 && fx && fx->lost.get();
+  // resume: the state a round that outgrew the previous workspace left
+  const bool resume = sus && sus->on;
+  if (resume && (sus->lists.size() != 6 * n_r || sus->rc.t > trace_cap ||
+                 sus->tsize.size() != sus->rc.t || sus->tk.size() != sus->rc.t))
+    return kErrRuntime;
+  const uint64_t na = g.nnz > 0 ? (uint64_t)g.nnz : 1;  // arc positions
   E.lists.reset(6 * n_r);
   uint32_t *L = E.lists.get();
-  // H = every r-clique
-  if (hipMemcpyAsync(L + 4 * n_r, occ, 4 * n_r, hipMemcpyDeviceToDevice, st) != hipSuccess)
+  if (resume) {
+    if (hipMemcpyAsync(L, sus->lists.data(), 24 * n_r, hipMemcpyHostToDevice, st) != hipSuccess)
+      return kErrRuntime;
+  } else if (hipMemcpyAsync(L + 4 * n_r, occ, 4 * n_r, hipMemcpyDeviceToDevice, st) !=
+             hipSuccess) {  // H = every r-clique
     return kErrRuntime;
+  }
   E.off.reset(n_r);
   E.len.reset(n_r);
   E.fv.reset(n_r * (uint64_t)r);
   if (path == 2) E.drv.reset(n_r);
   if (path == 2 && r == 2) {
-    const uint64_t na = g.nnz > 0 ? (uint64_t)g.nnz : 1;
     E.dead.reset(na);
-    fill_u32((uint32_t *)E.dead.get(), 0, (int64_t)(ws_block(na) / 4), st);
+    if (!resume) {
+      fill_u32((uint32_t *)E.dead.get(), 0, (int64_t)(ws_block(na) / 4), st);
+    } else if (sus->dead.size() != na ||
+               hipMemcpyAsync(E.dead.get(), sus->dead.data(), na, hipMemcpyHostToDevice, st) !=
+                   hipSuccess) {
+      return kErrRuntime;
+    }
   }
   if (path == 1) {
     E.desc.reset(n_r);
@@ -2443,9 +2458,29 @@ uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableVie
   if (path != 0) alloc_records(E, rec_cap);
   E.tsize.reset(E.tcap);
   E.tk.reset(E.tcap);
+  if (resume && sus->rc.t &&
+      (hipMemcpyAsync(E.tsize.get(), sus->tsize.data(), 4ull * sus->rc.t, hipMemcpyHostToDevice,
+                      st) != hipSuccess ||
+       hipMemcpyAsync(E.tk.get(), sus->tk.data(), 4ull * sus->rc.t, hipMemcpyHostToDevice, st) !=
+           hipSuccess))
+    return kErrRuntime;
 
   RoundCtl h;
-  memset(&h, 0, sizeof(h));
+  if (resume) {  // the stopped round starts again; its lists now sit in this workspace
+    h = sus->rc;
+    h.halt = 0;
+    h.need = 0;
+    h.F = nullptr;
+    h.Fnext = nullptr;
+    h.Low = nullptr;
+  } else {
+    memset(&h, 0, sizeof(h));
+    h.n_r = n_r;
+    h.nH = (uint32_t)n_r;
+    h.contract_every = ps.contract_every;
+    h.mw = kNone;
+    h.mh = kNone;
+  }
   for (int i = 0; i < 2; i++) {
     h.bufF[i] = L + (uint64_t)i * n_r;
     h.bufW[i] = L + (uint64_t)(2 + i) * n_r;
@@ -2454,13 +2489,9 @@ uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableVie
   h.trace_size = E.tsize.get();
   h.trace_k = E.tk.get();
   h.trace_cap = E.tcap;
-  h.n_r = n_r;
   h.cap = E.cap;
   h.cap3 = E.cap3;
-  h.nH = (uint32_t)n_r;
-  h.contract_every = ps.contract_every;
-  h.mw = kNone;
-  h.mh = kNone;
+  if (sus) sus->on = false;
   RoundCtl *mirror = ps.mirror;
   *mirror = h;  // staged through pinned memory: the copy is asynchronous
   if (hipMemcpyAsync(E.rc, mirror, sizeof(h), hipMemcpyHostToDevice, st) != hipSuccess ||
@@ -2519,6 +2550,28 @@ uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableVie
       res->max_rec = m.max_total;
       res->max_arcs = m.max_total3;
       status = kErrCapacity;
+      // records or out-arcs: keep the state between rounds for a larger
+      // workspace (the trace capacity is part of the layout: a run that
+      // outgrew it starts again)
+      if (sus && m.halt != 2) {
+        sus->rc = m;
+        sus->lists.resize(6 * n_r);
+        sus->tsize.resize(m.t);
+        sus->tk.resize(m.t);
+        sus->dead.resize(path == 2 && r == 2 ? na : 0);
+        bool ok = hipMemcpyAsync(sus->lists.data(), L, 24 * n_r, hipMemcpyDeviceToHost, st) ==
+                  hipSuccess;
+        if (m.t)
+          ok = ok &&
+               hipMemcpyAsync(sus->tsize.data(), E.tsize.get(), 4ull * m.t,
+                              hipMemcpyDeviceToHost, st) == hipSuccess &&
+               hipMemcpyAsync(sus->tk.data(), E.tk.get(), 4ull * m.t, hipMemcpyDeviceToHost,
+                              st) == hipSuccess;
+        if (!sus->dead.empty())
+          ok = ok && hipMemcpyAsync(sus->dead.data(), E.dead.get(), na, hipMemcpyDeviceToHost,
+                                    st) == hipSuccess;
+        sus->on = ok && hipStreamSynchronize(st) == hipSuccess;
+      }
       break;
     }
     if (m.halt) {

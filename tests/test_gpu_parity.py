@@ -479,6 +479,105 @@ def test_round_capacity_requery(r, s):
     check_against_oracle(g, r, s, record_cap=64, trace_cap=2)
 
 
+@pytest.mark.parametrize("r,s,kw", [
+    (3, 4, {}), (2, 4, {}), (2, 3, {"contract": True}), (3, 5, {}), (1, 3, {}), (4, 5, {}),
+    (2, 5, {}), (3, 4, {"canonical": True}), (2, 4, {"canonical": True}),
+    (3, 4, {"with_counts": False}),
+])
+def test_round_capacity_resume(r, s, kw):
+    """A round that outgrows the records or out-arcs of the workspace stops
+    the run with ND_ENOMEM; the next run on the plan, with the workspace it
+    then reports, goes on from that round.  Over many such stops the whole
+    peel is exact (rows, initial counts, kappa, every round's size and
+    level, decrements), and the finishing run does no counting."""
+    nd = _nd()
+    import torch
+    kw = dict(kw)
+    with_counts = kw.pop("with_counts", True)
+    canonical = kw.get("canonical", False)
+    g = inputs.rmat(10, 8, 321)
+    ref = oracle.decompose(g.n, g.row_ptr, g.col, r, s)
+    rp, col = nd.to_device(g)
+    plan = nd.nd_plan_create(rp, col, r, s, record_cap=64, timing=True, **kw)
+    try:
+        n_r = nd.nd_plan_sizes(plan)[0]
+        rcl = torch.empty((n_r, r), dtype=torch.int32, device="cuda")
+        kap = torch.empty((n_r,), dtype=torch.int32, device="cuda")
+        cnt = torch.empty((n_r,), dtype=torch.int32, device="cuda") if with_counts else None
+        stops = 0
+        while True:
+            ws_bytes = nd.nd_plan_sizes(plan)[1]
+            try:
+                st = nd.nd_run(plan, nd.workspace(ws_bytes), rcl, kap, cnt, ws_bytes=ws_bytes)
+                break
+            except nd.NdError as e:
+                assert e.name == "ND_ENOMEM"
+                stops += 1
+                assert stops < 40
+        assert stops >= 1
+        assert st["count_launches"] == 0  # resumed: the count ran in the first run only
+        sizes, levels = nd.nd_round_trace(plan)
+    finally:
+        nd.nd_plan_destroy(plan)
+    rows = rcl.cpu().numpy()
+    k = kap.cpu().numpy().view(np.uint32).astype(np.uint64)
+    c = cnt.cpu().numpy().view(np.uint32).astype(np.uint64) if with_counts else None
+    if canonical:
+        np.testing.assert_array_equal(rows, ref.rcliques)
+    else:
+        order = np.lexsort(rows.T[::-1])
+        rows, k = rows[order], k[order]
+        c = c[order] if with_counts else None
+        np.testing.assert_array_equal(rows, ref.rcliques)
+    np.testing.assert_array_equal(k, ref.kappa)
+    if with_counts:
+        np.testing.assert_array_equal(c, ref.counts)
+    np.testing.assert_array_equal(sizes, ref.round_sizes)
+    np.testing.assert_array_equal(levels.astype(np.uint64), ref.round_k)
+    assert st["rounds"] == ref.rounds
+    assert st["n_s"] == ref.n_s
+    assert st["decrements"] == ref.decrements
+
+
+def test_resume_then_fresh_run():
+    """After a resumed peel the plan runs again from its table (no stale
+    state), and a run asking for counts the stopped run did not take starts
+    again instead of resuming."""
+    nd = _nd()
+    import torch
+    g = inputs.rmat(9, 8, 5)
+    ref = oracle.decompose(g.n, g.row_ptr, g.col, 3, 4)
+    rp, col = nd.to_device(g)
+    plan = nd.nd_plan_create(rp, col, 3, 4, record_cap=64)
+    try:
+        n_r = nd.nd_plan_sizes(plan)[0]
+        rcl = torch.empty((n_r, 3), dtype=torch.int32, device="cuda")
+        kap = torch.empty((n_r,), dtype=torch.int32, device="cuda")
+        cnt = torch.empty((n_r,), dtype=torch.int32, device="cuda")
+        ws0 = nd.nd_plan_sizes(plan)[1]
+        with pytest.raises(nd.NdError):
+            nd.nd_run(plan, nd.workspace(ws0), rcl, kap)  # stops without counts
+        for _ in range(40):  # counts now: starts again, then resumes as it stops
+            ws_bytes = nd.nd_plan_sizes(plan)[1]
+            try:
+                nd.nd_run(plan, nd.workspace(ws_bytes), rcl, kap, cnt, ws_bytes=ws_bytes)
+                break
+            except nd.NdError as e:
+                assert e.name == "ND_ENOMEM"
+        first = (rcl.cpu().numpy().copy(), kap.cpu().numpy().copy(), cnt.cpu().numpy().copy())
+        ws_bytes = nd.nd_plan_sizes(plan)[1]
+        st = nd.nd_run(plan, nd.workspace(ws_bytes), rcl, kap, cnt, ws_bytes=ws_bytes)
+        assert st["rounds"] == ref.rounds
+        for a, b in zip(first, (rcl.cpu().numpy(), kap.cpu().numpy(), cnt.cpu().numpy())):
+            assert np.array_equal(a, b)
+    finally:
+        nd.nd_plan_destroy(plan)
+    order = np.lexsort(first[0].T[::-1])
+    np.testing.assert_array_equal(first[0][order], ref.rcliques)
+    np.testing.assert_array_equal(first[1].view(np.uint32)[order].astype(np.uint64), ref.kappa)
+    np.testing.assert_array_equal(first[2].view(np.uint32)[order].astype(np.uint64), ref.counts)
+
+
 @pytest.mark.parametrize("r,s", [(3, 4), (2, 3), (2, 4), (4, 5), (1, 2)])
 def test_canonical_rows(r, s):
     """options.canonical: rows come out in lexicographic order, equal to the
