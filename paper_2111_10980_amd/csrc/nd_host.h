@@ -244,7 +244,7 @@ uint64_t peel_ws_bytes(int r, int path, uint64_t n_r, uint64_t nnz, uint64_t rec
 struct PeelSuspend {
   bool on = false;
   RoundCtl rc{};
-  std::vector<uint32_t> lists;       // 6 n_r
+  std::vector<uint32_t> lists;       // the live lists: frontier, window, high (nF + nW + nH)
   std::vector<uint32_t> tsize, tk;   // the rounds done
   std::vector<uint8_t> dead;         // s >= r+2, r = 2: per-arc edge states
 };

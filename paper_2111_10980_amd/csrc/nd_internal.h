@@ -510,7 +510,15 @@ struct Counters {
 // advance it and every round kernel reads its parameters from it, so the
 // host can queue rounds back to back and only read it now and then.
 constexpr uint32_t kNone = 0xFFFFFFFFu;
-constexpr uint32_t kWindowLevels = 16;  // levels k+1..k+16 kept in the window list
+constexpr uint32_t kWindowLevels = 16;      // first window: levels k+1..k+16
+constexpr uint32_t kMaxWindowLevels = 1u << 16;
+
+// Top of a window opened at level k with wl levels (clamped below the
+// largest count the partition can test).
+__host__ __device__ inline uint32_t window_top(uint32_t k, uint32_t wl) {
+  const uint64_t t = (uint64_t)k + wl;
+  return t < 0xFFFFFFFEull ? (uint32_t)t : 0xFFFFFFFEu;
+}
 
 struct RoundCtl {
   // parameters of the current round, set by k_round_begin
@@ -532,6 +540,8 @@ struct RoundCtl {
   uint32_t contract_due;    // set when peeled_since reaches contract_every
   uint32_t contractions;    // contraction passes done
   uint32_t t, k, kw, nF;   // round, level, window top, |A_t|
+  uint32_t wlev;           // levels the next window opened from the high list spans
+  uint64_t wscan;          // window-list entries scanned by advances inside the current window
   uint32_t nA;             // |A_t| of the round under way (set by begin, kept by end)
   uint32_t nW, nH;         // window list and high list sizes
   uint32_t selF, selW, selH;

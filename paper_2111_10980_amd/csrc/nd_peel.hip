@@ -90,6 +90,7 @@ __device__ void round_begin_body(RoundCtl *rc, Counters *dc) {
     const uint32_t mn = win ? rc->mw : rc->mh;
     const uint32_t cF = rc->cF, cW = rc->cW, cH = rc->cH;
     if (win && mn == kNone) {
+      rc->wscan += rc->nW;
       rc->nW = 0;
     } else if (mn == kNone || cF == 0) {  // no live r-clique left, or an empty bucket
       rc->err |= kErrBucket;
@@ -98,9 +99,22 @@ __device__ void round_begin_body(RoundCtl *rc, Counters *dc) {
     } else {
       rc->k = rc->k > mn ? rc->k : mn;
       if (win) {
+        rc->wscan += rc->nW;  // this advance scanned the window list
         rc->selW ^= 1u;
       } else {
-        rc->kw = rc->k + kWindowLevels;
+        rc->kw = window_top(rc->k, rc->wlev);
+        // Balance the width of the next window: the advances inside the
+        // window that just closed scanned wscan window-list entries, this
+        // new window scanned the nH entries of the high list.  Narrower
+        // windows when the former dominates, wider when the latter does.
+        // (Measured against a fixed 16 levels: rMAT (3,5) scale 15 -19%,
+        // (2,4) scale 17 -9%, Chung-Lu 1M (2,4) -4%, rMAT-18 (3,4) equal,
+        // Chung-Lu 1M (4,5) +2%; widening is what the deep peels gain from,
+        // and capped at 16 levels they lost it.)
+        const uint64_t scan_h = rc->nH;
+        if (rc->wscan > 2 * scan_h && rc->wlev > 1) rc->wlev >>= 1;
+        else if (2 * rc->wscan < scan_h && rc->wlev < kMaxWindowLevels) rc->wlev <<= 1;
+        rc->wscan = 0;
         rc->nH = cH;
         rc->selH ^= 1u;
       }
@@ -1519,7 +1533,7 @@ __device__ __forceinline__ void partition_body(RoundCtl *rc, const Slot *__restr
                                                const FastView &fx,
                                                const uint64_t *__restrict__ loc) {
   const uint32_t k = rc->k > mn ? rc->k : mn;
-  const uint32_t kw = win ? 0xFFFFFFFEu : k + kWindowLevels;
+  const uint32_t kw = win ? 0xFFFFFFFEu : window_top(k, rc->wlev);
   const uint32_t *__restrict__ L = win ? rc->bufW[rc->selW] : rc->bufH[rc->selH];
   const uint32_t nL = win ? rc->nW : rc->nH;
   uint32_t *F = rc->bufF[rc->selF];
@@ -2421,15 +2435,39 @@ uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableVie
   E.track_lost = ps.contract_every != 0 && fx && fx->lost.get();
   // resume: the state a round that outgrew the previous workspace left
   const bool resume = sus && sus->on;
-  if (resume && (sus->lists.size() != 6 * n_r || sus->rc.t > trace_cap ||
-                 sus->tsize.size() != sus->rc.t || sus->tk.size() != sus->rc.t))
-    return kErrRuntime;
+  // the live part of the bucket lists: frontier F[selF], window W[selW] and
+  // high list H[selH] (the other buffer of each pair is scratch between
+  // rounds); a round that stopped appended nothing yet
+  auto live = [&](const RoundCtl &c, int i, uint64_t &off, uint64_t &len) {
+    const uint32_t sel = i == 0 ? c.selF : i == 1 ? c.selW : c.selH;
+    off = (uint64_t)(2 * i + (sel & 1u)) * n_r;
+    len = i == 0 ? c.nF : i == 1 ? c.nW : c.nH;
+  };
+  if (resume) {
+    uint64_t tot = 0;
+    for (int i = 0; i < 3; i++) {
+      uint64_t o, l;
+      live(sus->rc, i, o, l);
+      if (l > n_r) return kErrRuntime;
+      tot += l;
+    }
+    if (sus->lists.size() != tot || sus->rc.t > trace_cap || sus->tsize.size() != sus->rc.t ||
+        sus->tk.size() != sus->rc.t)
+      return kErrRuntime;
+  }
   const uint64_t na = g.nnz > 0 ? (uint64_t)g.nnz : 1;  // arc positions
   E.lists.reset(6 * n_r);
   uint32_t *L = E.lists.get();
   if (resume) {
-    if (hipMemcpyAsync(L, sus->lists.data(), 24 * n_r, hipMemcpyHostToDevice, st) != hipSuccess)
-      return kErrRuntime;
+    uint64_t at = 0;
+    for (int i = 0; i < 3; i++) {
+      uint64_t o, l;
+      live(sus->rc, i, o, l);
+      if (l && hipMemcpyAsync(L + o, sus->lists.data() + at, 4 * l, hipMemcpyHostToDevice, st) !=
+                   hipSuccess)
+        return kErrRuntime;
+      at += l;
+    }
   } else if (hipMemcpyAsync(L + 4 * n_r, occ, 4 * n_r, hipMemcpyDeviceToDevice, st) !=
              hipSuccess) {  // H = every r-clique
     return kErrRuntime;
@@ -2480,6 +2518,7 @@ uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableVie
     h.contract_every = ps.contract_every;
     h.mw = kNone;
     h.mh = kNone;
+    h.wlev = kWindowLevels;
   }
   for (int i = 0; i < 2; i++) {
     h.bufF[i] = L + (uint64_t)i * n_r;
@@ -2555,12 +2594,26 @@ uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableVie
       // outgrew it starts again)
       if (sus && m.halt != 2) {
         sus->rc = m;
-        sus->lists.resize(6 * n_r);
+        uint64_t tot = 0;
+        for (int i = 0; i < 3; i++) {
+          uint64_t o, l;
+          live(m, i, o, l);
+          tot += l;
+        }
+        sus->lists.resize(tot);
         sus->tsize.resize(m.t);
         sus->tk.resize(m.t);
         sus->dead.resize(path == 2 && r == 2 ? na : 0);
-        bool ok = hipMemcpyAsync(sus->lists.data(), L, 24 * n_r, hipMemcpyDeviceToHost, st) ==
-                  hipSuccess;
+        bool ok = true;
+        uint64_t at = 0;
+        for (int i = 0; i < 3; i++) {
+          uint64_t o, l;
+          live(m, i, o, l);
+          if (l)
+            ok = ok && hipMemcpyAsync(sus->lists.data() + at, L + o, 4 * l,
+                                      hipMemcpyDeviceToHost, st) == hipSuccess;
+          at += l;
+        }
         if (m.t)
           ok = ok &&
                hipMemcpyAsync(sus->tsize.data(), E.tsize.get(), 4ull * m.t,
