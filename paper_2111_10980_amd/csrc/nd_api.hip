@@ -899,6 +899,11 @@ void run_impl(nd_plan p, int32_t *rcl_dev, uint32_t *kappa_dev, uint32_t *counts
   if (perr & kErrRuntime) fail(ND_EHIP, "HIP error in the peel loop: %s",
                                hipGetErrorString(hipGetLastError()));
   if (perr) fail(ND_EHIP, "peel failed (flags %u)", perr);
+  if (!p->susp.lists.empty() || !p->susp_cnt.empty()) {  // a finished peel keeps nothing
+    p->susp = PeelSuspend();
+    std::vector<uint32_t>().swap(p->susp_cnt);
+    p->susp_counts = false;
+  }
   p->round_sizes = pr.sizes;
   p->round_k = pr.levels;
   p->k_advances = pr.advances;
