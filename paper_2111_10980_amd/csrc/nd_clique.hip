@@ -399,9 +399,13 @@ template <int C, class Op>
 void launch_listing(const OrientedGraph &g, const Bins &b, const Op &op, hipStream_t st) {
   const GraphView gv = g.view();
   auto grid = [](uint64_t n) { return dim3((unsigned)(n < 262144u ? n : 262144u)); };
-  // waves per root of bins 0..3 (d <= 64, 128, 256, 512)
+  // waves per root of bins 0..3 (d <= 64, 128, 256, 512).  Measured on rMAT
+  // (3,5) and (2,4): 5-cliques gain from the wider split (scale 13 count
+  // 180 -> 110 ms), 4-cliques lose from it (scale 17: 285 -> 329 ms).
   const bool deep = Op::kSplit && C >= 4;
-  const uint32_t sp[4] = {deep ? 2u : 1u, deep ? 8u : 1u, deep ? 16u : 1u, deep ? 32u : 1u};
+  const uint32_t sp4[4] = {2u, 8u, 16u, 32u}, sp5[4] = {4u, 32u, 64u, 64u};
+  uint32_t sp[4];
+  for (int i = 0; i < 4; i++) sp[i] = !deep ? 1u : C >= 5 ? sp5[i] : sp4[i];
   if (b.size[0])
     hipLaunchKernelGGL((k_list_bitmap<C, 1, Op>), grid((uint64_t)b.size[0] * sp[0]), dim3(kWave),
                        0, st, gv, b.list(0), b.size[0], op, sp[0]);
