@@ -552,6 +552,7 @@ struct RoundCtl {
   uint32_t cF, cW, cH;     // partition output sizes (advance)
   uint32_t advances;
   uint32_t trace_cap;
+  uint32_t ndone;          // blocks of the advance kernel finished (the last one resets it)
 };
 
 // Statistics accumulated by many waves go to kStatLines counter lines (one

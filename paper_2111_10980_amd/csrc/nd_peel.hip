@@ -88,7 +88,10 @@ __device__ void round_begin_body(RoundCtl *rc, Counters *dc) {
   if (rc->nF == 0) {  // finish the advance first: a rerun must not partition again
     const bool win = rc->nW != 0;
     const uint32_t mn = win ? rc->mw : rc->mh;
-    const uint32_t cF = rc->cF, cW = rc->cW, cH = rc->cH;
+    // written by other blocks' atomics in the same launch (k_advance_begin)
+    const uint32_t cF = __hip_atomic_load(&rc->cF, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t cW = __hip_atomic_load(&rc->cW, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t cH = __hip_atomic_load(&rc->cH, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (win && mn == kNone) {
       rc->wscan += rc->nW;
       rc->nW = 0;
@@ -1475,16 +1478,21 @@ __global__ void k_make_loc(GraphView g, TableView T, FastView fx, uint64_t n_slo
 }
 
 // ---------------------------------------------------------- round control
-// One round is queued as
+// The first round the host queues after reading the state is
 //   k_adv_min, k_adv_partition
-//       level advance; they act only when the round starts with an empty
-//       frontier (B.next_bucket of Algorithm 2);
+//       level advance (B.next_bucket of Algorithm 2), queued when the round
+//       starts with an empty frontier, on grids sized to the list;
 //   k_round_begin            one thread: finishes an advance (or drops a
 //                            window list of peeled entries), then the
 //                            round's lists and counters;
 //   the update passes of the path (the first one stamps A_t with t);
 //   k_round_end              one thread: trace, finished += |A_t|, next
-//                            frontier.
+//                            frontier; over the grid, when another round
+//                            is queued behind it and the next frontier is
+//                            empty, the minimum of that round's advance.
+// A round queued behind others starts with k_advance_begin instead: the
+// partition by that minimum, if its frontier is empty, and k_round_begin's
+// work in one launch on a small grid.
 // Every kernel returns at once once the peel has finished or halted, so the
 // host may queue rounds past the last one and read the state only now and
 // then.
@@ -1498,13 +1506,14 @@ __global__ void k_stamp(const RoundCtl *__restrict__ rc, Slot *slots) {
     slots[F[i]].stamp = t;
 }
 
-// Minimum count over the live entries of the window list, or of the high
-// list when the window list is empty.
-__global__ __launch_bounds__(256) void k_adv_min(RoundCtl *rc, const Slot *__restrict__ slots) {
-  if (rc_idle(rc) || rc->nF != 0) return;
-  const bool win = rc->nW != 0;
+// Minimum count over the live entries of the window list (nW entries), or
+// of the high list when the window list is empty.  Recomputing it gives the
+// same value as long as no count changes (atomicMin).
+__device__ __forceinline__ void adv_min_body(RoundCtl *rc, const Slot *__restrict__ slots,
+                                             uint32_t nW) {
+  const bool win = nW != 0;
   const uint32_t *__restrict__ L = win ? rc->bufW[rc->selW] : rc->bufH[rc->selH];
-  const uint32_t nL = win ? rc->nW : rc->nH;
+  const uint32_t nL = win ? nW : rc->nH;
   uint32_t m = kNone;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nL;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -1513,6 +1522,11 @@ __global__ __launch_bounds__(256) void k_adv_min(RoundCtl *rc, const Slot *__res
   }
   m = wave_min_u32(m);
   if (lane_id() == 0 && m != kNone) atomicMin(win ? &rc->mw : &rc->mh, m);
+}
+
+__global__ __launch_bounds__(256) void k_adv_min(RoundCtl *rc, const Slot *__restrict__ slots) {
+  if (rc_idle(rc) || rc->nF != 0) return;
+  adv_min_body(rc, slots, rc->nW);
 }
 
 // Three-way partition of the list the advance works on, by count c:
@@ -1610,23 +1624,78 @@ __global__ void k_round_begin(RoundCtl *rc, Counters *dc) {
   round_begin_body(rc, dc);
 }
 
-__global__ void k_round_end(RoundCtl *rc, const Counters *dc) {
+// Level advance and start of a round in one launch, for rounds queued behind
+// others (every block's fence and count is cheap only on their small grids:
+// on grids of thousands of blocks it cost more than the launch it saves).
+// Without an advance
+// (frontier not empty) block 0 starts the round at once: round_begin_body
+// then leaves nF, done and halt as the other blocks read them (halt 2 only
+// makes them return, as they do anyway).  With an advance every block
+// partitions its tiles and counts itself done; the last one, after a fence,
+// finishes the advance and starts the round.  Every block reads the state it
+// branches on before it counts itself, so no block sees the last one's
+// writes.  No block waits for another.
+__global__ __launch_bounds__(kPartThreads) void k_advance_begin(
+    RoundCtl *rc, Counters *dc, const Slot *__restrict__ slots, bool mark, GraphView g,
+    const int32_t *__restrict__ v1s, FastView fx, const uint64_t *__restrict__ loc) {
   if (rc_idle(rc)) return;
-  round_end_body(rc, dc);
+  if (rc->nF != 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) round_begin_body(rc, dc);
+    return;
+  }
+  const bool win = rc->nW != 0;
+  const uint32_t mn = win ? rc->mw : rc->mh;
+  // mn == kNone: round_begin_body drops the window or reports the error
+  if (mn != kNone) partition_body(rc, slots, win, mn, mark, g, v1s, fx, loc);
+  __shared__ uint32_t last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = atomicAdd(&rc->ndone, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    __threadfence();
+    rc->ndone = 0;
+    round_begin_body(rc, dc);
+  }
 }
 
-// r = 2, end of a round: the bookkeeping of k_round_end (one thread) and,
-// over the grid, the frontier's edges becoming dead for the candidate tests
+// Over the grid of a round's end that another queued round follows (the
+// first round the host queues after reading the state runs k_adv_min on a
+// grid sized to the list instead): when the next frontier is empty, the
+// minimum its level advance partitions by.  Every block decides from the
+// round's counters, which the bookkeeping of round_end_body leaves alone:
+// the next frontier holds next_size entries (zero after an empty round) and
+// the window list low_size.
+__device__ __forceinline__ void end_min(RoundCtl *rc, const Counters *dc,
+                                        const Slot *__restrict__ slots) {
+  if (dc->next_size != 0) return;
+  adv_min_body(rc, slots, dc->low_size);
+}
+
+__global__ __launch_bounds__(256) void k_round_end(RoundCtl *rc, const Counters *dc,
+                                                   const Slot *__restrict__ slots,
+                                                   uint32_t min_next) {
+  if (rc_idle(rc)) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) round_end_body(rc, dc);
+  if (min_next) end_min(rc, dc, slots);
+}
+
+// r = 2, end of a round: the bookkeeping and the next advance's minimum as
+// in k_round_end and, over the grid, the frontier's edges becoming dead for the candidate tests
 // of later rounds (both arc directions), counted as lost neighbours of both
 // endpoints when graph contraction is on (lost non-null).  The retirement
 // reads the round's |A_t| from nA, which the bookkeeping leaves alone.
 __global__ __launch_bounds__(256) void k_round_end_r2(RoundCtl *rc, const Counters *dc,
-                                                      GraphView g,
+                                                      const Slot *__restrict__ slots,
+                                                      uint32_t min_next, GraphView g,
                                                       const int32_t *__restrict__ fv,
                                                       uint8_t *arcst, uint32_t *lost) {
   if (rc_idle(rc)) return;
   const uint32_t nA = rc->nA;
   if (blockIdx.x == 0 && threadIdx.x == 0) round_end_body(rc, dc);
+  if (min_next) end_min(rc, dc, slots);
   for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nA;
        f += (int64_t)gridDim.x * blockDim.x) {
     const int32_t a = fv[f * 2], b = fv[f * 2 + 1];
@@ -2209,8 +2278,10 @@ void launch_gen(Engine &E, const PeelArgs &base, dim3 gf, dim3 gw, dim3 gc, dim3
 
 // Grids of one round's kernels.
 struct RoundGrids {
-  bool advance;         // queue the two level-advance kernels
-  dim3 amin, apart;     // level advance
+  bool exact;           // first round of a batch: separate advance kernels
+  bool advance;         // the round may start with a level advance
+  dim3 amin, apart;     // level advance: minimum, partition
+  dim3 aend;            // round end: the next advance's minimum
   dim3 gf, gw, ga, gc;  // per frontier entry, per frontier wave, record passes
 };
 
@@ -2228,6 +2299,7 @@ uint32_t pow2_at_least(uint64_t x) {
 RoundGrids round_grids(const Engine &E, const RoundCtl &m, bool exact, bool quantized) {
   RoundGrids g{};
   auto q = [&](dim3 d) { return quantized ? dim3(pow2_at_least(d.x)) : d; };
+  g.exact = exact;
   g.advance = !exact || m.nF == 0;
   // queued behind other rounds the advance kernels act only now and then:
   // small grids
@@ -2235,6 +2307,8 @@ RoundGrids round_grids(const Engine &E, const RoundCtl &m, bool exact, bool quan
   const uint64_t nl = m.nW != 0 ? m.nW : m.nH;
   g.amin = q(blocks_for(nl, 256 * 8, 1, cap_b));
   g.apart = q(blocks_for(nl, kPartThreads * kPartItems, 1, cap_b));
+  // the next frontier is rarely empty: the small grid of queued rounds
+  g.aend = q(blocks_for(nl, 256 * 8, 1, 256));
   // Grids: sized to the frontier when it is known (nothing in flight and no
   // level advance), otherwise wide enough to fill the chip, so that a large
   // round queued behind small ones never runs on a small grid.  Measured and
@@ -2256,20 +2330,27 @@ RoundGrids round_grids(const Engine &E, const RoundCtl &m, bool exact, bool quan
   return g;
 }
 
-// Queue one round with the given grids on E.st.
-void launch_round(Engine &E, const RoundGrids &G, hipEvent_t e0, hipEvent_t e1,
-                  hipEvent_t e_adv) {
+// Queue one round with the given grids on E.st; next_queued: another round
+// follows it in the same batch.
+void launch_round(Engine &E, const RoundGrids &G, bool next_queued, hipEvent_t e0,
+                  hipEvent_t e1, hipEvent_t e_adv) {
   const hipStream_t st = E.st;
   RoundCtl *rc = E.rc;
   // r = 3 on the s = r+1 path: frontier marks at selection
   const bool r3 = E.path == 1 && E.r == 3;
-  if (G.advance) {
-    hipLaunchKernelGGL(k_adv_min, G.amin, dim3(256), 0, st, rc, E.T.slots);
-    hipLaunchKernelGGL(k_adv_partition, G.apart, dim3(kPartThreads), 0, st, rc, E.T.slots, r3,
-                       E.gv, E.T.v1, E.fxv, E.loc);
+  if (G.exact) {
+    if (G.advance) {
+      hipLaunchKernelGGL(k_adv_min, G.amin, dim3(256), 0, st, rc, E.T.slots);
+      hipLaunchKernelGGL(k_adv_partition, G.apart, dim3(kPartThreads), 0, st, rc, E.T.slots, r3,
+                         E.gv, E.T.v1, E.fxv, E.loc);
+    }
+    if (e_adv) hipEventRecord(e_adv, st);
+    hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, st, rc, E.dc);
+  } else {
+    hipLaunchKernelGGL(k_advance_begin, G.apart, dim3(kPartThreads), 0, st, rc, E.dc,
+                       E.T.slots, r3, E.gv, E.T.v1, E.fxv, E.loc);
+    if (e_adv) hipEventRecord(e_adv, st);
   }
-  if (e_adv) hipEventRecord(e_adv, st);
-  hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, st, rc, E.dc);
   const dim3 gf = G.gf, gw = G.gw;
   const PeelArgs base{E.gv, E.T, 0u, 0u, nullptr, E.dc, E.stats, 0u, nullptr};
   if (E.path == 1) {
@@ -2308,11 +2389,14 @@ void launch_round(Engine &E, const RoundGrids &G, hipEvent_t e0, hipEvent_t e1,
   }
   // r = 2 keeps per-arc edge states: the round's end also retires its edges
   uint8_t *arcst = E.r != 2 ? nullptr : (E.path == 2 ? E.dead.get() : E.fxv.arcst);
+  const uint32_t ge = next_queued && G.aend.x > gf.x ? G.aend.x : gf.x;
   if (arcst)
-    hipLaunchKernelGGL(k_round_end_r2, gf, dim3(256), 0, st, rc, E.dc, E.gv, E.fv.get(), arcst,
+    hipLaunchKernelGGL(k_round_end_r2, dim3(ge), dim3(256), 0, st, rc,
+                       E.dc, E.T.slots, (uint32_t)next_queued, E.gv, E.fv.get(), arcst,
                        E.track_lost ? E.fxv.lost : nullptr);
   else
-    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, st, rc, E.dc);
+    hipLaunchKernelGGL(k_round_end, next_queued ? G.aend : dim3(1), dim3(256), 0, st, rc, E.dc,
+                       E.T.slots, (uint32_t)next_queued);
 }
 
 // Instantiated graphs of `rest` queued rounds (one run's cache: the graphs
@@ -2353,7 +2437,8 @@ bool launch_rounds_graph(Engine &E, GraphCache &gc, hipStream_t cap, int rest,
     if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
     E.st = cap;
     for (int d = 1; d <= rest; d++)
-      launch_round(E, G, ev ? ev[2 * d] : nullptr, ev ? ev[2 * d + 1] : nullptr, nullptr);
+      launch_round(E, G, d < rest, ev ? ev[2 * d] : nullptr, ev ? ev[2 * d + 1] : nullptr,
+                   nullptr);
     E.st = st;
     hipGraph_t g = nullptr;
     if (hipStreamEndCapture(cap, &g) != hipSuccess || !g) return false;
@@ -2546,7 +2631,7 @@ uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableVie
   GraphCache gcache;
   for (;;) {
     const auto t0 = std::chrono::steady_clock::now();
-    launch_round(E, round_grids(E, m, true, false), timing ? ev[0] : nullptr,
+    launch_round(E, round_grids(E, m, true, false), depth > 1, timing ? ev[0] : nullptr,
                  timing ? ev[1] : nullptr, first ? ev_first : nullptr);
     if (depth > 1 && ps.graph_stream) {
       if (!launch_rounds_graph(E, gcache, ps.graph_stream, depth - 1,
@@ -2558,8 +2643,8 @@ uint32_t peel_all(const OrientedGraph &g, int r, int s, int path, const TableVie
     } else {
       const RoundGrids G = round_grids(E, m, false, false);
       for (int d = 1; d < depth; d++)
-        launch_round(E, G, timing ? ev[2 * d] : nullptr, timing ? ev[2 * d + 1] : nullptr,
-                     nullptr);
+        launch_round(E, G, d + 1 < depth, timing ? ev[2 * d] : nullptr,
+                     timing ? ev[2 * d + 1] : nullptr, nullptr);
     }
     first = false;
     if (hipMemcpyAsync(mirror, E.rc, sizeof(RoundCtl), hipMemcpyDeviceToHost, st) != hipSuccess ||
